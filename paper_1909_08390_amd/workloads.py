@@ -1,0 +1,177 @@
+"""Seeded synthetic inputs for the shock problems and the parity tests.
+
+This module only draws and lays out macroscopic initial fields -- number
+density n, velocity u and temperature T = P/n per cell -- and seeds.  It holds
+no part of the lattice Boltzmann method: turning fields into distributions,
+stepping and taking moments belong to the library (GPU) and to the oracle
+(CPU), which both start from the same fields produced here.
+
+Fields are float64 numpy arrays of shape (nx,) for one axis or (ny, nx) for
+two, x fastest; cell centres are at (i + 1/2) * l / n.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+# Sod shock tube, Sec. V: (rho, u, P) left and right of the membrane.
+SOD_LEFT = (1.0, 0.0, 1.0)
+SOD_RIGHT = (0.125, 0.0, 0.1)
+
+# 2D Riemann configurations 11 and 12 as printed in Sec. V, per quadrant
+# (Q1 top right, Q2 top left, Q3 bottom left, Q4 bottom right):
+# (rho, u_x, u_y, P).
+LAX_LIU = {
+    11: ((1.0, 0.1, 0.0, 1.0), (0.5313, 0.8276, 0.0, 0.4),
+         (0.8, 0.1, 0.0, 0.4), (0.5313, 0.1, 0.7276, 0.4)),
+    12: ((0.5313, 0.0, 0.0, 0.4), (1.0, 0.7276, 0.0, 1.0),
+         (0.8, 0.0, 0.0, 1.0), (1.0, 0.0, 0.7276, 1.0)),
+}
+
+# Ranges of the seeded four-quadrant problems.
+RHO_RANGE = (0.1, 1.5)
+U_RANGE = (-1.0, 1.0)
+P_RANGE = (0.03, 1.5)
+# Accepted temperature window for seeded quadrant states (see design notes:
+# truncated equilibria far from T = 1 are strongly non-positive).
+T_WINDOW = (0.3, 2.0)
+
+
+def centres(n: int, length: float = 1.0) -> np.ndarray:
+    return (np.arange(n, dtype=np.float64) + 0.5) * (length / n)
+
+
+def sod_1d(nx: int, left=SOD_LEFT, right=SOD_RIGHT, x0: float = 0.5, lx: float = 1.0):
+    """(n, u, T) of a shock tube with the membrane at x0."""
+    x = centres(nx, lx)
+    L = x < x0
+    rho = np.where(L, left[0], right[0])
+    u = np.where(L, left[1], right[1])
+    P = np.where(L, left[2], right[2])
+    return rho.astype(np.float64), u.astype(np.float64), (P / rho).astype(np.float64)
+
+
+def quadrant_states(seed: int = 0, t_window=T_WINDOW, max_tries: int = 100000):
+    """Four i.i.d. quadrant states (rho, u_x, u_y, P) from the seeded ranges.
+
+    Draws are taken from numpy's PCG64 stream of ``seed + k`` for k = 0, 1, ...
+    and the first draw whose four temperatures P/rho all fall in ``t_window``
+    is returned together with the k used.
+    """
+    for k in range(max_tries):
+        rng = np.random.Generator(np.random.PCG64(seed + k))
+        rho = rng.uniform(*RHO_RANGE, size=4)
+        ux = rng.uniform(*U_RANGE, size=4)
+        uy = rng.uniform(*U_RANGE, size=4)
+        P = rng.uniform(*P_RANGE, size=4)
+        T = P / rho
+        if np.all((T >= t_window[0]) & (T <= t_window[1])):
+            return tuple((float(rho[i]), float(ux[i]), float(uy[i]), float(P[i]))
+                         for i in range(4)), k
+    raise RuntimeError("no acceptable quadrant states")
+
+
+def riemann_2d(nx: int, ny: int, states, x0: float = 0.5, y0: float = 0.5,
+               lx: float = 1.0, ly: float = 1.0):
+    """(n, u_x, u_y, T) of a four-quadrant problem; states ordered Q1..Q4."""
+    x = centres(nx, lx)[None, :]
+    y = centres(ny, ly)[:, None]
+    right = x >= x0
+    top = y >= y0
+    quad = np.where(top, np.where(right, 0, 1), np.where(right, 3, 2))
+    st = np.asarray(states, dtype=np.float64)  # (4, 4)
+    rho = st[quad, 0]
+    ux = st[quad, 1]
+    uy = st[quad, 2]
+    P = st[quad, 3]
+    return rho, ux, uy, P / rho
+
+
+def fourier_density(nx: int, ny: int, seed: int, modes: int = 8, amp: float = 0.2,
+                    kmax: int = 4):
+    """Periodic n = 1 + amp * sum_m a_m cos(2 pi k_m . x + phase_m), sum |a_m| = 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = rng.integers(-kmax, kmax + 1, size=(modes, 2))
+    k[np.all(k == 0, axis=1)] = (1, 0)
+    a = rng.uniform(-1.0, 1.0, size=modes)
+    a /= np.sum(np.abs(a))
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=modes)
+    x = centres(nx)[None, :]
+    y = centres(ny)[:, None]
+    n = np.ones((ny, nx))
+    for m in range(modes):
+        n = n + amp * a[m] * np.cos(2.0 * np.pi * (k[m, 0] * x + k[m, 1] * y) + ph[m])
+    return n
+
+
+def smooth_fields(shape, seed: int, du: float = 0.3, dT: float = 0.2, dn: float = 0.2,
+                  kmax: int = 3):
+    """Smooth periodic (n, u_x, u_y, T) of the given 1D or 2D shape.
+
+    Each field is a base value plus a few seeded Fourier modes, so n and T
+    stay positive (n in [1-dn, 1+dn], T in [1-dT, 1+dT], |u| <= du).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    two_d = len(shape) == 2
+    ny, nx = (shape if two_d else (1, shape[0]))
+    x = centres(nx)[None, :]
+    y = centres(ny)[:, None]
+
+    def field():
+        out = np.zeros((ny, nx))
+        a = rng.uniform(-1, 1, size=4)
+        a /= np.sum(np.abs(a))
+        for m in range(4):
+            kx = int(rng.integers(1, kmax + 1))
+            ky = int(rng.integers(0, kmax + 1)) if two_d else 0
+            ph = rng.uniform(0, 2 * np.pi)
+            out += a[m] * np.cos(2 * np.pi * (kx * x + ky * y) + ph)
+        return out
+
+    n = 1.0 + dn * field()
+    ux = du * field()
+    uy = du * field() if two_d else np.zeros((ny, nx))
+    T = 1.0 + dT * field()
+    if not two_d:
+        return n[0], ux[0], uy[0], T[0]
+    return n, ux, uy, T
+
+
+def random_fields(shape, seed: int, n_range=(0.5, 1.5), u_max: float = 0.5,
+                  T_range=(0.6, 1.4)):
+    """Cell-by-cell i.i.d. fields (rough data that exercises the limiter)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = rng.uniform(*n_range, size=shape)
+    ux = rng.uniform(-u_max, u_max, size=shape)
+    uy = rng.uniform(-u_max, u_max, size=shape)
+    T = rng.uniform(*T_range, size=shape)
+    return n, ux, uy, T
+
+
+@dataclass
+class Tube:
+    """One shock tube of the batched workload."""
+    nx: int
+    K: int
+    tau: float
+    left: tuple
+    right: tuple
+
+
+def batch_tubes(count: int = 256, seed: int = 0, nx_range=(256, 4096)):
+    """Seeded uneven shock tubes: Nx uniform, K in {0, 2}, tau log-uniform."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tubes = []
+    for _ in range(count):
+        nx = int(rng.integers(nx_range[0], nx_range[1] + 1))
+        K = int(rng.choice([0, 2]))
+        tau = float(10.0 ** rng.uniform(-6.0, -2.0))
+        st = []
+        for _side in range(2):
+            rho = float(rng.uniform(0.05, 2.0))
+            u = float(rng.uniform(-0.5, 0.5))
+            P = float(rng.uniform(0.05, 2.0))
+            st.append((rho, u, P))
+        tubes.append(Tube(nx, K, tau, st[0], st[1]))
+    return tubes

@@ -1,0 +1,297 @@
+"""Pins of the oracle's IMEX-SSP3(4,3,3) step (Sec. III of the paper) and of
+the whole method against closed forms and textbook limits.
+
+Expected values come from: the stability function of the implicit tableau
+(closed form), the Shu-Osher SSP-RK3 scheme (textbook) in the collisionless
+limit, conservation laws, the stage-moment relations the paper prints, the
+exact Riemann solution of the Euler equations (Sod tube), the BGK shear
+viscosity nu = tau T, and geometric symmetries.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1909_08390_amd import workloads as W
+
+from riemann_exact import sample as riemann_sample
+
+ALPHA, BETA, ETA = 0.24169426078821, 0.06042356519705, 0.12915286960590
+
+
+def stability_function(z):
+    """R(z) = 1 + z w^T (I - z A)^-1 1 of the implicit tableau (Table I)."""
+    A = np.array([[ALPHA, 0, 0, 0], [-ALPHA, ALPHA, 0, 0], [0, 1 - ALPHA, ALPHA, 0],
+                  [BETA, ETA, 0.5 - BETA - ETA - ALPHA, ALPHA]])
+    w = np.array([0, 1 / 6, 1 / 6, 2 / 3])
+    return 1.0 + z * w @ np.linalg.solve(np.eye(4) - z * A, np.ones(4))
+
+
+def _homogeneous_nonequilibrium(cfg, seed):
+    """A spatially uniform state F = E + delta, delta carrying no n, nu, energy."""
+    rng = np.random.default_rng(seed)
+    shape = cfg.field_shape
+    n, ux, uy, T = 1.1, 0.2, -0.1, 0.9
+    E = O.equilibrium(cfg, np.full(shape, n), np.full(shape, ux),
+                      np.full(shape, uy) if cfg.d == 2 else None, np.full(shape, T))
+    px, py = O.velocities(cfg)
+    nphi = cfg.q_phi ** cfg.d
+    # collision invariants as vectors over planes
+    inv = [np.r_[np.ones(nphi), np.zeros(cfg.planes - nphi)], np.r_[px[:nphi], np.zeros(cfg.planes - nphi)]]
+    if cfg.d == 2:
+        inv.append(np.r_[py[:nphi], np.zeros(cfg.planes - nphi)])
+    inv.append(np.r_[px[:nphi] ** 2 + py[:nphi] ** 2, np.ones(cfg.planes - nphi)])
+    B = np.array(inv).T
+    r = rng.normal(size=cfg.planes)
+    delta = r - B @ np.linalg.lstsq(B, r, rcond=None)[0]  # orthogonal to invariants
+    delta *= 0.01
+    F = E + delta.reshape((-1,) + (1,) * len(shape))
+    return F, E
+
+
+@pytest.mark.parametrize("omega", [0.1, 1.0, 10.0, 1e3])
+@pytest.mark.parametrize("d", [1, 2])
+def test_homogeneous_relaxation_follows_stability_function(omega, d):
+    """No gradients, no advection: each step multiplies F - E by R(-dt/tau)."""
+    cfg = O.Config(d=d, nx=6, ny=5 if d == 2 else 1, q_phi=4, q_chi=3, K=2,
+                   tau=1e-3, dt=omega * 1e-3, bc_x=O.PERIODIC, bc_y=O.PERIODIC)
+    F0, E = _homogeneous_nonequilibrium(cfg, 7)
+    F1 = O.step(cfg, F0, 1)
+    R = stability_function(-omega)
+    # dF = omega (F - E) carries the round-off of F - E multiplied by omega
+    atol = 1e-14 * max(1.0, omega) * np.abs(F0).max()
+    np.testing.assert_allclose(F1 - E, R * (F0 - E), rtol=1e-9, atol=atol)
+
+
+def test_stiff_limit_projects_onto_equilibrium():
+    """L-stability: for dt/tau = 1e8 one step leaves |F - E| < 1e-6 |F0 - E|
+    (the printed stage-3 closed form, read literally, would leave ~0.6)."""
+    cfg = O.Config(d=1, nx=4, q_phi=5, q_chi=3, tau=1e-8, dt=1.0, bc_x=O.PERIODIC)
+    F0, E = _homogeneous_nonequilibrium(cfg, 8)
+    F1 = O.step(cfg, F0, 1)
+    assert np.abs(F1 - E).max() < 1e-6 * np.abs(F0 - E).max()
+
+
+def test_stability_function_values():
+    assert stability_function(-1.0) == pytest.approx(0.367328, abs=2e-6)
+    assert abs(stability_function(-1e8)) < 1e-6
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_collisionless_limit_is_ssp_rk3(d):
+    """tau -> infinity: the explicit tableau is Shu-Osher's SSP-RK3,
+    u1 = F - dt VF, u2 = 3/4 F + 1/4 (u1 - dt V u1), F' = 1/3 F + 2/3 (u2 - dt V u2)."""
+    cfg = O.Config(d=d, nx=24, ny=18 if d == 2 else 1, q_phi=5, q_chi=3, K=2,
+                   tau=1e300, dt=1e-3, bc_x=O.PERIODIC, bc_y=O.OUTFLOW)
+    n, ux, uy, T = W.smooth_fields(cfg.field_shape, seed=5)
+    F = O.equilibrium(cfg, n, ux, uy if d == 2 else None, T)
+    dt = cfg.dt
+    u1 = F - dt * O.advect(cfg, F)
+    u2 = 0.75 * F + 0.25 * (u1 - dt * O.advect(cfg, u1))
+    ref = F / 3.0 + 2.0 / 3.0 * (u2 - dt * O.advect(cfg, u2))
+    got = O.step(cfg, F, 1)
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_uniform_equilibrium_is_a_fixed_point(d):
+    cfg = O.Config(d=d, nx=16, ny=12 if d == 2 else 1, q_phi=5, q_chi=3, tau=1e-5, dt=1e-3)
+    shape = cfg.field_shape
+    F = O.equilibrium(cfg, np.full(shape, 0.8), np.full(shape, 0.3),
+                      np.full(shape, -0.2) if d == 2 else None, np.full(shape, 1.2))
+    F1 = O.step(cfg, F, 5)
+    np.testing.assert_allclose(F1, F, rtol=0, atol=1e-13 * np.abs(F).max())
+
+
+def _conserved(cfg, F):
+    px, py = O.velocities(cfg)
+    nphi = cfg.q_phi ** cfg.d
+    ax = tuple(range(1, F.ndim))
+    mass = F[:nphi].sum(axis=ax).sum()
+    mx = (px[:nphi] * F[:nphi].sum(axis=ax)).sum()
+    my = (py[:nphi] * F[:nphi].sum(axis=ax)).sum()
+    en = 0.5 * ((px[:nphi] ** 2 + py[:nphi] ** 2) * F[:nphi].sum(axis=ax)).sum() \
+        + 0.5 * F[nphi:].sum()
+    return np.array([mass, mx, my, en])
+
+
+@pytest.mark.parametrize("d,qp,qc", [(1, 5, 3), (2, 4, 3)])
+def test_periodic_conservation(d, qp, qc):
+    """Fluxes telescope and dF carries no invariants: mass, momentum and total
+    energy are constant to round-off on a periodic grid."""
+    cfg = O.Config(d=d, nx=32, ny=20 if d == 2 else 1, q_phi=qp, q_chi=qc, K=2,
+                   tau=2e-4, dt=2e-3, bc_x=O.PERIODIC, bc_y=O.PERIODIC)
+    n, ux, uy, T = W.smooth_fields(cfg.field_shape, seed=11, du=0.3)
+    F = O.equilibrium(cfg, n, ux, uy if d == 2 else None, T)
+    c0 = _conserved(cfg, F)
+    F = O.step(cfg, F, 40)
+    c1 = _conserved(cfg, F)
+    assert np.isfinite(F).all()
+    np.testing.assert_allclose(c1, c0, rtol=0, atol=1e-12 * np.abs(c0).max())
+
+
+def test_stage_moment_relations():
+    """Sec. III: n, u, T of stages 1 and 2 are those of F^n; stage 3 has the
+    moments of the Euler-advanced F~(2) = F^(2) - dt V F^(2) - dF^(2); stage 4
+    mixes F^n and F~(3) as rho4 = 3/4 rho^n + 1/4 rho~3, the matching momentum
+    relation, and the energy relation with the 3 rho^n rho~3 (u^n - u~3)^2 /
+    (32 rho4) term."""
+    cfg = O.Config(d=2, nx=20, ny=14, q_phi=5, q_chi=3, K=2, tau=3e-4, dt=1e-3,
+                   bc_x=O.PERIODIC, bc_y=O.OUTFLOW)
+    n, ux, uy, T = W.smooth_fields(cfg.field_shape, seed=21, du=0.3)
+    F = O.equilibrium(cfg, n, ux, uy, T)
+    # put the start state out of equilibrium so that dF terms are non-zero
+    F = O.step(cfg, F, 2)
+    Fn = F.copy()
+    _, stages = O.step(cfg, F, 1, with_stages=True)
+    DK = 3 + cfg.K
+    mn = O.moments(cfg, Fn)
+    m = [O.moments(cfg, stages[i]) for i in range(4)]
+    for i in (0, 1):
+        for a, b in zip(m[i], mn):
+            np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-13)
+    # Euler-advanced stage values (their dF part carries no moments)
+    t2 = O.moments(cfg, stages[1] - cfg.dt * O.advect(cfg, stages[1]))
+    for a, b in zip(m[2], t2):
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-13)
+    r3, u3x, u3y, T3 = O.moments(cfg, stages[2] - cfg.dt * O.advect(cfg, stages[2]))
+    rn, unx, uny, Tn = mn
+    r4 = 0.75 * rn + 0.25 * r3
+    np.testing.assert_allclose(m[3][0], r4, rtol=1e-12)
+    np.testing.assert_allclose(m[3][1], (0.75 * rn * unx + 0.25 * r3 * u3x) / r4, atol=1e-12)
+    np.testing.assert_allclose(m[3][2], (0.75 * rn * uny + 0.25 * r3 * u3y) / r4, atol=1e-12)
+    du2 = (unx - u3x) ** 2 + (uny - u3y) ** 2
+    T4 = (3 * rn * r3 / (32 * r4) * du2 + DK / 2 * (0.75 * rn * Tn + 0.25 * r3 * T3)) / (DK / 2 * r4)
+    np.testing.assert_allclose(m[3][3], T4, rtol=1e-12)
+
+
+def _sod_l1(S, dt, t_end, K, tau=1e-5):
+    cfg = O.Config(d=1, nx=S, q_phi=5, q_chi=3, K=K, tau=tau, dt=dt)
+    n, u, T = W.sod_1d(S)
+    F = O.equilibrium(cfg, n, u, None, T)
+    F = O.step(cfg, F, int(round(t_end / dt)))
+    rho, uu, _, TT = O.moments(cfg, F)
+    return cfg, rho, uu, rho * TT
+
+
+@pytest.mark.parametrize("K,gamma", [(2, 1.4), (0, 5.0 / 3.0)])
+def test_sod_tube_matches_exact_riemann_solution(K, gamma):
+    """Near-inviscid limit (tau = 1e-5, S = 400, Q_phi = 5, Q_chi = 3) against
+    the exact Euler solution at t = 0.1 with gamma = (D + K + 2)/(D + K)."""
+    S, dt, t = 400, 2.5e-4, 0.1
+    cfg, rho, u, P = _sod_l1(S, dt, t, K)
+    x = W.centres(S)
+    xi = (x - 0.5) / t
+    er, eu, ep = riemann_sample(W.SOD_LEFT, W.SOD_RIGHT, gamma, xi)
+    l1 = np.mean(np.abs(rho - er))
+    assert l1 < 4e-3, l1
+    assert np.mean(np.abs(u - eu)) < 8e-3
+    assert np.mean(np.abs(P - ep)) < 4e-3
+    # the wrong adiabatic index is clearly rejected
+    other = 5.0 / 3.0 if K == 2 else 1.4
+    wr, _, _ = riemann_sample(W.SOD_LEFT, W.SOD_RIGHT, other, xi)
+    assert np.mean(np.abs(rho - wr)) > 3 * l1
+
+
+@pytest.mark.slow
+def test_sod_error_falls_with_resolution():
+    """Fig. 1a trend: the density error shrinks as S grows at fixed dt."""
+    errs = []
+    for S in (100, 200, 400):
+        cfg, rho, _, _ = _sod_l1(S, 2.5e-4, 0.1, 2)
+        xi = (W.centres(S) - 0.5) / 0.1
+        er, _, _ = riemann_sample(W.SOD_LEFT, W.SOD_RIGHT, 1.4, xi)
+        errs.append(np.mean(np.abs(rho - er)))
+    assert errs[0] > errs[1] > errs[2], errs
+
+
+def test_shear_wave_decays_at_bgk_viscosity():
+    """u_y = A sin(2 pi x): the amplitude decays as exp(-nu k^2 t) with the BGK
+    kinematic viscosity nu = tau T (to O((k tau)^2)).  The rate is measured
+    between t = 0.1 and t = 0.5, after the O(tau) start-up transient in which
+    the shear stress builds up from the equilibrium initial state."""
+    nx = 32
+    tau, dt = 1e-2, 1e-3
+    cfg = O.Config(d=2, nx=nx, ny=1, q_phi=6, q_chi=3, K=2, tau=tau, dt=dt,
+                   bc_x=O.PERIODIC, bc_y=O.PERIODIC)
+    x = W.centres(nx)
+    A = 1e-3
+    shape = cfg.field_shape
+    F = O.equilibrium(cfg, np.ones(shape), np.zeros(shape),
+                      (A * np.sin(2 * np.pi * x))[None, :], np.ones(shape))
+
+    def amplitude(G):
+        _, _, uy, _ = O.moments(cfg, G)
+        return 2.0 * np.mean(uy[0] * np.sin(2 * np.pi * x))
+
+    F = O.step(cfg, F, 100)
+    a1 = amplitude(F)
+    F = O.step(cfg, F, 400)
+    a2 = amplitude(F)
+    rate = np.log(a1 / a2) / (400 * dt)
+    nu = tau * 1.0
+    assert rate == pytest.approx(nu * (2 * np.pi) ** 2, rel=1e-2)
+
+
+def test_y_uniform_data_stays_y_uniform():
+    cfg = O.Config(d=2, nx=24, ny=11, q_phi=4, q_chi=2, K=2, tau=1e-4, dt=1e-3,
+                   bc_x=O.OUTFLOW, bc_y=O.PERIODIC)
+    n, ux, T = W.sod_1d(24)
+    shape = cfg.field_shape
+    F = O.equilibrium(cfg, np.broadcast_to(n, shape), np.broadcast_to(ux, shape),
+                      np.full(shape, 0.0), np.broadcast_to(T, shape))
+    F = O.step(cfg, F, 3)
+    assert np.all(F == F[:, :1, :])
+
+
+def test_transpose_symmetry():
+    """Swapping x and y (data and velocity order) gives the transposed result."""
+    nx, ny = 22, 17
+    cfg = O.Config(d=2, nx=nx, ny=ny, q_phi=4, q_chi=3, K=2, tau=1e-4, dt=2e-3,
+                   bc_x=O.OUTFLOW, bc_y=O.PERIODIC)
+    cfgT = O.Config(d=2, nx=ny, ny=nx, q_phi=4, q_chi=3, K=2, tau=1e-4, dt=2e-3,
+                    bc_x=O.PERIODIC, bc_y=O.OUTFLOW)
+    n, ux, uy, T = W.random_fields((ny, nx), seed=6)
+    F = O.equilibrium(cfg, n, ux, uy, T)
+    FT = O.equilibrium(cfgT, n.T, uy.T, ux.T, T.T)
+
+    def swap_planes(G, q_phi, q_chi):
+        a = G[:q_phi ** 2].reshape(q_phi, q_phi, *G.shape[1:]).transpose(1, 0, 3, 2)
+        b = G[q_phi ** 2:].reshape(q_chi, q_chi, *G.shape[1:]).transpose(1, 0, 3, 2)
+        return np.concatenate([a.reshape(q_phi ** 2, *a.shape[2:]),
+                               b.reshape(q_chi ** 2, *b.shape[2:])])
+
+    np.testing.assert_allclose(swap_planes(F, 4, 3), FT, rtol=1e-14, atol=1e-15)
+    F1 = O.step(cfg, F, 2)
+    FT1 = O.step(cfgT, FT, 2)
+    np.testing.assert_allclose(swap_planes(F1, 4, 3), FT1, rtol=1e-12, atol=1e-13)
+
+
+def test_mirror_symmetry_full_step():
+    """x -> 1 - x with velocities reversed gives the mirrored result."""
+    cfg = O.Config(d=1, nx=40, q_phi=6, q_chi=4, K=2, tau=1e-4, dt=1e-3)
+    n, u, T = W.sod_1d(40, left=(1.0, 0.3, 1.0), right=(0.2, -0.1, 0.3), x0=0.37)
+    F = O.equilibrium(cfg, n, u, None, T)
+    Fm = O.equilibrium(cfg, n[::-1], -u[::-1], None, T[::-1])
+    perm = np.concatenate([np.arange(6)[::-1], 6 + np.arange(4)[::-1]])
+    np.testing.assert_allclose(F[perm][:, ::-1], Fm, rtol=1e-13, atol=1e-15)
+    F1 = O.step(cfg, F, 10)
+    Fm1 = O.step(cfg, Fm, 10)
+    np.testing.assert_allclose(F1[perm][:, ::-1], Fm1, rtol=1e-11, atol=1e-13)
+
+
+def test_patch_step_reproduces_interior_of_full_step():
+    """Domain of dependence: one step reaches 3 x 5 = 15 cells.  A patch with a
+    15-cell margin around a cell, stepped on its own, gives the same value
+    there -- the basis of the sampled checks at full problem size."""
+    nx, ny = 48, 44
+    cfg = O.Config(d=2, nx=nx, ny=ny, q_phi=4, q_chi=2, K=2, tau=1e-5, dt=2e-3)
+    n, ux, uy, T = W.random_fields((ny, nx), seed=9)
+    F = O.equilibrium(cfg, n, ux, uy, T)
+    full = O.step(cfg, F, 1)
+    cx, cy, r = 24, 20, 15
+    sub = F[:, cy - r:cy + r + 1, cx - r:cx + r + 1]
+    pcfg = O.Config(d=2, nx=2 * r + 1, ny=2 * r + 1, lx=(2 * r + 1) / nx, ly=(2 * r + 1) / ny,
+                    q_phi=4, q_chi=2, K=2, tau=1e-5, dt=2e-3)
+    ps = O.step(pcfg, sub, 1)
+    # equal up to the rounding of the patch's own grid spacing lx/nx
+    np.testing.assert_allclose(ps[:, r, r], full[:, cy, cx], rtol=1e-13, atol=1e-15)
