@@ -1,0 +1,151 @@
+/*
+ * imexlb.h -- C ABI of the MI355X (gfx950) IMEX finite-difference lattice
+ * Boltzmann library (method of Kis & Ambrus, arXiv:1909.08390).
+ *
+ * The library advances the two reduced distributions phi and chi of the
+ * BGK-Boltzmann equation (Sec. II) on a 1D or 2D grid with the
+ * IMEX-SSP3(4,3,3) Runge-Kutta scheme of Sec. III (Table I): advection is
+ * explicit, by 9th-order monotonicity-preserving (MP-9) fluxes (Sec. IV);
+ * the BGK collision is implicit and solved in closed form from the stage
+ * moments.
+ *
+ * Memory model.  All large buffers are device memory owned by the caller
+ * (e.g. torch tensors): the state and a workspace, sized by
+ * imexlb_state_bytes() / imexlb_workspace_bytes() and handed over with
+ * imexlb_bind().  The context owns only small constant tables.  Every call
+ * is issued on the context's HIP stream; calls taking device pointers are
+ * asynchronous, calls taking host pointers synchronise that stream.
+ *
+ * State layout (the "plane-set").  F[v][y][x], x fastest, dense, element
+ * type double (IMEXLB_F64) or float (IMEXLB_F32).  Plane v runs over the
+ * discrete velocities: phi planes first, v = kx + Qphi*ky (ky = 0 when
+ * d = 1), then chi planes, v = Qphi^d + qx + Qchi*qy; node indices follow the
+ * ascending Gauss-Hermite nodes.  Cell centres sit at (i + 1/2) l/n.
+ * Macroscopic fields (n, ux, uy, T) are FP64 arrays [y][x] of nx*ny values.
+ *
+ * Errors.  Every call returns a status; nothing is thrown across the ABI.
+ * imexlb_last_error() gives a text for the last failing call of a context.
+ */
+#ifndef IMEXLB_H
+#define IMEXLB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IMEXLB_OK = 0,
+    IMEXLB_EINVAL = -1,   /* invalid argument or configuration            */
+    IMEXLB_ENOMEM = -2,   /* host or small device allocation failed        */
+    IMEXLB_EHIP = -3,     /* HIP runtime error (launch, copy, device)      */
+    IMEXLB_ENONPHYS = -4, /* state check found n <= 0, T <= 0 or non-finite */
+    IMEXLB_ESTATE = -5    /* call out of order (not bound / no state set)  */
+} imexlb_status;
+
+typedef enum { IMEXLB_OUTFLOW = 0, IMEXLB_PERIODIC = 1 } imexlb_bc;
+typedef enum { IMEXLB_F64 = 0, IMEXLB_F32 = 1 } imexlb_storage;
+
+/* Problem definition.  Sec. II fixes D = 3 momentum dimensions, of which the
+ * first d are non-homogeneous; K internal degrees of freedom give the
+ * adiabatic index gamma = (D + K + 2)/(D + K).  Units: m = k_B = 1, lengths
+ * in units of the domain size (Sec. II, non-dimensionalisation). */
+typedef struct {
+    int d;              /* 1 or 2                                              */
+    int nx, ny;         /* cells per axis; ny must be 1 when d = 1             */
+    double lx, ly;      /* domain lengths (> 0); ly ignored when d = 1         */
+    int q_phi, q_chi;   /* Gauss-Hermite order per axis: 3 <= q_phi <= 16,
+                           1 <= q_chi <= 16 (energy is exact only from q_phi = 3,
+                           Sec. II exactness up to order Q - 1)                */
+    int K;              /* internal degrees of freedom, >= 0                   */
+    double tau;         /* BGK relaxation time, > 0                            */
+    double dt;          /* time step, > 0, with max|p| dt / (l/n) <= 1 per axis
+                           (the CFL condition of Sec. IV)                      */
+    int bc_x, bc_y;     /* imexlb_bc per axis: outflow (ghost nodes copy the
+                           boundary node, Sec. IV) or periodic                 */
+    int storage;        /* imexlb_storage of the plane-sets                    */
+} imexlb_config;
+
+typedef struct imexlb_ctx imexlb_ctx;
+
+/* Validate cfg, build the Gauss-Hermite quadrature and the equilibrium
+ * tables (Sec. II) and upload them.  hip_stream is a hipStream_t (NULL for
+ * the default stream).  On success *out owns the context. */
+imexlb_status imexlb_create(const imexlb_config* cfg, void* hip_stream, imexlb_ctx** out);
+void imexlb_destroy(imexlb_ctx* ctx);
+
+/* Change the stream later calls are issued on. */
+imexlb_status imexlb_set_stream(imexlb_ctx* ctx, void* hip_stream);
+
+/* Bytes of one plane-set (planes * cells * element size). */
+size_t imexlb_state_bytes(const imexlb_ctx* ctx);
+/* Bytes of the workspace: two stage plane-sets and three FP64 moment sets. */
+size_t imexlb_workspace_bytes(const imexlb_ctx* ctx);
+/* Number of planes Qphi^d + Qchi^d. */
+int imexlb_num_planes(const imexlb_ctx* ctx);
+
+/* Hand over caller-owned device memory: d_state (imexlb_state_bytes) and
+ * d_workspace (imexlb_workspace_bytes), both 256-byte aligned.  The library
+ * never frees them.  Rebinding invalidates the stored state. */
+imexlb_status imexlb_bind(imexlb_ctx* ctx, void* d_state, void* d_workspace);
+
+/* Host copies of the per-axis nodes and weights (q_phi resp. q_chi values):
+ * nodes are the roots of He_Q, weights Q!/He_{Q+1}(p)^2 (Sec. II). */
+imexlb_status imexlb_quadrature(const imexlb_ctx* ctx, double* p_phi, double* w_phi,
+                                double* p_chi, double* w_chi);
+
+/* Set the state to the discrete equilibrium of the device fields
+ * (n, ux, uy, T) (Sec. II, Eq. gExpanded and chi_eq = (K + D - d) T phi_eq).
+ * d_uy is ignored when d = 1. */
+imexlb_status imexlb_set_equilibrium(imexlb_ctx* ctx, const double* d_n, const double* d_ux,
+                                     const double* d_uy, const double* d_T);
+
+/* Copy a raw plane-set (device, state layout) into the bound state and
+ * recompute its moments. */
+imexlb_status imexlb_set_state(imexlb_ctx* ctx, const void* d_F);
+/* Copy the bound state into d_F (device, state layout). */
+imexlb_status imexlb_get_state(const imexlb_ctx* ctx, void* d_F);
+
+/* Advance the bound state by nsteps IMEX-SSP3(4,3,3) steps (Sec. III):
+ * three fused stage passes per step, asynchronous on the stream. */
+imexlb_status imexlb_step(imexlb_ctx* ctx, int nsteps);
+
+/* imexlb_step with per-pass timing: adds to ms[0], ms[1], ms[2] the summed
+ * durations (milliseconds, HIP events recorded on the context's stream
+ * between the launches) of the stage-3, stage-4 and stage-5 passes of all
+ * nsteps steps.  Same results as imexlb_step; synchronises the stream at the
+ * end.  For measurement. */
+imexlb_status imexlb_step_timed(imexlb_ctx* ctx, int nsteps, double ms[3]);
+
+/* Device fields (n, ux, uy, T) of the current state (Sec. II, discrete
+ * moments); d_uy is neither read nor written when d = 1 (may be NULL). */
+imexlb_status imexlb_moments(const imexlb_ctx* ctx, double* d_n, double* d_ux,
+                             double* d_uy, double* d_T);
+
+/* Device FP64 fields of an arbitrary plane-set d_F (state layout, storage
+ * type of the context): the moments reduction on its own. */
+imexlb_status imexlb_compute_moments(const imexlb_ctx* ctx, const void* d_F, double* d_n,
+                                     double* d_ux, double* d_uy, double* d_T);
+
+/* Device FP64 plane-set d_VF = (p . grad) F of the plane-set d_F by MP-9
+ * fluxes with ghost nodes (Sec. IV), the advection operator on its own. */
+imexlb_status imexlb_advect(const imexlb_ctx* ctx, const void* d_F, double* d_VF);
+
+/* Host sums over all cells of the current state: out[0] = mass, out[1..2] =
+ * momentum (x, y), out[3] = total energy (D+K)/2 n T + n |u|^2 / 2.
+ * Synchronises the stream. */
+imexlb_status imexlb_domain_sums(const imexlb_ctx* ctx, double out[4]);
+
+/* Scan the current moments for n <= 0, T <= 0 or non-finite values:
+ * IMEXLB_OK or IMEXLB_ENONPHYS.  Synchronises the stream. */
+imexlb_status imexlb_check_state(const imexlb_ctx* ctx);
+
+/* Static text for a status; the context's last error message. */
+const char* imexlb_status_string(imexlb_status s);
+const char* imexlb_last_error(const imexlb_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,571 @@
+// Host side of the imexlb C ABI: configuration checks, Gauss-Hermite
+// quadrature and equilibrium tables (Sec. II), buffer binding and the launch
+// sequence of the IMEX-SSP3(4,3,3) step (Sec. III).
+#include "imexlb.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.hpp"
+
+using namespace imexlb;
+
+struct imexlb_ctx {
+    imexlb_config cfg;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int nplanes = 0, nphi = 0, nf = 0;  // planes, phi planes, moment fields
+    long long cells = 0;
+    size_t elem = 8;
+    double p[2][kQMax] = {}, w[2][kQMax] = {};
+    DevTables* d_tab = nullptr;
+    double* d_small = nullptr;   // reduction partials + 4 sums
+    int* d_flag = nullptr;
+    int nred = 0;
+    void* d_state = nullptr;
+    void* d_work = nullptr;
+    bool have_state = false;
+    std::string err;
+};
+
+namespace {
+
+constexpr double kAlpha = 0.24169426078821;  // Table I
+constexpr int kRedBlocks = 1024;
+
+imexlb_status fail(imexlb_ctx* c, imexlb_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+imexlb_status hip_fail(imexlb_ctx* c, hipError_t e, const char* what) {
+    return fail(c, IMEXLB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// He_n(x) by He_{n+1} = x He_n - n He_{n-1}.
+long double he(int n, long double x) {
+    long double a = 1.0L, b = x;
+    if (n == 0) return a;
+    for (int j = 1; j < n; ++j) {
+        long double c = x * b - (long double)j * a;
+        a = b;
+        b = c;
+    }
+    return b;
+}
+
+// Gauss-Hermite rule for the weight exp(-p^2/2)/sqrt(2 pi) (Sec. II):
+// eigenvalues of the symmetric Jacobi matrix of the monic recurrence
+// (off-diagonal sqrt(k)) by cyclic Jacobi rotations, polished by Newton on
+// He_Q; weights Q!/(Q He_{Q-1}(p))^2, which equals the paper's
+// Q!/He_{Q+1}(p)^2 at a root of He_Q.
+bool gauss_hermite(int Q, double* p, double* w) {
+    if (Q < 1 || Q > kQMax) return false;
+    long double A[kQMax][kQMax] = {};
+    for (int k = 0; k + 1 < Q; ++k) A[k][k + 1] = A[k + 1][k] = sqrtl((long double)(k + 1));
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        long double off = 0.0L;
+        for (int i = 0; i < Q; ++i)
+            for (int j = i + 1; j < Q; ++j) off += A[i][j] * A[i][j];
+        if (off < 1e-36L) break;
+        for (int i = 0; i < Q; ++i)
+            for (int j = i + 1; j < Q; ++j) {
+                if (A[i][j] == 0.0L) continue;
+                long double th = (A[j][j] - A[i][i]) / (2.0L * A[i][j]);
+                long double t = (th >= 0 ? 1.0L : -1.0L) / (fabsl(th) + sqrtl(th * th + 1.0L));
+                long double c = 1.0L / sqrtl(t * t + 1.0L), s = t * c;
+                for (int k = 0; k < Q; ++k) {  // A <- A R
+                    long double aki = A[k][i], akj = A[k][j];
+                    A[k][i] = c * aki - s * akj;
+                    A[k][j] = s * aki + c * akj;
+                }
+                for (int k = 0; k < Q; ++k) {  // A <- R^T A
+                    long double aik = A[i][k], ajk = A[j][k];
+                    A[i][k] = c * aik - s * ajk;
+                    A[j][k] = s * aik + c * ajk;
+                }
+            }
+    }
+    long double x[kQMax];
+    for (int i = 0; i < Q; ++i) x[i] = A[i][i];
+    for (int i = 1; i < Q; ++i)  // ascending
+        for (int j = i; j > 0 && x[j] < x[j - 1]; --j) {
+            long double t = x[j];
+            x[j] = x[j - 1];
+            x[j - 1] = t;
+        }
+    long double qf = 1.0L;
+    for (int j = 2; j <= Q; ++j) qf *= (long double)j;
+    for (int i = 0; i < Q; ++i) {
+        for (int it = 0; it < 8; ++it) {  // He_Q' = Q He_{Q-1}
+            long double f = he(Q, x[i]), df = (long double)Q * he(Q - 1, x[i]);
+            if (df == 0.0L) break;
+            x[i] -= f / df;
+        }
+    }
+    for (int i = 0; i < Q / 2; ++i) {  // He_Q(-x) = (-1)^Q He_Q(x)
+        long double m = 0.5L * (x[Q - 1 - i] - x[i]);
+        x[i] = -m;
+        x[Q - 1 - i] = m;
+    }
+    if (Q % 2) x[Q / 2] = 0.0L;
+    for (int i = 0; i < Q; ++i) {
+        long double d = (long double)Q * he(Q - 1, x[i]);
+        p[i] = (double)x[i];
+        w[i] = (double)(Q == 1 ? 1.0L : qf / (d * d));
+    }
+    return true;
+}
+
+imexlb_status validate(const imexlb_config* c, std::string& why) {
+    if (!c) { why = "config is NULL"; return IMEXLB_EINVAL; }
+    if (c->d != 1 && c->d != 2) { why = "d must be 1 or 2"; return IMEXLB_EINVAL; }
+    if (c->nx < 1 || c->ny < 1) { why = "nx, ny must be >= 1"; return IMEXLB_EINVAL; }
+    if (c->d == 1 && c->ny != 1) { why = "ny must be 1 when d = 1"; return IMEXLB_EINVAL; }
+    if ((long long)c->nx * c->ny >= (1LL << 31)) { why = "too many cells (>= 2^31)"; return IMEXLB_EINVAL; }
+    if (!(c->lx > 0.0) || (c->d == 2 && !(c->ly > 0.0))) { why = "lengths must be > 0"; return IMEXLB_EINVAL; }
+    if (c->q_phi < 3 || c->q_phi > kQMax) { why = "q_phi must be in [3, 16]"; return IMEXLB_EINVAL; }
+    if (c->q_chi < 1 || c->q_chi > kQMax) { why = "q_chi must be in [1, 16]"; return IMEXLB_EINVAL; }
+    if (c->K < 0) { why = "K must be >= 0"; return IMEXLB_EINVAL; }
+    if (!(c->tau > 0.0) || !std::isfinite(c->tau)) { why = "tau must be > 0"; return IMEXLB_EINVAL; }
+    if (!(c->dt > 0.0) || !std::isfinite(c->dt)) { why = "dt must be > 0"; return IMEXLB_EINVAL; }
+    if (c->bc_x != IMEXLB_OUTFLOW && c->bc_x != IMEXLB_PERIODIC) { why = "bad bc_x"; return IMEXLB_EINVAL; }
+    if (c->d == 2 && c->bc_y != IMEXLB_OUTFLOW && c->bc_y != IMEXLB_PERIODIC) { why = "bad bc_y"; return IMEXLB_EINVAL; }
+    if (c->storage != IMEXLB_F64 && c->storage != IMEXLB_F32) { why = "bad storage"; return IMEXLB_EINVAL; }
+    return IMEXLB_OK;
+}
+
+imexlb_status need_state(const imexlb_ctx* c) {
+    if (!c->d_state || !c->d_work) return IMEXLB_ESTATE;
+    if (!c->have_state) return IMEXLB_ESTATE;
+    return IMEXLB_OK;
+}
+
+// Workspace: G3 | G4 | M^n | M3 | M4.
+void* work_g(const imexlb_ctx* c, int i) {
+    return (char*)c->d_work + (size_t)i * align256((size_t)c->nplanes * c->cells * c->elem);
+}
+double* work_m(const imexlb_ctx* c, int i) {
+    size_t off = 2 * align256((size_t)c->nplanes * c->cells * c->elem) +
+                 (size_t)i * align256((size_t)c->nf * c->cells * sizeof(double));
+    return (double*)((char*)c->d_work + off);
+}
+
+StageArgs base_args(const imexlb_ctx* c) {
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const imexlb_config& k = c->cfg;
+    a.tab = c->d_tab;
+    a.nx = k.nx;
+    a.ny = k.d == 2 ? k.ny : 1;
+    a.bcx = k.bc_x;
+    a.bcy = k.d == 2 ? k.bc_y : 0;
+    if (k.d == 2) {
+        a.ntx = (k.nx + kTile2X - 1) / kTile2X;
+        a.nty = (k.ny + kTile2Y - 1) / kTile2Y;
+    } else {
+        a.ntx = (k.nx + kTile1X - 1) / kTile1X;
+        a.nty = 1;
+    }
+    a.tiles_per_xcd = (a.ntx * a.nty + 7) / 8;
+    a.plane_stride = c->cells;
+    a.inv_dx = k.nx / k.lx;
+    a.inv_dy = k.d == 2 ? k.ny / k.ly : 0.0;
+    a.dt = k.dt;
+    a.omega = k.dt / k.tau;
+    const double cc = kAlpha * a.omega;
+    a.a1 = 1.0 / (1.0 + cc);
+    a.a2 = (1.0 + 2.0 * cc) / ((1.0 + cc) * (1.0 + cc));
+    a.chi_fac = (double)(k.K + kDTotal - k.d);
+    a.dk = (double)(kDTotal + k.K);
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* imexlb_status_string(imexlb_status s) {
+    switch (s) {
+        case IMEXLB_OK: return "ok";
+        case IMEXLB_EINVAL: return "invalid argument";
+        case IMEXLB_ENOMEM: return "out of memory";
+        case IMEXLB_EHIP: return "HIP runtime error";
+        case IMEXLB_ENONPHYS: return "non-physical state (n <= 0, T <= 0 or non-finite)";
+        case IMEXLB_ESTATE: return "call out of order (no bound buffers or no state)";
+    }
+    return "unknown status";
+}
+
+const char* imexlb_last_error(const imexlb_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+imexlb_status imexlb_create(const imexlb_config* cfg, void* hip_stream, imexlb_ctx** out) {
+    if (!out) return IMEXLB_EINVAL;
+    *out = nullptr;
+    std::string why;
+    imexlb_status st = validate(cfg, why);
+    if (st != IMEXLB_OK) {
+        std::fprintf(stderr, "imexlb_create: %s\n", why.c_str());
+        return st;
+    }
+    imexlb_ctx* c = new (std::nothrow) imexlb_ctx();
+    if (!c) return IMEXLB_ENOMEM;
+    c->cfg = *cfg;
+    if (cfg->d == 1) c->cfg.ny = 1;
+    c->stream = (hipStream_t)hip_stream;
+    const int d = cfg->d;
+    const int Q[2] = {cfg->q_phi, cfg->q_chi};
+    for (int s = 0; s < 2; ++s)
+        if (!gauss_hermite(Q[s], c->p[s], c->w[s])) {
+            delete c;
+            return IMEXLB_EINVAL;
+        }
+    // CFL = |p| dt / delta s <= 1 for every advection velocity (Sec. IV).
+    double pmax = 0.0;
+    for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < Q[s]; ++k) pmax = std::fmax(pmax, std::fabs(c->p[s][k]));
+    const double cflx = pmax * cfg->dt * cfg->nx / cfg->lx;
+    const double cfly = d == 2 ? pmax * cfg->dt * cfg->ny / cfg->ly : 0.0;
+    if (cflx > 1.0 || cfly > 1.0) {
+        std::fprintf(stderr, "imexlb_create: CFL %.3f > 1\n", std::fmax(cflx, cfly));
+        delete c;
+        return IMEXLB_EINVAL;
+    }
+    c->nphi = d == 2 ? Q[0] * Q[0] : Q[0];
+    c->nplanes = c->nphi + (d == 2 ? Q[1] * Q[1] : Q[1]);
+    c->nf = d + 2;
+    c->cells = (long long)cfg->nx * c->cfg.ny;
+    c->elem = cfg->storage == IMEXLB_F32 ? 4 : 8;
+
+    DevTables* t = new (std::nothrow) DevTables();
+    if (!t) {
+        delete c;
+        return IMEXLB_ENOMEM;
+    }
+    std::memset(t, 0, sizeof(*t));
+    for (int s = 0; s < 2; ++s) {
+        t->q[s] = Q[s];
+        for (int k = 0; k < Q[s]; ++k) {
+            long double fact = 1.0L;
+            for (int l = 0; l < Q[s]; ++l) {
+                if (l > 0) fact *= (long double)l;
+                t->h[s][k][l] = (double)((long double)c->w[s][k] * he(l, (long double)c->p[s][k]) / fact);
+            }
+        }
+    }
+    t->nplanes = c->nplanes;
+    t->nphi = c->nphi;
+    int v = 0;
+    for (int s = 0; s < 2; ++s) {
+        const int ny_ = d == 2 ? Q[s] : 1;
+        for (int ky = 0; ky < ny_; ++ky)
+            for (int kx = 0; kx < Q[s]; ++kx, ++v) {
+                PlaneDesc& pd = t->plane[v];
+                pd.px = c->p[s][kx];
+                pd.py = d == 2 ? c->p[s][ky] : 0.0;
+                pd.set = s;
+                pd.kx = kx;
+                pd.ky = ky;
+                if (s == 0) {
+                    pd.m0 = 1.0;
+                    pd.mx = pd.px;
+                    pd.my = pd.py;
+                    pd.me = pd.px * pd.px + pd.py * pd.py;
+                } else {
+                    pd.m0 = pd.mx = pd.my = 0.0;
+                    pd.me = 1.0;
+                }
+            }
+    }
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_tab, sizeof(DevTables));
+    c->nred = kRedBlocks;
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_small, sizeof(double) * (4 * c->nred + 4));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_flag, sizeof(int) * 64);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_tab, t, sizeof(DevTables), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    delete t;
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "imexlb_create: %s\n", hipGetErrorString(e));
+        imexlb_destroy(c);
+        return IMEXLB_EHIP;
+    }
+    *out = c;
+    return IMEXLB_OK;
+}
+
+void imexlb_destroy(imexlb_ctx* c) {
+    if (!c) return;
+    if (c->d_tab) (void)hipFree(c->d_tab);
+    if (c->d_small) (void)hipFree(c->d_small);
+    if (c->d_flag) (void)hipFree(c->d_flag);
+    delete c;
+}
+
+imexlb_status imexlb_set_stream(imexlb_ctx* c, void* s) {
+    if (!c) return IMEXLB_EINVAL;
+    c->stream = (hipStream_t)s;
+    return IMEXLB_OK;
+}
+
+size_t imexlb_state_bytes(const imexlb_ctx* c) {
+    return c ? (size_t)c->nplanes * c->cells * c->elem : 0;
+}
+
+size_t imexlb_workspace_bytes(const imexlb_ctx* c) {
+    if (!c) return 0;
+    return 2 * align256((size_t)c->nplanes * c->cells * c->elem) +
+           3 * align256((size_t)c->nf * c->cells * sizeof(double));
+}
+
+int imexlb_num_planes(const imexlb_ctx* c) { return c ? c->nplanes : 0; }
+
+imexlb_status imexlb_bind(imexlb_ctx* c, void* d_state, void* d_work) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!d_state || !d_work) return fail(c, IMEXLB_EINVAL, "bind: NULL buffer");
+    if (((uintptr_t)d_state & 255) || ((uintptr_t)d_work & 255))
+        return fail(c, IMEXLB_EINVAL, "bind: buffers must be 256-byte aligned");
+    c->d_state = d_state;
+    c->d_work = d_work;
+    c->have_state = false;
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_quadrature(const imexlb_ctx* c, double* pp, double* wp, double* pc, double* wc) {
+    if (!c) return IMEXLB_EINVAL;
+    for (int k = 0; k < c->cfg.q_phi; ++k) {
+        if (pp) pp[k] = c->p[0][k];
+        if (wp) wp[k] = c->w[0][k];
+    }
+    for (int k = 0; k < c->cfg.q_chi; ++k) {
+        if (pc) pc[k] = c->p[1][k];
+        if (wc) wc[k] = c->w[1][k];
+    }
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_set_equilibrium(imexlb_ctx* c, const double* n, const double* ux,
+                                     const double* uy, const double* T) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!c->d_state || !c->d_work) return fail(c, IMEXLB_ESTATE, "set_equilibrium: not bound");
+    if (!n || !ux || !T || (c->cfg.d == 2 && !uy)) return fail(c, IMEXLB_EINVAL, "set_equilibrium: NULL field");
+    const bool f32 = c->cfg.storage == IMEXLB_F32;
+    hipError_t e = launch_init_equilibrium(c->cfg.d, f32, c->d_tab, n, ux, uy, T, c->d_state, nullptr,
+                                           c->cells, (double)(c->cfg.K + kDTotal - c->cfg.d), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set_equilibrium");
+    e = launch_moments(c->cfg.d, f32, c->d_tab, c->d_state, work_m(c, 0), c->cells,
+                       (double)(kDTotal + c->cfg.K), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set_equilibrium moments");
+    c->have_state = true;
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_set_state(imexlb_ctx* c, const void* F) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!c->d_state || !c->d_work) return fail(c, IMEXLB_ESTATE, "set_state: not bound");
+    if (!F) return fail(c, IMEXLB_EINVAL, "set_state: NULL");
+    hipError_t e = hipSuccess;
+    if (F != c->d_state)
+        e = hipMemcpyAsync(c->d_state, F, imexlb_state_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set_state copy");
+    e = launch_moments(c->cfg.d, c->cfg.storage == IMEXLB_F32, c->d_tab, c->d_state, work_m(c, 0),
+                       c->cells, (double)(kDTotal + c->cfg.K), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set_state moments");
+    c->have_state = true;
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_get_state(const imexlb_ctx* c, void* F) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!F) return fail(const_cast<imexlb_ctx*>(c), IMEXLB_EINVAL, "get_state: NULL");
+    if (need_state(c) != IMEXLB_OK) return fail(const_cast<imexlb_ctx*>(c), IMEXLB_ESTATE, "get_state: no state");
+    if (F == c->d_state) return IMEXLB_OK;
+    hipError_t e = hipMemcpyAsync(F, c->d_state, imexlb_state_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(const_cast<imexlb_ctx*>(c), e, "get_state");
+    return IMEXLB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The launch sequence of nsteps IMEX steps.  When ev is non-NULL it holds
+// 3 * nsteps + 1 events recorded around the passes.
+imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev) {
+    const int d = c->cfg.d;
+    const bool f32 = c->cfg.storage == IMEXLB_F32;
+    StageArgs a = base_args(c);
+    void* F = c->d_state;
+    void* G3 = work_g(c, 0);
+    void* G4 = work_g(c, 1);
+    double* Mn = work_m(c, 0);
+    double* M3 = work_m(c, 1);
+    double* M4 = work_m(c, 2);
+    const double cc = kAlpha * a.omega;
+    // pass 3 advects F2 = a2 F^n + b2 E^n; passes 4 and 5 advect
+    // F3 = a1 G3 + c a1 E3 and F4 = a1 G4 + c a1 E4.
+    StageArgs a3 = a, a4 = a, a5 = a;
+    a3.src = F;
+    a3.msrc = Mn;
+    a3.out = G3;
+    a3.mout = M3;
+    a3.a_rel = a.a2;
+    a3.b_rel = cc * cc / ((1.0 + cc) * (1.0 + cc));
+    a4.src = G3;
+    a4.msrc = M3;
+    a4.out = G4;
+    a4.mout = M4;
+    a4.fbuf = F;
+    a4.mn = Mn;
+    a4.a_rel = a.a1;
+    a4.b_rel = cc * a.a1;
+    a5.src = G4;
+    a5.msrc = M4;
+    a5.out = F;
+    a5.mout = Mn;
+    a5.fbuf = F;
+    a5.a_rel = a.a1;
+    a5.b_rel = cc * a.a1;
+    hipError_t e = hipSuccess;
+    if (ev) e = hipEventRecord(ev[0], c->stream);
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+        e = launch_stage(d, f32, kStage3, a3, c->stream);
+        if (e == hipSuccess && ev) e = hipEventRecord(ev[3 * s + 1], c->stream);
+        if (e == hipSuccess) e = launch_stage(d, f32, kStage4, a4, c->stream);
+        if (e == hipSuccess && ev) e = hipEventRecord(ev[3 * s + 2], c->stream);
+        if (e == hipSuccess) e = launch_stage(d, f32, kStage5, a5, c->stream);
+        if (e == hipSuccess && ev) e = hipEventRecord(ev[3 * s + 3], c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "step");
+    return IMEXLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+imexlb_status imexlb_step(imexlb_ctx* c, int nsteps) {
+    if (!c) return IMEXLB_EINVAL;
+    if (nsteps < 0) return fail(c, IMEXLB_EINVAL, "step: nsteps < 0");
+    if (need_state(c) != IMEXLB_OK) return fail(c, IMEXLB_ESTATE, "step: no bound state");
+    return run_steps(c, nsteps, nullptr);
+}
+
+imexlb_status imexlb_step_timed(imexlb_ctx* c, int nsteps, double ms[3]) {
+    if (!c || !ms) return IMEXLB_EINVAL;
+    if (nsteps < 0) return fail(c, IMEXLB_EINVAL, "step_timed: nsteps < 0");
+    if (need_state(c) != IMEXLB_OK) return fail(c, IMEXLB_ESTATE, "step_timed: no bound state");
+    const int ne = 3 * nsteps + 1;
+    hipEvent_t* ev = new (std::nothrow) hipEvent_t[ne];
+    if (!ev) return fail(c, IMEXLB_ENOMEM, "step_timed: events");
+    int made = 0;
+    hipError_t e = hipSuccess;
+    for (; made < ne && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
+    imexlb_status st = IMEXLB_OK;
+    if (e != hipSuccess) {
+        --made;
+        st = hip_fail(c, e, "step_timed: event create");
+    } else {
+        st = run_steps(c, nsteps, ev);
+        if (st == IMEXLB_OK) {
+            e = hipEventSynchronize(ev[ne - 1]);
+            for (int s = 0; s < nsteps && e == hipSuccess; ++s)
+                for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+                    float t = 0.0f;
+                    e = hipEventElapsedTime(&t, ev[3 * s + k], ev[3 * s + k + 1]);
+                    ms[k] += t;
+                }
+            if (e != hipSuccess) st = hip_fail(c, e, "step_timed: elapsed");
+        }
+    }
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    delete[] ev;
+    return st;
+}
+
+imexlb_status imexlb_moments(const imexlb_ctx* c, double* n, double* ux, double* uy, double* T) {
+    if (!c) return IMEXLB_EINVAL;
+    imexlb_ctx* m = const_cast<imexlb_ctx*>(c);
+    if (need_state(c) != IMEXLB_OK) return fail(m, IMEXLB_ESTATE, "moments: no state");
+    const double* M = work_m(c, 0);
+    const size_t b = (size_t)c->cells * sizeof(double);
+    double* dst[4] = {n, ux, c->cfg.d == 2 ? uy : nullptr, T};
+    int src[4] = {0, 1, 2, c->nf - 1};
+    for (int f = 0; f < 4; ++f) {
+        if (!dst[f]) continue;
+        hipError_t e = hipMemcpyAsync(dst[f], M + (size_t)src[f] * c->cells, b, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(m, e, "moments copy");
+    }
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_compute_moments(const imexlb_ctx* c, const void* F, double* n, double* ux,
+                                     double* uy, double* T) {
+    if (!c) return IMEXLB_EINVAL;
+    imexlb_ctx* m = const_cast<imexlb_ctx*>(c);
+    if (!c->d_work) return fail(m, IMEXLB_ESTATE, "compute_moments: not bound");
+    if (!F || !n || !ux || !T) return fail(m, IMEXLB_EINVAL, "compute_moments: NULL");
+    // computed into the M3 slot of the workspace, then copied out
+    double* M = work_m(c, 1);
+    hipError_t e = launch_moments(c->cfg.d, c->cfg.storage == IMEXLB_F32, c->d_tab, F, M, c->cells,
+                                  (double)(kDTotal + c->cfg.K), c->stream);
+    if (e != hipSuccess) return hip_fail(m, e, "compute_moments");
+    const size_t b = (size_t)c->cells * sizeof(double);
+    double* dst[4] = {n, ux, c->cfg.d == 2 ? uy : nullptr, T};
+    int src[4] = {0, 1, 2, c->nf - 1};
+    for (int f = 0; f < 4; ++f) {
+        if (!dst[f]) continue;
+        e = hipMemcpyAsync(dst[f], M + (size_t)src[f] * c->cells, b, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(m, e, "compute_moments copy");
+    }
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_advect(const imexlb_ctx* c, const void* F, double* VF) {
+    if (!c) return IMEXLB_EINVAL;
+    imexlb_ctx* m = const_cast<imexlb_ctx*>(c);
+    if (!F || !VF) return fail(m, IMEXLB_EINVAL, "advect: NULL");
+    StageArgs a = base_args(c);
+    a.src = F;
+    a.out = VF;
+    a.a_rel = 1.0;
+    a.b_rel = 0.0;
+    hipError_t e = launch_stage(c->cfg.d, c->cfg.storage == IMEXLB_F32, kAdvect, a, c->stream);
+    if (e != hipSuccess) return hip_fail(m, e, "advect");
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_domain_sums(const imexlb_ctx* c, double out[4]) {
+    if (!c || !out) return IMEXLB_EINVAL;
+    imexlb_ctx* m = const_cast<imexlb_ctx*>(c);
+    if (need_state(c) != IMEXLB_OK) return fail(m, IMEXLB_ESTATE, "domain_sums: no state");
+    double* part = c->d_small;
+    double* res = c->d_small + 4 * c->nred;
+    hipError_t e = launch_domain_sums(c->cfg.d, work_m(c, 0), c->cells, (double)(kDTotal + c->cfg.K), part,
+                                      c->nred, res, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(m, e, "domain_sums");
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_check_state(const imexlb_ctx* c) {
+    if (!c) return IMEXLB_EINVAL;
+    imexlb_ctx* m = const_cast<imexlb_ctx*>(c);
+    if (need_state(c) != IMEXLB_OK) return fail(m, IMEXLB_ESTATE, "check_state: no state");
+    int h = 0;
+    hipError_t e = launch_check(c->cfg.d, work_m(c, 0), c->cells, c->d_flag, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(m, e, "check_state");
+    return h ? fail(m, IMEXLB_ENONPHYS, "check_state: non-physical moments") : IMEXLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,892 @@
+// HIP kernels of the imexlb library for gfx950 (MI355X).
+//
+// One IMEX-SSP3(4,3,3) step (Sec. III, Table I) runs as three fused stage
+// passes over the plane-sets; the BGK stages are closed forms because the
+// collision conserves n, u and T (Sec. III):
+//
+//   c = alpha dt/tau, w = dt/tau, a1 = 1/(1+c), a2 = (1+2c)/(1+c)^2, b2 = 1-a2
+//   F1 = a1 F^n + c a1 E^n,  F2 = a2 F^n + b2 E^n          (stages 1-2, pointwise)
+//   pass 3: G3 = F^n - dt V F2 - (1-alpha) dF2,  M3 = moments(G3)
+//   pass 4: F3 = a1 G3 + c a1 E3 (relax on read),
+//           G4 = F^n - (dt/4)(V F2 + V F3) - beta dF1 - eta dF2 - kappa dF3,
+//           R  = F^n - (dt/6)(V F2 + V F3) - (dF2 + dF3)/6  (written over F^n),
+//           M4 = moments(G4)
+//   pass 5: F4 = a1 G4 + c a1 E4 (relax on read),
+//           F^{n+1} = R - (2/3)(dt V F4 + dF4),  M^{n+1} = moments(F^{n+1})
+//   with dF1 = w a1 (F^n - E^n), dF2 = w a2 (F^n - E^n), dF3 = w a1 (G3 - E3),
+//   dF4 = w a1 (G4 - E4), kappa = 1/2 - alpha - beta - eta, and dt V F2
+//   recovered pointwise in pass 4 as F^n - (1 - alpha) dF2 - G3.
+//
+// Every pass streams all planes of a tile of cells through LDS: per plane,
+// the tile plus a 5-cell cross-shaped halo is loaded, relaxed on read to
+// the stage value F_i = a G + b E_i (the equilibrium E_i rebuilt per cell
+// from the stage moments), swept with MP-9 along x and y, combined with the
+// pointwise terms, stored, and its moments accumulated in FP64 registers
+// across the plane loop.  The advection operator V is the MP-9 flux
+// difference of Sec. IV, dimensionally unsplit.
+#include "common.hpp"
+
+namespace imexlb {
+namespace {
+
+// Table I constants.
+constexpr double kAlpha = 0.24169426078821;
+constexpr double kBeta = 0.06042356519705;
+constexpr double kEta = 0.12915286960590;
+constexpr double kKappa = 0.5 - kBeta - kEta - kAlpha;
+
+// Ghost-node addressing (Sec. IV): outflow copies the boundary node,
+// periodic wraps.
+__device__ __forceinline__ int bc_map(int i, int n, int bc) {
+    if (bc == 1) {
+        i %= n;
+        return i < 0 ? i + n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// One-axis factor of the discrete equilibrium, Eq. (gExpanded):
+// g_k = w_k sum_l He_l(p_k)/l! a_l with a_l = sum_s l!/(2^s s!(l-2s)!) (T-1)^s u^(l-2s).
+// The a_l satisfy a_0 = 1, a_1 = u, a_{l+1} = u a_l + l (T-1) a_{l-1}
+// (they are E[He_l(X)] for X ~ N(u, T)); h[l] = w_k He_l(p_k)/l! is tabulated.
+__device__ __forceinline__ double herm_factor(const double* __restrict__ h, int Q, double u,
+                                              double th) {
+    double am = 1.0, ac = u;
+    double g = fma(h[1], u, h[0]);
+    double lth = th;  // l (T - 1)
+    for (int l = 1; l < Q - 1; ++l) {
+        const double an = fma(u, ac, lth * am);
+        g = fma(h[l + 1], an, g);
+        am = ac;
+        ac = an;
+        lth += th;
+    }
+    return g;
+}
+
+template <typename R>
+__device__ __forceinline__ R med3(R a, R b, R c) {
+    return fmax(fmin(a, b), fmin(fmax(a, b), c));
+}
+
+// Four-argument minmod: signed smallest magnitude when all share a sign.
+template <typename R>
+__device__ __forceinline__ R minmod4(R a, R b, R c, R d) {
+    const R mn = fmin(fmin(a, b), fmin(c, d));
+    const R mx = fmax(fmax(a, b), fmax(c, d));
+    return fmax(mn, R(0)) + fmin(mx, R(0));
+}
+
+// MP-9 interface values along a line (Sec. IV) for an upwind-first window
+// w[0 .. L+8]: the face between window positions m and m+1 (m = 4 .. L+4)
+// is reconstructed from w[m-4 .. m+4] with w[m] the upwind node.  Returns
+// dif[i] = face(5+i) - face(4+i), the flux difference of the node at
+// window position 5+i (divide by delta s, multiply by |p|).
+//
+// F^L is evaluated in difference form, F_s + sum_j e_j (F_{j+1} - F_j), with
+// e = (-4, 37, -162, 479, 1120, -255, 50, -5)/2520 (the paper's nine weights
+// re-expressed on first differences), so uniform data give F^L = F_s
+// exactly.  When (F^L - F_s)(F^L - F^MP) <= 0 the face is F^L; otherwise it
+// is F^L clipped to [F^min, F^max] (equal to F^L + minmod(F^min - F^L,
+// F^max - F^L), since F^min <= F_s <= F^max).  F^MP = median(F_s, F_{s+1},
+// F^UL) equals F_s + minmod(F_{s+1} - F_s, 4 (F_s - F_{s-1})).  The
+// limiter branch is skipped when no lane of the wavefront needs it.
+template <typename R, int L>
+__device__ __forceinline__ void mp9_line(const R (&w)[L + 9], R (&dif)[L]) {
+    constexpr R e0 = R(-4.0 / 2520.0), e1 = R(37.0 / 2520.0), e2 = R(-162.0 / 2520.0),
+                e3 = R(479.0 / 2520.0), e4 = R(1120.0 / 2520.0), e5 = R(-255.0 / 2520.0),
+                e6 = R(50.0 / 2520.0), e7 = R(-5.0 / 2520.0);
+    R d[L + 8];
+#pragma unroll
+    for (int j = 0; j < L + 8; ++j) d[j] = w[j + 1] - w[j];
+    R fl[L + 1], ul[L + 1];
+    bool need[L + 1];
+    bool slow = false;
+#pragma unroll
+    for (int i = 0; i <= L; ++i) {
+        const int m = i + 4;
+        const R fs = w[m];
+        R s = e0 * d[m - 4];
+        s = fma(e1, d[m - 3], s);
+        s = fma(e2, d[m - 2], s);
+        s = fma(e3, d[m - 1], s);
+        s = fma(e4, d[m], s);
+        s = fma(e5, d[m + 1], s);
+        s = fma(e6, d[m + 2], s);
+        s = fma(e7, d[m + 3], s);
+        fl[i] = fs + s;
+        ul[i] = fma(R(4), d[m - 1], fs);
+        const R fmp = med3(fs, w[m + 1], ul[i]);
+        need[i] = (fl[i] - fs) * (fl[i] - fmp) > R(0);
+        slow |= need[i];
+    }
+    if (slow) {
+        R C[L + 3];  // C_m = d_m - d_{m-1} at m = 3 .. L+5
+#pragma unroll
+        for (int k = 0; k < L + 3; ++k) C[k] = d[k + 3] - d[k + 2];
+        R D[L + 2];  // D(m) = minmod4 over the curvature pair (m, m+1), m = 3 .. L+4
+#pragma unroll
+        for (int k = 0; k < L + 2; ++k)
+            D[k] = minmod4(fma(R(4), C[k], -C[k + 1]), fma(R(4), C[k + 1], -C[k]), C[k], C[k + 1]);
+#pragma unroll
+        for (int i = 0; i <= L; ++i) {
+            const int m = i + 4;
+            const R fs = w[m], fp = w[m + 1];
+            const R lc = fma(R(4.0 / 3.0), D[i], fma(R(0.5), d[m - 1], fs));
+            const R md = fma(R(0.5), d[m] - D[i + 1], fs);
+            const R lo = fmax(fmin(fmin(fs, fp), md), fmin(fmin(fs, ul[i]), lc));
+            const R hi = fmin(fmax(fmax(fs, fp), md), fmax(fmax(fs, ul[i]), lc));
+            const R clipped = fmin(fmax(fl[i], lo), hi);
+            fl[i] = need[i] ? clipped : fl[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) dif[i] = fl[i + 1] - fl[i];
+}
+
+template <typename S>
+struct Vec4;
+template <>
+struct Vec4<double> {
+    using T = double4;
+};
+template <>
+struct Vec4<float> {
+    using T = float4;
+};
+
+template <typename S>
+__device__ __forceinline__ void load4(const S* p, double (&o)[4]) {
+    const typename Vec4<S>::T v = *reinterpret_cast<const typename Vec4<S>::T*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+}
+
+template <typename S>
+__device__ __forceinline__ void store4(S* p, const S (&o)[4]) {
+    typename Vec4<S>::T v;
+    v.x = o[0];
+    v.y = o[1];
+    v.z = o[2];
+    v.w = o[3];
+    *reinterpret_cast<typename Vec4<S>::T*>(p) = v;
+}
+
+// Moments accumulated per cell in FP64 (Sec. II, Eq. Moments_discrete).
+struct Acc {
+    double s0, sx, sy, se;
+};
+
+__device__ __forceinline__ void acc_add(Acc& a, const PlaneDesc& pd, double f) {
+    a.s0 = fma(pd.m0, f, a.s0);
+    a.sx = fma(pd.mx, f, a.sx);
+    a.sy = fma(pd.my, f, a.sy);
+    a.se = fma(pd.me, f, a.se);
+}
+
+// ---------------------------------------------------------------------------
+// Two-dimensional stage pass.  Tile TX x TY cells, 256 threads.  Thread t owns
+// the 4 consecutive cells (4 seg .. 4 seg + 3, row) with seg = t % 16,
+// row = t / 16, sweeps them along x, and sweeps the 4-cell column segment
+// (column t % 64, rows 4 (t / 64) ..) along y for the y-part of V.
+// ---------------------------------------------------------------------------
+template <typename S, int KIND>
+__global__ void __launch_bounds__(256) stage2d_kernel(StageArgs a) {
+    constexpr int TX = kTile2X, TY = kTile2Y, NT = 256, L = 4;
+    constexpr int SEG = TX / L;
+    constexpr int P = TX + 10;              // LDS row pitch
+    constexpr int NH = 10 * TY + 10 * TX;   // cross-shaped halo
+    constexpr int HS = (NH + NT - 1) / NT;  // halo slots per thread
+    constexpr int NS = L + HS;              // loaded cells per thread
+    constexpr bool RELAX = KIND != kAdvect;
+    static_assert(SEG * TY == NT && TX * (TY / L) == NT, "tile / thread mismatch");
+    using R = S;
+
+    __shared__ S tile[2][(TY + 10) * P];
+    __shared__ R vfy[TY * TX];
+
+    const int tid = threadIdx.x;
+    const int logical = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
+    if (logical >= a.ntx * a.nty) return;
+    const int x0 = (logical % a.ntx) * TX;
+    const int y0 = (logical / a.ntx) * TY;
+    const int nx = a.nx, ny = a.ny;
+    const long long ps = a.plane_stride;
+    const DevTables* __restrict__ tab = a.tab;
+
+    const int orow = tid / SEG, oseg = tid % SEG;
+    const int oy = y0 + orow, ox0 = x0 + oseg * L;
+    const bool row_real = oy < ny;
+    const bool vec = (x0 + TX <= nx) && (y0 + TY <= ny) && (nx % 4 == 0);
+
+    int gcell[NS];
+    int lidx[NS];
+    {
+        const int gy = bc_map(oy, ny, a.bcy) * nx;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            gcell[i] = gy + bc_map(ox0 + i, nx, a.bcx);
+            lidx[i] = (orow + 5) * P + oseg * L + i + 5;
+        }
+#pragma unroll
+        for (int j = 0; j < HS; ++j) {
+            const int h = tid + j * NT;
+            int lx = 0, ly = 0;
+            if (h < 10 * TY) {  // x-halo: 5 left + 5 right nodes of each row
+                const int k = h % 10;
+                ly = h / 10 + 5;
+                lx = k < 5 ? k : TX + k;
+            } else {            // y-halo: 5 rows below + 5 above
+                const int hh = h - 10 * TY;
+                const int k = hh / TX;
+                lx = hh % TX + 5;
+                ly = k < 5 ? k : TY + k;
+            }
+            if (h < NH) {
+                gcell[L + j] = bc_map(y0 + ly - 5, ny, a.bcy) * nx + bc_map(x0 + lx - 5, nx, a.bcx);
+                lidx[L + j] = ly * P + lx;
+            } else {
+                gcell[L + j] = -1;
+                lidx[L + j] = 0;
+            }
+        }
+    }
+
+    // Per loaded cell: u_x and T - 1 of the source moments, and the plane
+    // group factor A = P_set * g_y (P_phi = n, P_chi = (K + D - d) n T).
+    double sux[NS], sth[NS], sA[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        sux[s] = 0.0;
+        sth[s] = 0.0;
+        sA[s] = 0.0;
+        if (RELAX && gcell[s] >= 0) {
+            sux[s] = a.msrc[ps + gcell[s]];
+            sth[s] = a.msrc[3 * ps + gcell[s]] - 1.0;
+        }
+    }
+    // Stage 4 also needs E^n at its own cells.
+    double nux[L], nth[L], nA[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        nux[i] = 0.0;
+        nth[i] = 0.0;
+        nA[i] = 0.0;
+        if (KIND == kStage4) {
+            nux[i] = a.mn[ps + gcell[i]];
+            nth[i] = a.mn[3 * ps + gcell[i]] - 1.0;
+        }
+    }
+    Acc acc[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) acc[i] = Acc{0.0, 0.0, 0.0, 0.0};
+
+    int parity = 0;
+    for (int set = 0; set < 2; ++set) {
+        const int Q = tab->q[set];
+        const int vbase = set ? tab->nphi : 0;
+        for (int ky = 0; ky < Q; ++ky) {
+            if constexpr (RELAX) {
+                const double* hy = tab->h[set][ky];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (gcell[s] >= 0) {
+                        const double n = a.msrc[gcell[s]];
+                        const double uy = a.msrc[2 * ps + gcell[s]];
+                        const double pre = set ? a.chi_fac * n * (sth[s] + 1.0) : n;
+                        sA[s] = pre * herm_factor(hy, Q, uy, sth[s]);
+                    }
+                }
+                if constexpr (KIND == kStage4) {
+#pragma unroll
+                    for (int i = 0; i < L; ++i) {
+                        const double n = a.mn[gcell[i]];
+                        const double uy = a.mn[2 * ps + gcell[i]];
+                        const double pre = set ? a.chi_fac * n * (nth[i] + 1.0) : n;
+                        nA[i] = pre * herm_factor(hy, Q, uy, nth[i]);
+                    }
+                }
+            }
+            for (int kx = 0; kx < Q; ++kx) {
+                const int v = vbase + kx + Q * ky;
+                const PlaneDesc pd = tab->plane[v];
+                const double* hx = tab->h[set][kx];
+                const S* __restrict__ sv = static_cast<const S*>(a.src) + (size_t)v * ps;
+                S* buf = tile[parity];
+                parity ^= 1;
+
+                double gown[L], eown[L];
+                if (vec) {
+                    load4<S>(sv + gcell[0], gown);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < L; ++i) gown[i] = sv[gcell[i]];
+                }
+                double ghalo[HS];
+#pragma unroll
+                for (int j = 0; j < HS; ++j) ghalo[j] = gcell[L + j] >= 0 ? (double)sv[gcell[L + j]] : 0.0;
+
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    double val = gown[i];
+                    eown[i] = 0.0;
+                    if constexpr (RELAX) {
+                        eown[i] = sA[i] * herm_factor(hx, Q, sux[i], sth[i]);
+                        val = fma(a.a_rel, gown[i], a.b_rel * eown[i]);
+                    }
+                    buf[lidx[i]] = (S)val;
+                }
+#pragma unroll
+                for (int j = 0; j < HS; ++j) {
+                    if (gcell[L + j] >= 0) {
+                        double val = ghalo[j];
+                        if constexpr (RELAX) {
+                            const double e = sA[L + j] * herm_factor(hx, Q, sux[L + j], sth[L + j]);
+                            val = fma(a.a_rel, ghalo[j], a.b_rel * e);
+                        }
+                        buf[lidx[L + j]] = (S)val;
+                    }
+                }
+                __syncthreads();
+
+                // x sweep of the own segment
+                R difx[L];
+#pragma unroll
+                for (int i = 0; i < L; ++i) difx[i] = R(0);
+                if (pd.px != 0.0) {
+                    const bool fwd = pd.px > 0.0;
+                    const S* base = buf + (orow + 5) * P + oseg * L + (fwd ? 0 : L + 9);
+                    const int st = fwd ? 1 : -1;
+                    R w[L + 9];
+#pragma unroll
+                    for (int m = 0; m < L + 9; ++m) w[m] = base[m * st];
+                    R dif[L];
+                    mp9_line<R, L>(w, dif);
+                    if (fwd) {
+#pragma unroll
+                        for (int i = 0; i < L; ++i) difx[i] = dif[i];
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < L; ++i) difx[i] = dif[L - 1 - i];
+                    }
+                }
+                // y sweep of column segment (c, rows L sy ..)
+                if (pd.py != 0.0) {
+                    const int c = tid % TX, sy = tid / TX;
+                    const bool fwd = pd.py > 0.0;
+                    const S* base = buf + (sy * L + (fwd ? 0 : L + 9)) * P + c + 5;
+                    const int st = fwd ? P : -P;
+                    R w[L + 9];
+#pragma unroll
+                    for (int m = 0; m < L + 9; ++m) w[m] = base[m * st];
+                    R dif[L];
+                    mp9_line<R, L>(w, dif);
+#pragma unroll
+                    for (int i = 0; i < L; ++i) {
+                        const int r = fwd ? sy * L + i : sy * L + L - 1 - i;
+                        vfy[r * TX + c] = dif[i];
+                    }
+                }
+                __syncthreads();
+
+                const double sx = fabs(pd.px) * a.inv_dx;
+                const double sy = fabs(pd.py) * a.inv_dy;
+                double vf[L];
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    vf[i] = (double)difx[i] * sx;
+                    if (pd.py != 0.0) vf[i] = fma((double)vfy[orow * TX + oseg * L + i], sy, vf[i]);
+                }
+
+                const size_t own0 = (size_t)v * ps + (size_t)oy * nx + ox0;
+                if constexpr (KIND == kAdvect) {
+                    double* o = static_cast<double*>(a.out) + own0;
+#pragma unroll
+                    for (int i = 0; i < L; ++i)
+                        if (row_real && ox0 + i < nx) o[i] = vf[i];
+                } else {
+                    S outv[L], fbv[L];
+                    double fb[L];
+                    if constexpr (KIND == kStage4 || KIND == kStage5) {
+                        const S* fbp = static_cast<const S*>(a.fbuf) + (size_t)v * ps;
+                        if (vec) {
+                            load4<S>(fbp + gcell[0], fb);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < L; ++i) fb[i] = fbp[gcell[i]];
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < L; ++i) {
+                        if constexpr (KIND == kStage3) {
+                            const double fn = gown[i], en = eown[i];
+                            const double s3 = fn - a.dt * vf[i] - (1.0 - kAlpha) * a.omega * a.a2 * (fn - en);
+                            outv[i] = (S)s3;
+                        } else if constexpr (KIND == kStage4) {
+                            const double fn = fb[i];
+                            const double en = nA[i] * herm_factor(hx, Q, nux[i], nth[i]);
+                            const double g3 = gown[i], e3 = eown[i];
+                            const double dn = fn - en, d3 = g3 - e3;
+                            const double df1 = a.omega * a.a1 * dn;
+                            const double df2 = a.omega * a.a2 * dn;
+                            const double df3 = a.omega * a.a1 * d3;
+                            const double dtvf2 = fn - (1.0 - kAlpha) * df2 - g3;
+                            const double dtvf3 = a.dt * vf[i];
+                            const double s4 = fn - 0.25 * (dtvf2 + dtvf3) - kBeta * df1 - kEta * df2 - kKappa * df3;
+                            const double r = fn - (dtvf2 + dtvf3) * (1.0 / 6.0) - (df2 + df3) * (1.0 / 6.0);
+                            outv[i] = (S)s4;
+                            fbv[i] = (S)r;
+                        } else {  // kStage5
+                            const double r = fb[i];
+                            const double df4 = a.omega * a.a1 * (gown[i] - eown[i]);
+                            fbv[i] = (S)(r - (2.0 / 3.0) * (a.dt * vf[i] + df4));
+                        }
+                    }
+                    S* op = static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + own0;
+                    const S(&ov)[L] = (KIND == kStage5) ? fbv : outv;
+                    if (vec) {
+                        store4<S>(op, ov);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < L; ++i)
+                            if (row_real && ox0 + i < nx) op[i] = ov[i];
+                    }
+                    if constexpr (KIND == kStage4) {
+                        S* fp = static_cast<S*>(a.fbuf) + own0;
+                        if (vec) {
+                            store4<S>(fp, fbv);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < L; ++i)
+                                if (row_real && ox0 + i < nx) fp[i] = fbv[i];
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < L; ++i) acc_add(acc[i], pd, (double)ov[i]);
+                }
+            }
+        }
+    }
+
+    if constexpr (KIND != kAdvect) {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            if (row_real && ox0 + i < nx) {
+                const double n = acc[i].s0;
+                const double ux = acc[i].sx / n, uy = acc[i].sy / n;
+                const double T = (acc[i].se - n * (ux * ux + uy * uy)) / (a.dk * n);
+                const size_t c = (size_t)oy * nx + ox0 + i;
+                a.mout[c] = n;
+                a.mout[ps + c] = ux;
+                a.mout[2 * ps + c] = uy;
+                a.mout[3 * ps + c] = T;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-dimensional stage pass.  Tile of 1024 cells, 256 threads, 4 cells per
+// thread; moments (n, u_x, T).
+// ---------------------------------------------------------------------------
+template <typename S, int KIND>
+__global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
+    constexpr int NT = 256, L = 4, TX = kTile1X;
+    constexpr int P = TX + 10;
+    constexpr int NS = L + 1;
+    constexpr bool RELAX = KIND != kAdvect;
+    static_assert(NT * L == TX, "tile / thread mismatch");
+    using R = S;
+
+    __shared__ S tile[2][P];
+
+    const int tid = threadIdx.x;
+    const int logical = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
+    if (logical >= a.ntx) return;
+    const int x0 = logical * TX;
+    const int nx = a.nx;
+    const long long ps = a.plane_stride;
+    const DevTables* __restrict__ tab = a.tab;
+    const int ox0 = x0 + tid * L;
+    const bool vec = (x0 + TX <= nx) && (nx % 4 == 0);
+
+    int gcell[NS], lidx[NS];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        gcell[i] = bc_map(ox0 + i, nx, a.bcx);
+        lidx[i] = tid * L + i + 5;
+    }
+    if (tid < 10) {
+        const int lx = tid < 5 ? tid : TX + tid;
+        gcell[L] = bc_map(x0 + lx - 5, nx, a.bcx);
+        lidx[L] = lx;
+    } else {
+        gcell[L] = -1;
+        lidx[L] = 0;
+    }
+
+    double sux[NS], sth[NS], sA[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        sux[s] = 0.0;
+        sth[s] = 0.0;
+        sA[s] = 0.0;
+        if (RELAX && gcell[s] >= 0) {
+            sux[s] = a.msrc[ps + gcell[s]];
+            sth[s] = a.msrc[2 * ps + gcell[s]] - 1.0;
+        }
+    }
+    double nux[L], nth[L], nA[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        nux[i] = 0.0;
+        nth[i] = 0.0;
+        nA[i] = 0.0;
+        if (KIND == kStage4) {
+            nux[i] = a.mn[ps + gcell[i]];
+            nth[i] = a.mn[2 * ps + gcell[i]] - 1.0;
+        }
+    }
+    Acc acc[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) acc[i] = Acc{0.0, 0.0, 0.0, 0.0};
+
+    int parity = 0;
+    for (int set = 0; set < 2; ++set) {
+        const int Q = tab->q[set];
+        const int vbase = set ? tab->nphi : 0;
+        if constexpr (RELAX) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (gcell[s] >= 0) {
+                    const double n = a.msrc[gcell[s]];
+                    sA[s] = set ? a.chi_fac * n * (sth[s] + 1.0) : n;
+                }
+            }
+            if constexpr (KIND == kStage4) {
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    const double n = a.mn[gcell[i]];
+                    nA[i] = set ? a.chi_fac * n * (nth[i] + 1.0) : n;
+                }
+            }
+        }
+        for (int kx = 0; kx < Q; ++kx) {
+            const int v = vbase + kx;
+            const PlaneDesc pd = tab->plane[v];
+            const double* hx = tab->h[set][kx];
+            const S* __restrict__ sv = static_cast<const S*>(a.src) + (size_t)v * ps;
+            S* buf = tile[parity];
+            parity ^= 1;
+
+            double gown[L], eown[L];
+            if (vec) {
+                load4<S>(sv + gcell[0], gown);
+            } else {
+#pragma unroll
+                for (int i = 0; i < L; ++i) gown[i] = sv[gcell[i]];
+            }
+            const double ghalo = gcell[L] >= 0 ? (double)sv[gcell[L]] : 0.0;
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                double val = gown[i];
+                eown[i] = 0.0;
+                if constexpr (RELAX) {
+                    eown[i] = sA[i] * herm_factor(hx, Q, sux[i], sth[i]);
+                    val = fma(a.a_rel, gown[i], a.b_rel * eown[i]);
+                }
+                buf[lidx[i]] = (S)val;
+            }
+            if (gcell[L] >= 0) {
+                double val = ghalo;
+                if constexpr (RELAX) {
+                    const double e = sA[L] * herm_factor(hx, Q, sux[L], sth[L]);
+                    val = fma(a.a_rel, ghalo, a.b_rel * e);
+                }
+                buf[lidx[L]] = (S)val;
+            }
+            __syncthreads();
+
+            R difx[L];
+#pragma unroll
+            for (int i = 0; i < L; ++i) difx[i] = R(0);
+            if (pd.px != 0.0) {
+                const bool fwd = pd.px > 0.0;
+                const S* base = buf + tid * L + (fwd ? 0 : L + 9);
+                const int st = fwd ? 1 : -1;
+                R w[L + 9];
+#pragma unroll
+                for (int m = 0; m < L + 9; ++m) w[m] = base[m * st];
+                R dif[L];
+                mp9_line<R, L>(w, dif);
+                if (fwd) {
+#pragma unroll
+                    for (int i = 0; i < L; ++i) difx[i] = dif[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < L; ++i) difx[i] = dif[L - 1 - i];
+                }
+            }
+            const double sx = fabs(pd.px) * a.inv_dx;
+            double vf[L];
+#pragma unroll
+            for (int i = 0; i < L; ++i) vf[i] = (double)difx[i] * sx;
+
+            const size_t own0 = (size_t)v * ps + ox0;
+            if constexpr (KIND == kAdvect) {
+                double* o = static_cast<double*>(a.out) + own0;
+#pragma unroll
+                for (int i = 0; i < L; ++i)
+                    if (ox0 + i < nx) o[i] = vf[i];
+            } else {
+                S outv[L], fbv[L];
+                double fb[L];
+                if constexpr (KIND == kStage4 || KIND == kStage5) {
+                    const S* fbp = static_cast<const S*>(a.fbuf) + (size_t)v * ps;
+                    if (vec) {
+                        load4<S>(fbp + gcell[0], fb);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < L; ++i) fb[i] = fbp[gcell[i]];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    if constexpr (KIND == kStage3) {
+                        const double fn = gown[i], en = eown[i];
+                        outv[i] = (S)(fn - a.dt * vf[i] - (1.0 - kAlpha) * a.omega * a.a2 * (fn - en));
+                    } else if constexpr (KIND == kStage4) {
+                        const double fn = fb[i];
+                        const double en = nA[i] * herm_factor(hx, Q, nux[i], nth[i]);
+                        const double g3 = gown[i], e3 = eown[i];
+                        const double dn = fn - en, d3 = g3 - e3;
+                        const double df1 = a.omega * a.a1 * dn;
+                        const double df2 = a.omega * a.a2 * dn;
+                        const double df3 = a.omega * a.a1 * d3;
+                        const double dtvf2 = fn - (1.0 - kAlpha) * df2 - g3;
+                        const double dtvf3 = a.dt * vf[i];
+                        outv[i] = (S)(fn - 0.25 * (dtvf2 + dtvf3) - kBeta * df1 - kEta * df2 - kKappa * df3);
+                        fbv[i] = (S)(fn - (dtvf2 + dtvf3) * (1.0 / 6.0) - (df2 + df3) * (1.0 / 6.0));
+                    } else {
+                        const double df4 = a.omega * a.a1 * (gown[i] - eown[i]);
+                        fbv[i] = (S)(fb[i] - (2.0 / 3.0) * (a.dt * vf[i] + df4));
+                    }
+                }
+                S* op = static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + own0;
+                const S(&ov)[L] = (KIND == kStage5) ? fbv : outv;
+                if (vec) {
+                    store4<S>(op, ov);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < L; ++i)
+                        if (ox0 + i < nx) op[i] = ov[i];
+                }
+                if constexpr (KIND == kStage4) {
+                    S* fp = static_cast<S*>(a.fbuf) + own0;
+                    if (vec) {
+                        store4<S>(fp, fbv);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < L; ++i)
+                            if (ox0 + i < nx) fp[i] = fbv[i];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < L; ++i) acc_add(acc[i], pd, (double)ov[i]);
+            }
+        }
+    }
+
+    if constexpr (KIND != kAdvect) {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            if (ox0 + i < nx) {
+                const double n = acc[i].s0;
+                const double ux = acc[i].sx / n;
+                const double T = (acc[i].se - n * ux * ux) / (a.dk * n);
+                const size_t c = (size_t)ox0 + i;
+                a.mout[c] = n;
+                a.mout[ps + c] = ux;
+                a.mout[2 * ps + c] = T;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// F = discrete equilibrium of (n, u, T) (Sec. II); one thread per cell.
+// ---------------------------------------------------------------------------
+template <typename S, int D>
+__global__ void __launch_bounds__(256) init_eq_kernel(const DevTables* __restrict__ tab,
+                                                      const double* __restrict__ n,
+                                                      const double* __restrict__ ux,
+                                                      const double* __restrict__ uy,
+                                                      const double* __restrict__ T, S* F,
+                                                      long long cells, double chi_fac) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const double nn = n[c], u = ux[c], w = D == 2 ? uy[c] : 0.0, th = T[c] - 1.0;
+    int v = 0;
+    for (int set = 0; set < 2; ++set) {
+        const int Q = tab->q[set];
+        const double pre = set ? chi_fac * nn * (th + 1.0) : nn;
+        for (int ky = 0; ky < (D == 2 ? Q : 1); ++ky) {
+            const double gy = D == 2 ? pre * herm_factor(tab->h[set][ky], Q, w, th) : pre;
+            for (int kx = 0; kx < Q; ++kx, ++v)
+                F[(size_t)v * cells + c] = (S)(gy * herm_factor(tab->h[set][kx], Q, u, th));
+        }
+    }
+}
+
+// Moments of a plane-set (Sec. II, Eq. Moments_discrete): n, n u from the phi
+// planes; (D + K) n T = sum_phi |p|^2 phi + sum_chi chi - n |u|^2.
+template <typename S, int D>
+__global__ void __launch_bounds__(256) moments_kernel(const DevTables* __restrict__ tab,
+                                                      const S* __restrict__ F, double* M,
+                                                      long long cells, double dk) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    Acc a{0.0, 0.0, 0.0, 0.0};
+    const int np = tab->nplanes;
+    for (int v = 0; v < np; ++v) acc_add(a, tab->plane[v], (double)F[(size_t)v * cells + c]);
+    const double nn = a.s0, ux = a.sx / nn, uy = a.sy / nn;
+    if (D == 2) {
+        M[c] = nn;
+        M[cells + c] = ux;
+        M[2 * cells + c] = uy;
+        M[3 * cells + c] = (a.se - nn * (ux * ux + uy * uy)) / (dk * nn);
+    } else {
+        M[c] = nn;
+        M[cells + c] = ux;
+        M[2 * cells + c] = (a.se - nn * ux * ux) / (dk * nn);
+    }
+}
+
+// Block-level sum of mass, momentum and total energy, fixed reduction order.
+template <int D>
+__global__ void __launch_bounds__(256) sums_kernel(const double* __restrict__ M, long long cells,
+                                                   double dk, double* partial) {
+    __shared__ double red[4][256];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    const long long per = (cells + gridDim.x - 1) / gridDim.x;
+    const long long beg = (long long)blockIdx.x * per;
+    const long long end = beg + per < cells ? beg + per : cells;
+    for (long long c = beg + threadIdx.x; c < end; c += blockDim.x) {
+        const double n = M[c], ux = M[cells + c];
+        const double uy = D == 2 ? M[2 * cells + c] : 0.0;
+        const double T = M[(D + 1) * cells + c];
+        s[0] += n;
+        s[1] += n * ux;
+        s[2] += n * uy;
+        s[3] += 0.5 * dk * n * T + 0.5 * n * (ux * ux + uy * uy);
+    }
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) sums_final_kernel(const double* partial, int nblocks, double* out) {
+    __shared__ double red[4][256];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int k = 0; k < 4; ++k) s[k] += partial[b * 4 + k];
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) check_kernel(const double* __restrict__ M, long long cells, int* flag) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    bool bad = false;
+    for (int f = 0; f < D + 2; ++f) bad |= !isfinite(M[f * cells + c]);
+    bad |= !(M[c] > 0.0) || !(M[(D + 1) * cells + c] > 0.0);
+    if (bad) atomicOr(flag, 1);
+}
+
+template <typename S, int KIND>
+hipError_t launch_stage_t(int d, const StageArgs& a, hipStream_t s) {
+    const int ntiles = d == 2 ? a.ntx * a.nty : a.ntx;
+    const int grid = 8 * ((ntiles + 7) / 8);
+    if (d == 2)
+        hipLaunchKernelGGL((stage2d_kernel<S, KIND>), dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((stage1d_kernel<S, KIND>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stage(int d, bool f32, int kind, const StageArgs& a, hipStream_t s) {
+    switch (kind) {
+        case kAdvect: return f32 ? launch_stage_t<float, kAdvect>(d, a, s) : launch_stage_t<double, kAdvect>(d, a, s);
+        case kStage3: return f32 ? launch_stage_t<float, kStage3>(d, a, s) : launch_stage_t<double, kStage3>(d, a, s);
+        case kStage4: return f32 ? launch_stage_t<float, kStage4>(d, a, s) : launch_stage_t<double, kStage4>(d, a, s);
+        case kStage5: return f32 ? launch_stage_t<float, kStage5>(d, a, s) : launch_stage_t<double, kStage5>(d, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_init_equilibrium(int d, bool f32, const DevTables* tab, const double* n,
+                                   const double* ux, const double* uy, const double* T,
+                                   void* F, double* M, long long cells, double chi_fac,
+                                   hipStream_t s) {
+    (void)M;
+    const int grid = (int)((cells + 255) / 256);
+    if (d == 2) {
+        if (f32) hipLaunchKernelGGL((init_eq_kernel<float, 2>), dim3(grid), dim3(256), 0, s, tab, n, ux, uy, T, (float*)F, cells, chi_fac);
+        else hipLaunchKernelGGL((init_eq_kernel<double, 2>), dim3(grid), dim3(256), 0, s, tab, n, ux, uy, T, (double*)F, cells, chi_fac);
+    } else {
+        if (f32) hipLaunchKernelGGL((init_eq_kernel<float, 1>), dim3(grid), dim3(256), 0, s, tab, n, ux, uy, T, (float*)F, cells, chi_fac);
+        else hipLaunchKernelGGL((init_eq_kernel<double, 1>), dim3(grid), dim3(256), 0, s, tab, n, ux, uy, T, (double*)F, cells, chi_fac);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int d, bool f32, const DevTables* tab, const void* F, double* M,
+                          long long cells, double dk, hipStream_t s) {
+    const int grid = (int)((cells + 255) / 256);
+    if (d == 2) {
+        if (f32) hipLaunchKernelGGL((moments_kernel<float, 2>), dim3(grid), dim3(256), 0, s, tab, (const float*)F, M, cells, dk);
+        else hipLaunchKernelGGL((moments_kernel<double, 2>), dim3(grid), dim3(256), 0, s, tab, (const double*)F, M, cells, dk);
+    } else {
+        if (f32) hipLaunchKernelGGL((moments_kernel<float, 1>), dim3(grid), dim3(256), 0, s, tab, (const float*)F, M, cells, dk);
+        else hipLaunchKernelGGL((moments_kernel<double, 1>), dim3(grid), dim3(256), 0, s, tab, (const double*)F, M, cells, dk);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_domain_sums(int d, const double* M, long long cells, double dk,
+                              double* partial, int nblocks, double* out4, hipStream_t s) {
+    if (d == 2) hipLaunchKernelGGL((sums_kernel<2>), dim3(nblocks), dim3(256), 0, s, M, cells, dk, partial);
+    else hipLaunchKernelGGL((sums_kernel<1>), dim3(nblocks), dim3(256), 0, s, M, cells, dk, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sums_final_kernel, dim3(1), dim3(256), 0, s, partial, nblocks, out4);
+    return hipGetLastError();
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+hipError_t launch_check(int d, const double* M, long long cells, int* flag, hipStream_t s) {
+    const int grid = (int)((cells + 255) / 256);
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, flag);
+    if (d == 2) hipLaunchKernelGGL((check_kernel<2>), dim3(grid), dim3(256), 0, s, M, cells, flag);
+    else hipLaunchKernelGGL((check_kernel<1>), dim3(grid), dim3(256), 0, s, M, cells, flag);
+    return hipGetLastError();
+}
+
+}  // namespace imexlb

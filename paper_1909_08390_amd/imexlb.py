@@ -1,0 +1,254 @@
+"""ctypes binding of ``libimexlb.so`` (the HIP library for gfx950).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides the device memory (caller-owned state and
+workspace tensors) and the stream.  If the library has not been built the
+import of :func:`lib` fails loudly; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libimexlb.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENONPHYS, ESTATE = 0, -1, -2, -3, -4, -5
+OUTFLOW, PERIODIC = 0, 1
+F64, F32 = 0, 1
+
+
+class CConfig(ctypes.Structure):
+    """Mirror of ``imexlb_config``."""
+    _fields_ = [("d", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("q_phi", ctypes.c_int), ("q_chi", ctypes.c_int), ("K", ctypes.c_int),
+                ("tau", ctypes.c_double), ("dt", ctypes.c_double),
+                ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("storage", ctypes.c_int)]
+
+
+class ImexlbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"imexlb status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1909_08390_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.imexlb_create.argtypes = [ctypes.POINTER(CConfig), _vp, ctypes.POINTER(_vp)]
+        L.imexlb_destroy.argtypes = [_vp]
+        L.imexlb_destroy.restype = None
+        L.imexlb_set_stream.argtypes = [_vp, _vp]
+        L.imexlb_state_bytes.argtypes = [_vp]
+        L.imexlb_state_bytes.restype = ctypes.c_size_t
+        L.imexlb_workspace_bytes.argtypes = [_vp]
+        L.imexlb_workspace_bytes.restype = ctypes.c_size_t
+        L.imexlb_num_planes.argtypes = [_vp]
+        L.imexlb_bind.argtypes = [_vp, _vp, _vp]
+        L.imexlb_quadrature.argtypes = [_vp, _dp, _dp, _dp, _dp]
+        L.imexlb_set_equilibrium.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.imexlb_set_state.argtypes = [_vp, _vp]
+        L.imexlb_get_state.argtypes = [_vp, _vp]
+        L.imexlb_step.argtypes = [_vp, ctypes.c_int]
+        L.imexlb_step_timed.argtypes = [_vp, ctypes.c_int, _dp]
+        L.imexlb_moments.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.imexlb_compute_moments.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.imexlb_advect.argtypes = [_vp, _vp, _vp]
+        L.imexlb_domain_sums.argtypes = [_vp, _dp]
+        L.imexlb_check_state.argtypes = [_vp]
+        L.imexlb_status_string.argtypes = [ctypes.c_int]
+        L.imexlb_status_string.restype = ctypes.c_char_p
+        L.imexlb_last_error.argtypes = [_vp]
+        L.imexlb_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+@dataclass
+class Config:
+    """Problem definition (mirrors ``imexlb_config``)."""
+    d: int
+    nx: int
+    ny: int = 1
+    lx: float = 1.0
+    ly: float = 1.0
+    q_phi: int = 5
+    q_chi: int = 3
+    K: int = 2
+    tau: float = 1e-5
+    dt: float = 1e-4
+    bc_x: int = OUTFLOW
+    bc_y: int = OUTFLOW
+    storage: int = F64
+
+    def c(self) -> CConfig:
+        return CConfig(self.d, self.nx, self.ny, self.lx, self.ly,
+                       self.q_phi, self.q_chi, self.K, self.tau, self.dt, self.bc_x,
+                       self.bc_y, self.storage)
+
+    @property
+    def planes(self) -> int:
+        return self.q_phi ** self.d + self.q_chi ** self.d
+
+    @property
+    def cells(self) -> int:
+        return self.nx * (self.ny if self.d == 2 else 1)
+
+    @property
+    def shape(self):
+        return (self.planes, self.ny, self.nx) if self.d == 2 else (self.planes, self.nx)
+
+    @property
+    def field_shape(self):
+        return (self.ny, self.nx) if self.d == 2 else (self.nx,)
+
+
+def validate(cfg: Config) -> int:
+    """Status of ``imexlb_create`` for cfg when it is rejected before any
+    device work (EINVAL), else creates and destroys a context."""
+    L = lib()
+    h = _vp()
+    c = cfg.c()
+    st = L.imexlb_create(ctypes.byref(c), None, ctypes.byref(h))
+    if st == OK:
+        L.imexlb_destroy(h)
+    return st
+
+
+class Solver:
+    """One context bound to caller-owned torch device buffers."""
+
+    def __init__(self, cfg: Config, device="cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.L = lib()
+        self._h = _vp()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device)
+            c = cfg.c()
+            self._check(self.L.imexlb_create(ctypes.byref(c), _vp(stream.cuda_stream),
+                                             ctypes.byref(self._h)), "create")
+            self.stream = stream
+            sdt = torch.float32 if cfg.storage == F32 else torch.float64
+            self.state_dtype = sdt
+            self.state = torch.empty(cfg.shape, dtype=sdt, device=self.device)
+            assert self.state.numel() * self.state.element_size() == \
+                self.L.imexlb_state_bytes(self._h)
+            wb = self.L.imexlb_workspace_bytes(self._h)
+            self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
+            self._check(self.L.imexlb_bind(self._h, _vp(self.state.data_ptr()),
+                                           _vp(self.workspace.data_ptr())), "bind")
+
+    # ------------------------------------------------------------------ util
+    def _check(self, st: int, what: str):
+        if st != OK:
+            msg = self.L.imexlb_last_error(self._h).decode() if self._h else ""
+            base = self.L.imexlb_status_string(st).decode()
+            raise ImexlbError(st, f"{what}: {base} {msg}".strip())
+
+    def _dev64(self, a):
+        torch = self.torch
+        if a is None:
+            return None
+        t = torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+        return t.reshape(self.cfg.field_shape)
+
+    def close(self):
+        if self._h:
+            self.L.imexlb_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------- API
+    @property
+    def planes(self) -> int:
+        return self.L.imexlb_num_planes(self._h)
+
+    def quadrature(self):
+        qp, qc = self.cfg.q_phi, self.cfg.q_chi
+        pp, wp, pc, wc = (np.zeros(qp), np.zeros(qp), np.zeros(qc), np.zeros(qc))
+        self._check(self.L.imexlb_quadrature(
+            self._h, pp.ctypes.data_as(_dp), wp.ctypes.data_as(_dp),
+            pc.ctypes.data_as(_dp), wc.ctypes.data_as(_dp)), "quadrature")
+        return pp, wp, pc, wc
+
+    def set_equilibrium(self, n, ux, uy, T):
+        n, ux, T = self._dev64(n), self._dev64(ux), self._dev64(T)
+        uy = self._dev64(uy) if self.cfg.d == 2 else None
+        self._keep = (n, ux, uy, T)  # alive until the stream has used them
+        self._check(self.L.imexlb_set_equilibrium(
+            self._h, _vp(n.data_ptr()), _vp(ux.data_ptr()),
+            _vp(uy.data_ptr()) if uy is not None else None, _vp(T.data_ptr())), "set_equilibrium")
+
+    def set_state(self, F):
+        F = self.torch.as_tensor(F, dtype=self.state_dtype, device=self.device).contiguous()
+        assert tuple(F.shape) == tuple(self.cfg.shape)
+        self._keep = F
+        self._check(self.L.imexlb_set_state(self._h, _vp(F.data_ptr())), "set_state")
+
+    def step(self, nsteps: int = 1):
+        self._check(self.L.imexlb_step(self._h, int(nsteps)), "step")
+
+    def step_timed(self, nsteps: int):
+        """Step and return the summed per-pass milliseconds (stage 3, 4, 5),
+        timed with HIP events on the library's stream."""
+        ms = np.zeros(3)
+        self._check(self.L.imexlb_step_timed(self._h, int(nsteps), ms.ctypes.data_as(_dp)),
+                    "step_timed")
+        return ms
+
+    def moments(self):
+        """(n, ux, uy, T) device tensors of the current state (uy zero in 1D)."""
+        torch = self.torch
+        out = [torch.zeros(self.cfg.field_shape, dtype=torch.float64, device=self.device)
+               for _ in range(4)]
+        self._check(self.L.imexlb_moments(self._h, *[_vp(t.data_ptr()) for t in out]), "moments")
+        return tuple(out)
+
+    def compute_moments(self, F):
+        torch = self.torch
+        F = torch.as_tensor(F, dtype=self.state_dtype, device=self.device).contiguous()
+        out = [torch.zeros(self.cfg.field_shape, dtype=torch.float64, device=self.device)
+               for _ in range(4)]
+        self._check(self.L.imexlb_compute_moments(self._h, _vp(F.data_ptr()),
+                                                  *[_vp(t.data_ptr()) for t in out]),
+                    "compute_moments")
+        return tuple(out)
+
+    def advect(self, F):
+        """FP64 (p . grad) F of a plane-set (the MP-9 operator alone)."""
+        torch = self.torch
+        F = torch.as_tensor(F, dtype=self.state_dtype, device=self.device).contiguous()
+        VF = torch.empty(self.cfg.shape, dtype=torch.float64, device=self.device)
+        self._check(self.L.imexlb_advect(self._h, _vp(F.data_ptr()), _vp(VF.data_ptr())), "advect")
+        return VF
+
+    def domain_sums(self) -> np.ndarray:
+        out = np.zeros(4)
+        self._check(self.L.imexlb_domain_sums(self._h, out.ctypes.data_as(_dp)), "domain_sums")
+        return out
+
+    def check_state(self) -> int:
+        return self.L.imexlb_check_state(self._h)

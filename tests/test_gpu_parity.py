@@ -1,0 +1,284 @@
+"""GPU-vs-oracle parity of every row of the hot path, through the C ABI.
+
+Each test builds the same seeded input fields (paper_1909_08390_amd.workloads)
+for both sides: the GPU library turns them into distributions and steps them
+in its HIP kernels, the FP64 CPU oracle does the same from the paper.  The
+FP64 tolerance is 1e-12 of the reference's infinity norm (velocities in units
+of c_ref: 1e-12 absolute); see the design notes for the derivation.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1909_08390_amd import imexlb as I
+from paper_1909_08390_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def ocfg(c: I.Config) -> O.Config:
+    return O.Config(d=c.d, nx=c.nx, ny=c.ny, lx=c.lx, ly=c.ly, q_phi=c.q_phi, q_chi=c.q_chi,
+                    K=c.K, tau=c.tau, dt=c.dt, bc_x=c.bc_x, bc_y=c.bc_y)
+
+
+def assert_close_inf(got, ref, tol=TOL, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = max(np.abs(ref).max(), 1e-300)
+    err = np.abs(got - ref).max()
+    assert err <= tol * scale, f"{what}: max err {err:.3e} vs {tol:.1e} * {scale:.3e}"
+
+
+def assert_moments_close(gm, om, d, tol=TOL):
+    n, ux, uy, T = [np.asarray(x.cpu() if hasattr(x, "cpu") else x) for x in gm]
+    on, oux, ouy, oT = om
+    assert_close_inf(n, on, tol, "n")
+    assert np.abs(ux - oux).max() <= tol * max(1.0, np.abs(oux).max()), "ux"
+    if d == 2:
+        assert np.abs(uy - ouy).max() <= tol * max(1.0, np.abs(ouy).max()), "uy"
+    assert_close_inf(T, oT, tol, "T")
+    assert_close_inf(n * T, on * oT, tol, "P")
+
+
+def fields_for(c: I.Config, kind: str, seed: int):
+    if kind == "smooth":
+        n, ux, uy, T = W.smooth_fields(c.field_shape, seed)
+    elif kind == "random":
+        n, ux, uy, T = W.random_fields(c.field_shape, seed)
+    elif kind == "sod":
+        n, ux, T = W.sod_1d(c.nx)
+        uy = np.zeros_like(n)
+    elif kind == "riemann":
+        st, _ = W.quadrant_states(seed)
+        n, ux, uy, T = W.riemann_2d(c.nx, c.ny, st)
+    else:
+        raise ValueError(kind)
+    return n, ux, uy, T
+
+
+# ---------------------------------------------------------------- row a1
+@pytest.mark.parametrize("qp,qc", [(3, 1), (5, 3), (8, 8), (16, 16), (12, 7)])
+def test_quadrature_matches_oracle(qp, qc):
+    _torch()
+    s = I.Solver(I.Config(d=1, nx=8, q_phi=qp, q_chi=qc, dt=1e-5))
+    pp, wp, pc, wc = s.quadrature()
+    op, ow = O.gauss_hermite(qp)
+    np.testing.assert_allclose(pp, op, rtol=0, atol=1e-14 * max(1, np.abs(op).max()))
+    np.testing.assert_allclose(wp, ow, rtol=1e-13, atol=1e-300)
+    op, ow = O.gauss_hermite(qc)
+    np.testing.assert_allclose(pc, op, rtol=0, atol=1e-14 * max(1, np.abs(op).max()))
+    np.testing.assert_allclose(wc, ow, rtol=1e-13, atol=1e-300)
+
+
+# ---------------------------------------------------------- rows a2, a3
+EQ_CASES = [
+    dict(d=1, nx=1500, q_phi=5, q_chi=3, K=2),
+    dict(d=1, nx=333, q_phi=16, q_chi=16, K=0),
+    dict(d=2, nx=70, ny=37, q_phi=8, q_chi=8, K=2),
+    dict(d=2, nx=19, ny=23, q_phi=5, q_chi=3, K=2),
+]
+
+
+@pytest.mark.parametrize("case", EQ_CASES)
+def test_equilibrium_and_moments_match_oracle(case):
+    _torch()
+    c = I.Config(dt=1e-6, **case)
+    s = I.Solver(c)
+    n, ux, uy, T = fields_for(c, "random", 3)
+    s.set_equilibrium(n, ux, uy, T)
+    oc = ocfg(c)
+    ref = O.equilibrium(oc, n, ux, uy if c.d == 2 else None, T)
+    assert_close_inf(s.state.cpu().numpy(), ref, what="equilibrium")
+    assert_moments_close(s.moments(), O.moments(oc, ref), c.d)
+    # the moment reduction alone on a non-equilibrium plane-set
+    rng = np.random.default_rng(5)
+    G = ref * (1.0 + 0.05 * rng.standard_normal(ref.shape))
+    assert_moments_close(s.compute_moments(G), O.moments(oc, G), c.d)
+
+
+# ---------------------------------------------------------- rows a5, a6
+ADV_CASES = [
+    dict(d=1, nx=2500, q_phi=5, q_chi=3, bc_x=I.OUTFLOW),
+    dict(d=1, nx=1031, q_phi=8, q_chi=8, bc_x=I.PERIODIC),
+    dict(d=1, nx=7, q_phi=4, q_chi=3, bc_x=I.PERIODIC),
+    dict(d=2, nx=150, ny=40, q_phi=4, q_chi=3, bc_x=I.OUTFLOW, bc_y=I.PERIODIC),
+    dict(d=2, nx=64, ny=16, q_phi=5, q_chi=3, bc_x=I.PERIODIC, bc_y=I.OUTFLOW),
+    dict(d=2, nx=131, ny=77, q_phi=8, q_chi=8, bc_x=I.OUTFLOW, bc_y=I.OUTFLOW),
+    dict(d=2, nx=3, ny=5, q_phi=3, q_chi=2, bc_x=I.PERIODIC, bc_y=I.PERIODIC),
+]
+
+
+@pytest.mark.parametrize("case", ADV_CASES)
+@pytest.mark.parametrize("data", ["random", "smooth", "steps"])
+def test_mp9_advection_matches_oracle(case, data):
+    _torch()
+    c = I.Config(dt=1e-6, **case)
+    s = I.Solver(c)
+    rng = np.random.default_rng(11)
+    if data == "random":
+        F = rng.uniform(-1.0, 1.0, c.shape)
+    elif data == "smooth":
+        n, ux, uy, T = fields_for(c, "smooth", 2)
+        F = O.equilibrium(ocfg(c), n, ux, uy if c.d == 2 else None, T)
+    else:  # piecewise constant with jumps: exercises the limiter
+        F = np.round(rng.uniform(0, 3, c.shape)) * 0.5
+        F = np.repeat(F[..., ::3], 3, axis=-1)[..., :c.nx].copy()
+    VF = s.advect(F).cpu().numpy()
+    ref = O.advect(ocfg(c), F)
+    assert_close_inf(VF, ref, what=f"advect {data}")
+
+
+# --------------------------------------------------------- rows a4, a7-a9
+STEP_CASES = [
+    # Sod tube of the paper's Sec. V (Q_phi = 5, Q_chi = 3, tau = 1e-5)
+    (dict(d=1, nx=400, q_phi=5, q_chi=3, K=2, tau=1e-5, dt=2.5e-4), "sod", 40),
+    (dict(d=1, nx=2100, q_phi=8, q_chi=8, K=0, tau=1e-3, dt=5e-5, bc_x=I.PERIODIC), "smooth", 3),
+    (dict(d=1, nx=1500, q_phi=6, q_chi=4, K=2, tau=2e-4, dt=1e-4), "random", 3),
+    (dict(d=2, nx=130, ny=70, q_phi=8, q_chi=8, K=2, tau=1e-6, dt=0.5 / 130 / 4.1445),
+     "riemann", 2),
+    (dict(d=2, nx=97, ny=45, q_phi=5, q_chi=3, K=2, tau=1e-4, dt=1e-3, bc_x=I.PERIODIC,
+          bc_y=I.PERIODIC), "smooth", 3),
+    (dict(d=2, nx=70, ny=33, q_phi=4, q_chi=2, K=0, tau=1e-3, dt=1e-3, bc_x=I.OUTFLOW,
+          bc_y=I.PERIODIC), "random", 3),
+]
+
+
+@pytest.mark.parametrize("case,data,steps", STEP_CASES)
+def test_imex_step_matches_oracle(case, data, steps):
+    _torch()
+    c = I.Config(**case)
+    s = I.Solver(c)
+    n, ux, uy, T = fields_for(c, data, 1)
+    s.set_equilibrium(n, ux, uy, T)
+    oc = ocfg(c)
+    F0 = O.equilibrium(oc, n, ux, uy if c.d == 2 else None, T)
+    s.step(steps)
+    ref = O.step(oc, F0, steps)
+    assert_close_inf(s.state.cpu().numpy(), ref, what="state")
+    assert_moments_close(s.moments(), O.moments(oc, ref), c.d)
+
+
+@pytest.mark.slow
+def test_sod_full_run_matches_oracle():
+    """The paper's Sod setup run to t = 0.1 (400 steps of 2.5e-4)."""
+    _torch()
+    c = I.Config(d=1, nx=400, q_phi=5, q_chi=3, K=2, tau=1e-5, dt=2.5e-4)
+    s = I.Solver(c)
+    n, ux, T = W.sod_1d(400)
+    s.set_equilibrium(n, ux, None, T)
+    s.step(400)
+    oc = ocfg(c)
+    ref = O.step(oc, O.equilibrium(oc, n, ux, None, T), 400)
+    assert_close_inf(s.state.cpu().numpy(), ref, what="state")
+    assert_moments_close(s.moments(), O.moments(oc, ref), 1)
+
+
+# ------------------------------------------------------------ row a10
+@pytest.mark.parametrize("d", [1, 2])
+def test_fp32_storage_close_to_fp64(d):
+    """FP32 planes with FP64 moments and equilibria: relative L1 of rho, u, P
+    against the FP64 GPU run stays below 1e-5 after 20 steps (bound stated in
+    the design notes)."""
+    _torch()
+    if d == 1:
+        base = dict(d=1, nx=800, q_phi=8, q_chi=8, K=2, tau=1e-5, dt=0.5 / 800 / 4.1445)
+        n, ux, T = W.sod_1d(800)
+        uy = None
+    else:
+        base = dict(d=2, nx=128, ny=96, q_phi=8, q_chi=8, K=2, tau=1e-6, dt=0.5 / 128 / 4.1445)
+        st, _ = W.quadrant_states(0)
+        n, ux, uy, T = W.riemann_2d(128, 96, st)
+    out = {}
+    for stg in (I.F64, I.F32):
+        s = I.Solver(I.Config(storage=stg, **base))
+        s.set_equilibrium(n, ux, uy, T)
+        s.step(20)
+        out[stg] = [x.cpu().numpy() for x in s.moments()]
+    r64, r32 = out[I.F64], out[I.F32]
+    rel = lambda a, b: np.abs(a - b).sum() / np.abs(b).sum()
+    assert rel(r32[0], r64[0]) < 1e-5
+    assert np.abs(r32[1] - r64[1]).mean() < 1e-5
+    assert rel(r32[0] * r32[3], r64[0] * r64[3]) < 1e-5
+
+
+# ------------------------------------------------------------ row a11
+def test_domain_sums_and_periodic_conservation():
+    _torch()
+    c = I.Config(d=2, nx=192, ny=80, q_phi=6, q_chi=4, K=2, tau=1e-4, dt=5e-4,
+                 bc_x=I.PERIODIC, bc_y=I.PERIODIC)
+    s = I.Solver(c)
+    n, ux, uy, T = W.smooth_fields(c.field_shape, 4)
+    s.set_equilibrium(n, ux, uy, T)
+    sums0 = s.domain_sums()
+    ref = np.array([n.sum(), (n * ux).sum(), (n * uy).sum(),
+                    (2.5 * n * T + 0.5 * n * (ux ** 2 + uy ** 2)).sum()])
+    np.testing.assert_allclose(sums0, ref, rtol=1e-12, atol=1e-10)
+    s.step(50)
+    sums1 = s.domain_sums()
+    np.testing.assert_allclose(sums1, sums0, rtol=0, atol=1e-12 * np.abs(sums0).max())
+
+
+def test_check_state_flags_nonphysical_input():
+    _torch()
+    c = I.Config(d=1, nx=64, q_phi=5, q_chi=3, dt=1e-4)
+    s = I.Solver(c)
+    n, ux, T = W.sod_1d(64)
+    s.set_equilibrium(n, ux, None, T)
+    assert s.check_state() == I.OK
+    F = s.state.clone()
+    F[:, 10] = -1.0  # negative density at one cell
+    s.set_state(F)
+    assert s.check_state() == I.ENONPHYS
+    F[:, 10] = float("nan")
+    s.set_state(F)
+    assert s.check_state() == I.ENONPHYS
+
+
+def test_step_before_state_is_an_error():
+    _torch()
+    s = I.Solver(I.Config(d=1, nx=64, q_phi=5, q_chi=3, dt=1e-4))
+    with pytest.raises(I.ImexlbError) as e:
+        s.step(1)
+    assert e.value.status == I.ESTATE
+
+
+def test_run_to_run_bitwise_deterministic():
+    _torch()
+    c = I.Config(d=2, nx=150, ny=70, q_phi=8, q_chi=8, K=2, tau=1e-6, dt=0.5 / 150 / 4.1445)
+    st, _ = W.quadrant_states(0)
+    n, ux, uy, T = W.riemann_2d(150, 70, st)
+    outs = []
+    for _ in range(2):
+        s = I.Solver(c)
+        s.set_equilibrium(n, ux, uy, T)
+        s.step(3)
+        outs.append(s.state.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_uniform_state_is_fixed_point_at_full_size():
+    """4096^2 x 128 planes, FP32 storage: a uniform equilibrium is unchanged
+    to the FP32 rounding of the stored values (property at any size)."""
+    torch = _torch()
+    c = I.Config(d=2, nx=4096, ny=4096, q_phi=8, q_chi=8, K=2, tau=1e-7, dt=2.9453e-5,
+                 storage=I.F32)
+    s = I.Solver(c)
+    shape = c.field_shape
+    s.set_equilibrium(torch.full(shape, 0.9, dtype=torch.float64),
+                      torch.full(shape, 0.2, dtype=torch.float64),
+                      torch.full(shape, -0.1, dtype=torch.float64),
+                      torch.full(shape, 1.1, dtype=torch.float64))
+    F0 = s.state.clone()
+    s.step(1)
+    err = (s.state - F0).abs().max().item()
+    assert err <= 4e-7 * F0.abs().max().item()
+    del s, F0
+    torch.cuda.empty_cache()
