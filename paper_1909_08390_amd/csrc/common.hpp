@@ -22,15 +22,55 @@ struct PlaneDesc {
     int pad;
 };
 
+// Layout of the even/odd Horner coefficients of one node for a padded order
+// QM (8 or 16).  The one-axis equilibrium factor of Eq. (gExpanded),
+//   g_k(u, T) = w_k sum_{l<Q} He_l(p_k)/l! sum_s l!/(2^s s!(l-2s)!) (T-1)^s u^(l-2s),
+// regrouped by powers th^s (th = T - 1) and u^j (j = l - 2s), has the
+// coefficients B_k[s][j] = w_k He_{j+2s}(p_k) / (2^s s! j!) for j + 2s < Q.
+// Splitting each u-polynomial into even and odd parts, g = Ge(u^2) + u Go(u^2),
+// gives the factor of the mirrored node p = -p_k as Ge - u Go for free.
+// Per s (from 0): the even coefficients j = 0, 2, .. then the odd j = 1, 3, ..
+template <int QM>
+struct HornerLayout {
+    static constexpr int S = (QM - 1) / 2;
+    static constexpr int ne(int s) { return (QM - 1 - 2 * s) / 2 + 1; }
+    static constexpr int no(int s) { return (QM - 2 - 2 * s) >= 0 ? (QM - 2 - 2 * s) / 2 + 1 : 0; }
+    static constexpr int off(int s) {
+        int o = 0;
+        for (int t = 0; t < s; ++t) o += ne(t) + no(t);
+        return o;
+    }
+    static constexpr int total() { return off(S + 1); }
+};
+
+// One entry of the plane processing order of the 2D stage passes: planes
+// run set by set, ky-major, with each x-node followed by its mirror so that
+// one Horner evaluation serves both.
+struct PlaneStep {
+    double px, py;            // velocity of the plane
+    double m0, mx, my, me;    // moment weights (as in PlaneDesc)
+    int v;                    // plane index in the state layout
+    int set;                  // 0 = phi, 1 = chi
+    int kx, ky;               // node indices
+    int hx;                   // node whose Horner row evaluates (kx, mirror)
+    int first;                // 1: evaluate the pair now; 0: use the cached mirror
+    int mirror_is_next;       // 1 when the next step is kx's mirror (cache it)
+    int new_group;            // 1: ky (or the set) changed -> recompute the y factor
+};
+
 // Constant tables of one context, in device memory.
 struct DevTables {
     // h[set][k][l] = w_k He_l(p_k) / l!  (zero for l >= Q_set), so that the
     // one-axis equilibrium factor of Eq. (gExpanded) is g_k = sum_l h[k][l] a_l
     // with the Hermite coefficients a_l(u, T) of the local Maxwellian.
     double h[2][kQMax][kQMax];
+    // Even/odd Horner coefficients per set and node (HornerLayout<8> and <16>).
+    double hc8[2][kQMax][HornerLayout<8>::total()];
+    double hc16[2][kQMax][HornerLayout<16>::total()];
     int q[2];                 // Q_phi, Q_chi
     int nplanes, nphi;
     PlaneDesc plane[kMaxPlanes];
+    PlaneStep order[kMaxPlanes];
 };
 
 enum Kind : int { kAdvect = 0, kStage3 = 3, kStage4 = 4, kStage5 = 5 };
@@ -45,7 +85,7 @@ struct StageArgs {
     const double* mn;      // moments of F^n (stage 4)
     const DevTables* tab;
     int nx, ny, bcx, bcy;
-    int ntx, nty, tiles_per_xcd, pad0;
+    int ntx, nty, tiles_per_xcd, qm;  // qm: padded Horner order (8 or 16)
     long long plane_stride;  // cells per plane
     double inv_dx, inv_dy;
     double dt, omega;
@@ -67,8 +107,19 @@ hipError_t launch_domain_sums(int d, const double* M, long long cells, double dk
                               double* partial, int nblocks, double* out4, hipStream_t s);
 hipError_t launch_check(int d, const double* M, long long cells, int* flag, hipStream_t s);
 
-// Tile shapes (cells) used by the stage kernels.
-constexpr int kTile2X = 64, kTile2Y = 16;
+// Tile shapes (cells) used by the stage kernels: 2D tiles of 64 x kTile2Y
+// cells, kOwn2 consecutive cells per thread (64 kTile2Y / kOwn2 threads).
+#ifndef IMEXLB_TILE2Y
+#define IMEXLB_TILE2Y 16
+#endif
+#ifndef IMEXLB_OWN2
+#define IMEXLB_OWN2 2
+#endif
+constexpr int kTile2X = 64, kTile2Y = IMEXLB_TILE2Y;
+constexpr int kOwn2 = IMEXLB_OWN2;
 constexpr int kTile1X = 1024;
+// Tiles are visited in column bands of this many tiles (2D blocking of the
+// work that runs concurrently on one XCD, so halos hit that XCD's L2).
+constexpr int kBand = 8;
 
 }  // namespace imexlb

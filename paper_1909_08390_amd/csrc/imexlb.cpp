@@ -175,6 +175,7 @@ StageArgs base_args(const imexlb_ctx* c) {
         a.nty = 1;
     }
     a.tiles_per_xcd = (a.ntx * a.nty + 7) / 8;
+    a.qm = (k.q_phi <= 8 && k.q_chi <= 8) ? 8 : 16;
     a.plane_stride = c->cells;
     a.inv_dx = k.nx / k.lx;
     a.inv_dy = k.d == 2 ? k.ny / k.ly : 0.0;
@@ -260,8 +261,60 @@ imexlb_status imexlb_create(const imexlb_config* cfg, void* hip_stream, imexlb_c
             }
         }
     }
+    // Even/odd Horner rows: B_k[s][j] = w_k He_{j+2s}(p_k) / (2^s s! j!) for
+    // j + 2s < Q (the regrouped double sum of Eq. gExpanded), zero beyond.
+    auto horner_row = [&](int s, int k, int QM, double* row) {
+        const int S = (QM - 1) / 2;
+        int o = 0;
+        for (int ss = 0; ss <= S; ++ss) {
+            for (int par = 0; par < 2; ++par)
+                for (int j = par; j <= QM - 1 - 2 * ss; j += 2) {
+                    double val = 0.0;
+                    if (j + 2 * ss < Q[s]) {
+                        long double den = 1.0L;
+                        for (int i = 1; i <= ss; ++i) den *= 2.0L * (long double)i;  // 2^s s!
+                        for (int i = 2; i <= j; ++i) den *= (long double)i;          // j!
+                        val = (double)((long double)c->w[s][k] * he(j + 2 * ss, (long double)c->p[s][k]) / den);
+                    }
+                    row[o++] = val;
+                }
+        }
+    };
+    for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < Q[s]; ++k) {
+            horner_row(s, k, 8, t->hc8[s][k]);
+            horner_row(s, k, 16, t->hc16[s][k]);
+        }
     t->nplanes = c->nplanes;
     t->nphi = c->nphi;
+    {   // processing order of the 2D passes: per set, ky-major; each x-node
+        // followed by its mirror (one Horner evaluation gives both factors)
+        int j = 0;
+        for (int s = 0; s < 2; ++s) {
+            const int base = s ? c->nphi : 0;
+            const int nyg = d == 2 ? Q[s] : 1;
+            for (int ky = 0; ky < nyg; ++ky) {
+                bool group_start = true;
+                for (int k = 0; k < (Q[s] + 1) / 2; ++k) {
+                    const int pair[2] = {k, Q[s] - 1 - k};
+                    const int cnt = pair[0] == pair[1] ? 1 : 2;
+                    for (int e = 0; e < cnt; ++e, ++j) {
+                        PlaneStep& st = t->order[j];
+                        const int kx = pair[e];
+                        st.v = base + kx + Q[s] * ky;
+                        st.set = s;
+                        st.kx = kx;
+                        st.ky = ky;
+                        st.hx = k;
+                        st.first = e == 0;
+                        st.mirror_is_next = cnt == 2 && e == 0;
+                        st.new_group = group_start;
+                        group_start = false;
+                    }
+                }
+            }
+        }
+    }
     int v = 0;
     for (int s = 0; s < 2; ++s) {
         const int ny_ = d == 2 ? Q[s] : 1;
@@ -283,6 +336,16 @@ imexlb_status imexlb_create(const imexlb_config* cfg, void* hip_stream, imexlb_c
                     pd.me = 1.0;
                 }
             }
+    }
+    for (int j = 0; j < c->nplanes; ++j) {
+        PlaneStep& st = t->order[j];
+        const PlaneDesc& pd = t->plane[st.v];
+        st.px = pd.px;
+        st.py = pd.py;
+        st.m0 = pd.m0;
+        st.mx = pd.mx;
+        st.my = pd.my;
+        st.me = pd.me;
     }
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_tab, sizeof(DevTables));

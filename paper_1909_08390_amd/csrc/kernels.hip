@@ -29,6 +29,12 @@
 namespace imexlb {
 namespace {
 
+// Tables are read through the constant address space so that uniform
+// accesses become scalar loads.
+#define IMEXLB_CONST __attribute__((address_space(4)))
+typedef const DevTables IMEXLB_CONST CTab;
+typedef const double IMEXLB_CONST* CDp;
+
 // Table I constants.
 constexpr double kAlpha = 0.24169426078821;
 constexpr double kBeta = 0.06042356519705;
@@ -49,7 +55,7 @@ __device__ __forceinline__ int bc_map(int i, int n, int bc) {
 // g_k = w_k sum_l He_l(p_k)/l! a_l with a_l = sum_s l!/(2^s s!(l-2s)!) (T-1)^s u^(l-2s).
 // The a_l satisfy a_0 = 1, a_1 = u, a_{l+1} = u a_l + l (T-1) a_{l-1}
 // (they are E[He_l(X)] for X ~ N(u, T)); h[l] = w_k He_l(p_k)/l! is tabulated.
-__device__ __forceinline__ double herm_factor(const double* __restrict__ h, int Q, double u,
+__device__ __forceinline__ double herm_factor(CDp h, int Q, double u,
                                               double th) {
     double am = 1.0, ac = u;
     double g = fma(h[1], u, h[0]);
@@ -174,12 +180,44 @@ __device__ __forceinline__ void store4(S* p, const S (&o)[4]) {
     *reinterpret_cast<typename Vec4<S>::T*>(p) = v;
 }
 
+// N consecutive elements (N = 2 or 4) as one vector access.
+template <typename S, int N>
+struct VecN;
+template <> struct VecN<double, 2> { using T = double2; };
+template <> struct VecN<float, 2> { using T = float2; };
+template <> struct VecN<double, 4> { using T = double4; };
+template <> struct VecN<float, 4> { using T = float4; };
+
+template <typename S, int N>
+__device__ __forceinline__ void loadN(const S* p, double* o) {
+    const typename VecN<S, N>::T v = *reinterpret_cast<const typename VecN<S, N>::T*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    if constexpr (N == 4) {
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+}
+
+template <typename S, int N>
+__device__ __forceinline__ void storeN(S* p, const S* o) {
+    typename VecN<S, N>::T v;
+    v.x = o[0];
+    v.y = o[1];
+    if constexpr (N == 4) {
+        v.z = o[2];
+        v.w = o[3];
+    }
+    *reinterpret_cast<typename VecN<S, N>::T*>(p) = v;
+}
+
 // Moments accumulated per cell in FP64 (Sec. II, Eq. Moments_discrete).
 struct Acc {
     double s0, sx, sy, se;
 };
 
-__device__ __forceinline__ void acc_add(Acc& a, const PlaneDesc& pd, double f) {
+template <typename PD>
+__device__ __forceinline__ void acc_add(Acc& a, const PD& pd, double f) {
     a.s0 = fma(pd.m0, f, a.s0);
     a.sx = fma(pd.mx, f, a.sx);
     a.sy = fma(pd.my, f, a.sy);
@@ -187,48 +225,122 @@ __device__ __forceinline__ void acc_add(Acc& a, const PlaneDesc& pd, double f) {
 }
 
 // ---------------------------------------------------------------------------
-// Two-dimensional stage pass.  Tile TX x TY cells, 256 threads.  Thread t owns
-// the 4 consecutive cells (4 seg .. 4 seg + 3, row) with seg = t % 16,
-// row = t / 16, sweeps them along x, and sweeps the 4-cell column segment
-// (column t % 64, rows 4 (t / 64) ..) along y for the y-part of V.
+// One-axis equilibrium factors of node k and of its mirror -p_k from the
+// even/odd Horner table row c (HornerLayout<QM>): g = Ge + u Go, gm = Ge - u Go.
 // ---------------------------------------------------------------------------
-template <typename S, int KIND>
-__global__ void __launch_bounds__(256) stage2d_kernel(StageArgs a) {
-    constexpr int TX = kTile2X, TY = kTile2Y, NT = 256, L = 4;
-    constexpr int SEG = TX / L;
-    constexpr int P = TX + 10;              // LDS row pitch
-    constexpr int NH = 10 * TY + 10 * TX;   // cross-shaped halo
-    constexpr int HS = (NH + NT - 1) / NT;  // halo slots per thread
-    constexpr int NS = L + HS;              // loaded cells per thread
+template <int QM>
+__device__ __forceinline__ void g_pair(CDp c, double u, double th,
+                                       double& g, double& gm) {
+    using H = HornerLayout<QM>;
+    const double v = u * u;
+    double ge = 0.0, go = 0.0;
+#pragma unroll
+    for (int s = H::S; s >= 0; --s) {
+        CDp ce = c + H::off(s);
+        double e = ce[H::ne(s) - 1];
+#pragma unroll
+        for (int i = H::ne(s) - 2; i >= 0; --i) e = fma(e, v, ce[i]);
+        double o = 0.0;
+        if (H::no(s) > 0) {
+            CDp co = ce + H::ne(s);
+            o = co[H::no(s) - 1];
+#pragma unroll
+            for (int i = H::no(s) - 2; i >= 0; --i) o = fma(o, v, co[i]);
+        }
+        ge = (s == H::S) ? e : fma(ge, th, e);
+        go = (s == H::S) ? o : fma(go, th, o);
+    }
+    g = fma(u, go, ge);
+    gm = fma(-u, go, ge);
+}
+
+__device__ __forceinline__ PlaneStep load_step(CTab* t, int j) {
+    const PlaneStep IMEXLB_CONST& r = t->order[j];
+    PlaneStep s;
+    s.px = r.px; s.py = r.py; s.m0 = r.m0; s.mx = r.mx; s.my = r.my; s.me = r.me;
+    s.v = r.v; s.set = r.set; s.kx = r.kx; s.ky = r.ky; s.hx = r.hx; s.first = r.first;
+    s.mirror_is_next = r.mirror_is_next; s.new_group = r.new_group;
+    return s;
+}
+
+__device__ __forceinline__ PlaneDesc load_desc(CTab* t, int v) {
+    const PlaneDesc IMEXLB_CONST& r = t->plane[v];
+    PlaneDesc s;
+    s.px = r.px; s.py = r.py; s.m0 = r.m0; s.mx = r.mx; s.my = r.my; s.me = r.me;
+    s.set = r.set; s.kx = r.kx; s.ky = r.ky; s.pad = 0;
+    return s;
+}
+
+template <int QM>
+__device__ __forceinline__ CDp hrow(CTab* t, int set, int k) {
+    if constexpr (QM == 8) return t->hc8[set][k];
+    else return t->hc16[set][k];
+}
+
+// Tile visiting order: column bands of kBand tiles, row-major inside a band;
+// consecutive logical indices go to one XCD (blockIdx % 8 selects the XCD).
+__device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& ty) {
+    const int ntiles = a.ntx * a.nty;
+    const int l = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
+    if (l >= ntiles) return false;
+    const int per_band = kBand * a.nty;
+    const int band = l / per_band, rem = l % per_band;
+    const int wb = min(kBand, a.ntx - band * kBand);
+    tx = band * kBand + rem % wb;
+    ty = rem / wb;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Two-dimensional stage pass.  Tile of 64 x TY cells, 16 TY threads.
+//  - own cells: thread t owns the 4 consecutive cells (4 (t % 16) .. +3) of
+//    row t / 16 (vector loads/stores, FP64 moment accumulators);
+//  - loaded cells: own cells plus the 5-cell cross halo (10 TY + 640 cells),
+//    spread over the threads; each is relaxed on read into the LDS tile;
+//  - sweeps: threads t < 8 TY slide the MP-9 window along x over 8 cells of a
+//    row, the others along y over 8 cells of a column;
+//  - per plane: fill LDS (next plane's global loads already in flight),
+//    barrier, sweeps, barrier, pointwise stage algebra + stores + moments.
+// LDS pitches are odd so the row-strided x windows and the column-strided
+// results spread over all banks.
+// ---------------------------------------------------------------------------
+template <typename S, int KIND, int QM, int TY, int OWN>
+__global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
+    constexpr int TX = 64, NT = TX * TY / OWN, L = 2 * OWN;
+    constexpr int OPR = TX / OWN;         // threads per tile row
+    constexpr int P = TX + 11;            // tile pitch (odd)
+    constexpr int VP = TX + 1;            // VF buffer pitch (odd)
+    constexpr int NH = 10 * TY + 10 * TX; // cross-shaped halo
+    constexpr int HS = (NH + NT - 1) / NT;
+    constexpr int NS = OWN + HS;
     constexpr bool RELAX = KIND != kAdvect;
-    static_assert(SEG * TY == NT && TX * (TY / L) == NT, "tile / thread mismatch");
+    static_assert(TY * (TX / L) == NT / 2 && TX * (TY / L) == NT / 2, "sweep split");
     using R = S;
 
-    __shared__ S tile[2][(TY + 10) * P];
-    __shared__ R vfy[TY * TX];
+    __shared__ S tile[(TY + 10) * P];
+    __shared__ R vfx[TY * VP];
+    __shared__ R vfy[TY * VP];
 
+    int txi, tyi;
+    if (!tile_of_block(a, txi, tyi)) return;
     const int tid = threadIdx.x;
-    const int logical = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
-    if (logical >= a.ntx * a.nty) return;
-    const int x0 = (logical % a.ntx) * TX;
-    const int y0 = (logical / a.ntx) * TY;
+    const int x0 = txi * TX, y0 = tyi * TY;
     const int nx = a.nx, ny = a.ny;
     const long long ps = a.plane_stride;
-    const DevTables* __restrict__ tab = a.tab;
+    CTab* tab = (CTab*)a.tab;
 
-    const int orow = tid / SEG, oseg = tid % SEG;
-    const int oy = y0 + orow, ox0 = x0 + oseg * L;
+    const int orow = tid / OPR, ox = (tid % OPR) * OWN;
+    const int oy = y0 + orow, ox0 = x0 + ox;
+    const bool vec = (x0 + TX <= nx) && (y0 + TY <= ny) && (nx % OWN == 0);
     const bool row_real = oy < ny;
-    const bool vec = (x0 + TX <= nx) && (y0 + TY <= ny) && (nx % 4 == 0);
 
-    int gcell[NS];
-    int lidx[NS];
+    int gcell[NS], lidx[NS];
     {
         const int gy = bc_map(oy, ny, a.bcy) * nx;
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
+        for (int i = 0; i < OWN; ++i) {
             gcell[i] = gy + bc_map(ox0 + i, nx, a.bcx);
-            lidx[i] = (orow + 5) * P + oseg * L + i + 5;
+            lidx[i] = (orow + 5) * P + ox + i + 5;
         }
 #pragma unroll
         for (int j = 0; j < HS; ++j) {
@@ -245,234 +357,259 @@ __global__ void __launch_bounds__(256) stage2d_kernel(StageArgs a) {
                 ly = k < 5 ? k : TY + k;
             }
             if (h < NH) {
-                gcell[L + j] = bc_map(y0 + ly - 5, ny, a.bcy) * nx + bc_map(x0 + lx - 5, nx, a.bcx);
-                lidx[L + j] = ly * P + lx;
+                gcell[OWN + j] = bc_map(y0 + ly - 5, ny, a.bcy) * nx + bc_map(x0 + lx - 5, nx, a.bcx);
+                lidx[OWN + j] = ly * P + lx;
             } else {
-                gcell[L + j] = -1;
-                lidx[L + j] = 0;
+                gcell[OWN + j] = -1;
+                lidx[OWN + j] = 0;
             }
         }
     }
 
-    // Per loaded cell: u_x and T - 1 of the source moments, and the plane
-    // group factor A = P_set * g_y (P_phi = n, P_chi = (K + D - d) n T).
-    double sux[NS], sth[NS], sA[NS];
+    // Per loaded cell: u_x and T - 1 of the source moments, the y factor
+    // A = P_set g_y (P_phi = n, P_chi = (K + D - d) n T) of the current group,
+    // and the cached x factor of the mirrored node.
+    double sux[NS], sth[NS], sA[NS], sgm[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         sux[s] = 0.0;
         sth[s] = 0.0;
         sA[s] = 0.0;
+        sgm[s] = 0.0;
         if (RELAX && gcell[s] >= 0) {
             sux[s] = a.msrc[ps + gcell[s]];
             sth[s] = a.msrc[3 * ps + gcell[s]] - 1.0;
         }
     }
-    // Stage 4 also needs E^n at its own cells.
-    double nux[L], nth[L], nA[L];
+    // Stage 4 also needs E^n at its own cells (moments of F^n).
+    double nux[OWN], nth[OWN], nA[OWN], ngm[OWN];
 #pragma unroll
-    for (int i = 0; i < L; ++i) {
+    for (int i = 0; i < OWN; ++i) {
         nux[i] = 0.0;
         nth[i] = 0.0;
         nA[i] = 0.0;
+        ngm[i] = 0.0;
         if (KIND == kStage4) {
             nux[i] = a.mn[ps + gcell[i]];
             nth[i] = a.mn[3 * ps + gcell[i]] - 1.0;
         }
     }
-    Acc acc[L];
+    Acc acc[OWN];
 #pragma unroll
-    for (int i = 0; i < L; ++i) acc[i] = Acc{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < OWN; ++i) acc[i] = Acc{0.0, 0.0, 0.0, 0.0};
 
-    int parity = 0;
-    for (int set = 0; set < 2; ++set) {
-        const int Q = tab->q[set];
-        const int vbase = set ? tab->nphi : 0;
-        for (int ky = 0; ky < Q; ++ky) {
-            if constexpr (RELAX) {
-                const double* hy = tab->h[set][ky];
+    // Global loads of one plane: the source plane at the loaded cells and,
+    // for stages 4 and 5, the state buffer at the own cells.
+    double pg[NS], pf[OWN];
+    auto fetch = [&](int v) {
+        const S* __restrict__ sv = static_cast<const S*>(a.src) + (size_t)v * ps;
+        if (vec) {
+            loadN<S, OWN>(sv + gcell[0], pg);
+        } else {
+#pragma unroll
+            for (int i = 0; i < OWN; ++i) pg[i] = sv[gcell[i]];
+        }
+#pragma unroll
+        for (int j = 0; j < HS; ++j) pg[OWN + j] = gcell[OWN + j] >= 0 ? (double)sv[gcell[OWN + j]] : 0.0;
+        if constexpr (KIND == kStage4 || KIND == kStage5) {
+            const S* fbp = static_cast<const S*>(a.fbuf) + (size_t)v * ps;
+            if (vec) {
+                loadN<S, OWN>(fbp + gcell[0], pf);
+            } else {
+#pragma unroll
+                for (int i = 0; i < OWN; ++i) pf[i] = fbp[gcell[i]];
+            }
+        }
+    };
+
+    const int np = tab->nplanes;
+    fetch(tab->order[0].v);
+    for (int j = 0; j < np; ++j) {
+        const PlaneStep st = load_step(tab, j);
+        const int Q = tab->q[st.set];
+        double g[NS], fb[OWN];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) g[s] = pg[s];
+#pragma unroll
+        for (int i = 0; i < OWN; ++i) fb[i] = pf[i];
+        if (j + 1 < np) fetch(tab->order[j + 1].v);
+
+        if constexpr (RELAX) {
+            if (st.new_group) {
+                CDp hy = tab->h[st.set][st.ky];
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (gcell[s] >= 0) {
                         const double n = a.msrc[gcell[s]];
                         const double uy = a.msrc[2 * ps + gcell[s]];
-                        const double pre = set ? a.chi_fac * n * (sth[s] + 1.0) : n;
+                        const double pre = st.set ? a.chi_fac * n * (sth[s] + 1.0) : n;
                         sA[s] = pre * herm_factor(hy, Q, uy, sth[s]);
                     }
                 }
                 if constexpr (KIND == kStage4) {
 #pragma unroll
-                    for (int i = 0; i < L; ++i) {
+                    for (int i = 0; i < OWN; ++i) {
                         const double n = a.mn[gcell[i]];
                         const double uy = a.mn[2 * ps + gcell[i]];
-                        const double pre = set ? a.chi_fac * n * (nth[i] + 1.0) : n;
+                        const double pre = st.set ? a.chi_fac * n * (nth[i] + 1.0) : n;
                         nA[i] = pre * herm_factor(hy, Q, uy, nth[i]);
                     }
                 }
             }
-            for (int kx = 0; kx < Q; ++kx) {
-                const int v = vbase + kx + Q * ky;
-                const PlaneDesc pd = tab->plane[v];
-                const double* hx = tab->h[set][kx];
-                const S* __restrict__ sv = static_cast<const S*>(a.src) + (size_t)v * ps;
-                S* buf = tile[parity];
-                parity ^= 1;
+        }
 
-                double gown[L], eown[L];
-                if (vec) {
-                    load4<S>(sv + gcell[0], gown);
-                } else {
+        // relax on read into the LDS tile
+        double eown[OWN], enown[OWN];
+        {
+            CDp hx = hrow<QM>(tab, st.set, st.hx);
 #pragma unroll
-                    for (int i = 0; i < L; ++i) gown[i] = sv[gcell[i]];
-                }
-                double ghalo[HS];
-#pragma unroll
-                for (int j = 0; j < HS; ++j) ghalo[j] = gcell[L + j] >= 0 ? (double)sv[gcell[L + j]] : 0.0;
-
-#pragma unroll
-                for (int i = 0; i < L; ++i) {
-                    double val = gown[i];
-                    eown[i] = 0.0;
-                    if constexpr (RELAX) {
-                        eown[i] = sA[i] * herm_factor(hx, Q, sux[i], sth[i]);
-                        val = fma(a.a_rel, gown[i], a.b_rel * eown[i]);
-                    }
-                    buf[lidx[i]] = (S)val;
-                }
-#pragma unroll
-                for (int j = 0; j < HS; ++j) {
-                    if (gcell[L + j] >= 0) {
-                        double val = ghalo[j];
-                        if constexpr (RELAX) {
-                            const double e = sA[L + j] * herm_factor(hx, Q, sux[L + j], sth[L + j]);
-                            val = fma(a.a_rel, ghalo[j], a.b_rel * e);
+            for (int s = 0; s < NS; ++s) {
+                double e = 0.0;
+                if constexpr (RELAX) {
+                    if (gcell[s] >= 0) {
+                        double gx = sgm[s];
+                        if (st.first) {
+                            double gp, gq;
+                            g_pair<QM>(hx, sux[s], sth[s], gp, gq);
+                            const bool lo = st.kx == st.hx;  // kx is the row's own node
+                            gx = lo ? gp : gq;
+                            sgm[s] = lo ? gq : gp;
                         }
-                        buf[lidx[L + j]] = (S)val;
+                        e = sA[s] * gx;
                     }
                 }
-                __syncthreads();
-
-                // x sweep of the own segment
-                R difx[L];
-#pragma unroll
-                for (int i = 0; i < L; ++i) difx[i] = R(0);
-                if (pd.px != 0.0) {
-                    const bool fwd = pd.px > 0.0;
-                    const S* base = buf + (orow + 5) * P + oseg * L + (fwd ? 0 : L + 9);
-                    const int st = fwd ? 1 : -1;
-                    R w[L + 9];
-#pragma unroll
-                    for (int m = 0; m < L + 9; ++m) w[m] = base[m * st];
-                    R dif[L];
-                    mp9_line<R, L>(w, dif);
-                    if (fwd) {
-#pragma unroll
-                        for (int i = 0; i < L; ++i) difx[i] = dif[i];
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < L; ++i) difx[i] = dif[L - 1 - i];
-                    }
-                }
-                // y sweep of column segment (c, rows L sy ..)
-                if (pd.py != 0.0) {
-                    const int c = tid % TX, sy = tid / TX;
-                    const bool fwd = pd.py > 0.0;
-                    const S* base = buf + (sy * L + (fwd ? 0 : L + 9)) * P + c + 5;
-                    const int st = fwd ? P : -P;
-                    R w[L + 9];
-#pragma unroll
-                    for (int m = 0; m < L + 9; ++m) w[m] = base[m * st];
-                    R dif[L];
-                    mp9_line<R, L>(w, dif);
-#pragma unroll
-                    for (int i = 0; i < L; ++i) {
-                        const int r = fwd ? sy * L + i : sy * L + L - 1 - i;
-                        vfy[r * TX + c] = dif[i];
-                    }
-                }
-                __syncthreads();
-
-                const double sx = fabs(pd.px) * a.inv_dx;
-                const double sy = fabs(pd.py) * a.inv_dy;
-                double vf[L];
-#pragma unroll
-                for (int i = 0; i < L; ++i) {
-                    vf[i] = (double)difx[i] * sx;
-                    if (pd.py != 0.0) vf[i] = fma((double)vfy[orow * TX + oseg * L + i], sy, vf[i]);
-                }
-
-                const size_t own0 = (size_t)v * ps + (size_t)oy * nx + ox0;
-                if constexpr (KIND == kAdvect) {
-                    double* o = static_cast<double*>(a.out) + own0;
-#pragma unroll
-                    for (int i = 0; i < L; ++i)
-                        if (row_real && ox0 + i < nx) o[i] = vf[i];
-                } else {
-                    S outv[L], fbv[L];
-                    double fb[L];
-                    if constexpr (KIND == kStage4 || KIND == kStage5) {
-                        const S* fbp = static_cast<const S*>(a.fbuf) + (size_t)v * ps;
-                        if (vec) {
-                            load4<S>(fbp + gcell[0], fb);
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < L; ++i) fb[i] = fbp[gcell[i]];
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < L; ++i) {
-                        if constexpr (KIND == kStage3) {
-                            const double fn = gown[i], en = eown[i];
-                            const double s3 = fn - a.dt * vf[i] - (1.0 - kAlpha) * a.omega * a.a2 * (fn - en);
-                            outv[i] = (S)s3;
-                        } else if constexpr (KIND == kStage4) {
-                            const double fn = fb[i];
-                            const double en = nA[i] * herm_factor(hx, Q, nux[i], nth[i]);
-                            const double g3 = gown[i], e3 = eown[i];
-                            const double dn = fn - en, d3 = g3 - e3;
-                            const double df1 = a.omega * a.a1 * dn;
-                            const double df2 = a.omega * a.a2 * dn;
-                            const double df3 = a.omega * a.a1 * d3;
-                            const double dtvf2 = fn - (1.0 - kAlpha) * df2 - g3;
-                            const double dtvf3 = a.dt * vf[i];
-                            const double s4 = fn - 0.25 * (dtvf2 + dtvf3) - kBeta * df1 - kEta * df2 - kKappa * df3;
-                            const double r = fn - (dtvf2 + dtvf3) * (1.0 / 6.0) - (df2 + df3) * (1.0 / 6.0);
-                            outv[i] = (S)s4;
-                            fbv[i] = (S)r;
-                        } else {  // kStage5
-                            const double r = fb[i];
-                            const double df4 = a.omega * a.a1 * (gown[i] - eown[i]);
-                            fbv[i] = (S)(r - (2.0 / 3.0) * (a.dt * vf[i] + df4));
-                        }
-                    }
-                    S* op = static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + own0;
-                    const S(&ov)[L] = (KIND == kStage5) ? fbv : outv;
-                    if (vec) {
-                        store4<S>(op, ov);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < L; ++i)
-                            if (row_real && ox0 + i < nx) op[i] = ov[i];
-                    }
-                    if constexpr (KIND == kStage4) {
-                        S* fp = static_cast<S*>(a.fbuf) + own0;
-                        if (vec) {
-                            store4<S>(fp, fbv);
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < L; ++i)
-                                if (row_real && ox0 + i < nx) fp[i] = fbv[i];
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < L; ++i) acc_add(acc[i], pd, (double)ov[i]);
+                if (s < OWN) eown[s] = e;
+                if (gcell[s] >= 0) {
+                    const double val = RELAX ? fma(a.a_rel, g[s], a.b_rel * e) : g[s];
+                    tile[lidx[s]] = (S)val;
                 }
             }
+            if constexpr (KIND == kStage4) {
+#pragma unroll
+                for (int i = 0; i < OWN; ++i) {
+                    double gx = ngm[i];
+                    if (st.first) {
+                        double gp, gq;
+                        g_pair<QM>(hx, nux[i], nth[i], gp, gq);
+                        const bool lo = st.kx == st.hx;
+                        gx = lo ? gp : gq;
+                        ngm[i] = lo ? gq : gp;
+                    }
+                    enown[i] = nA[i] * gx;
+                }
+            }
+        }
+        __syncthreads();
+
+        if (tid < NT / 2) {  // x sweep: row tid % TY, cells 8 (tid / TY) .. +7
+            if (st.px != 0.0) {
+                const int row = tid % TY, seg = tid / TY;
+                const bool fwd = st.px > 0.0;
+                const S* base = tile + (row + 5) * P + seg * L + (fwd ? 0 : L + 9);
+                const int sd = fwd ? 1 : -1;
+                R w[L + 9];
+#pragma unroll
+                for (int m = 0; m < L + 9; ++m) w[m] = base[m * sd];
+                R dif[L];
+                mp9_line<R, L>(w, dif);
+                R* o = vfx + row * VP + seg * L;
+                if (fwd) {
+#pragma unroll
+                    for (int i = 0; i < L; ++i) o[i] = dif[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < L; ++i) o[i] = dif[L - 1 - i];
+                }
+            }
+        } else {             // y sweep: column (tid - NT/2) % 64, cells 8 seg .. +7
+            if (st.py != 0.0) {
+                const int i2 = tid - NT / 2;
+                const int col = i2 % TX, seg = i2 / TX;
+                const bool fwd = st.py > 0.0;
+                const S* base = tile + (seg * L + (fwd ? 0 : L + 9)) * P + col + 5;
+                const int sd = fwd ? P : -P;
+                R w[L + 9];
+#pragma unroll
+                for (int m = 0; m < L + 9; ++m) w[m] = base[m * sd];
+                R dif[L];
+                mp9_line<R, L>(w, dif);
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    const int r = fwd ? seg * L + i : seg * L + L - 1 - i;
+                    vfy[r * VP + col] = dif[i];
+                }
+            }
+        }
+        __syncthreads();
+
+        const double sx = fabs(st.px) * a.inv_dx;
+        const double sy = fabs(st.py) * a.inv_dy;
+        double vf[OWN];
+#pragma unroll
+        for (int i = 0; i < OWN; ++i) {
+            vf[i] = 0.0;
+            if (st.px != 0.0) vf[i] = (double)vfx[orow * VP + ox + i] * sx;
+            if (st.py != 0.0) vf[i] = fma((double)vfy[orow * VP + ox + i], sy, vf[i]);
+        }
+
+        const size_t own0 = (size_t)st.v * ps + (size_t)oy * nx + ox0;
+        if constexpr (KIND == kAdvect) {
+            double* o = static_cast<double*>(a.out) + own0;
+#pragma unroll
+            for (int i = 0; i < OWN; ++i)
+                if (row_real && ox0 + i < nx) o[i] = vf[i];
+        } else {
+            S outv[OWN], fbv[OWN];
+#pragma unroll
+            for (int i = 0; i < OWN; ++i) {
+                if constexpr (KIND == kStage3) {
+                    const double fn = g[i], en = eown[i];
+                    outv[i] = (S)(fn - a.dt * vf[i] - (1.0 - kAlpha) * a.omega * a.a2 * (fn - en));
+                    fbv[i] = outv[i];
+                } else if constexpr (KIND == kStage4) {
+                    const double fn = fb[i], en = enown[i];
+                    const double g3 = g[i], e3 = eown[i];
+                    const double dn = fn - en, d3 = g3 - e3;
+                    const double df1 = a.omega * a.a1 * dn;
+                    const double df2 = a.omega * a.a2 * dn;
+                    const double df3 = a.omega * a.a1 * d3;
+                    const double dtvf2 = fn - (1.0 - kAlpha) * df2 - g3;
+                    const double dtvf3 = a.dt * vf[i];
+                    outv[i] = (S)(fn - 0.25 * (dtvf2 + dtvf3) - kBeta * df1 - kEta * df2 - kKappa * df3);
+                    fbv[i] = (S)(fn - (dtvf2 + dtvf3) * (1.0 / 6.0) - (df2 + df3) * (1.0 / 6.0));
+                } else {  // kStage5
+                    const double df4 = a.omega * a.a1 * (g[i] - eown[i]);
+                    fbv[i] = (S)(fb[i] - (2.0 / 3.0) * (a.dt * vf[i] + df4));
+                    outv[i] = fbv[i];
+                }
+            }
+            S* op = static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + own0;
+            if (vec) {
+                storeN<S, OWN>(op, outv);
+            } else {
+#pragma unroll
+                for (int i = 0; i < OWN; ++i)
+                    if (row_real && ox0 + i < nx) op[i] = outv[i];
+            }
+            if constexpr (KIND == kStage4) {
+                S* fp = static_cast<S*>(a.fbuf) + own0;
+                if (vec) {
+                    storeN<S, OWN>(fp, fbv);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < OWN; ++i)
+                        if (row_real && ox0 + i < nx) fp[i] = fbv[i];
+                }
+            }
+            const PlaneDesc pd{st.px, st.py, st.m0, st.mx, st.my, st.me, 0, 0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < OWN; ++i) acc_add(acc[i], pd, (double)outv[i]);
         }
     }
 
     if constexpr (KIND != kAdvect) {
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
+        for (int i = 0; i < OWN; ++i) {
             if (row_real && ox0 + i < nx) {
                 const double n = acc[i].s0;
                 const double ux = acc[i].sx / n, uy = acc[i].sy / n;
@@ -508,7 +645,7 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
     const int x0 = logical * TX;
     const int nx = a.nx;
     const long long ps = a.plane_stride;
-    const DevTables* __restrict__ tab = a.tab;
+    CTab* tab = (CTab*)a.tab;
     const int ox0 = x0 + tid * L;
     const bool vec = (x0 + TX <= nx) && (nx % 4 == 0);
 
@@ -575,8 +712,8 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
         }
         for (int kx = 0; kx < Q; ++kx) {
             const int v = vbase + kx;
-            const PlaneDesc pd = tab->plane[v];
-            const double* hx = tab->h[set][kx];
+            const PlaneDesc pd = load_desc(tab, v);
+            CDp hx = tab->h[set][kx];
             const S* __restrict__ sv = static_cast<const S*>(a.src) + (size_t)v * ps;
             S* buf = tile[parity];
             parity ^= 1;
@@ -719,12 +856,13 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
 // F = discrete equilibrium of (n, u, T) (Sec. II); one thread per cell.
 // ---------------------------------------------------------------------------
 template <typename S, int D>
-__global__ void __launch_bounds__(256) init_eq_kernel(const DevTables* __restrict__ tab,
+__global__ void __launch_bounds__(256) init_eq_kernel(const DevTables* __restrict__ tabp,
                                                       const double* __restrict__ n,
                                                       const double* __restrict__ ux,
                                                       const double* __restrict__ uy,
                                                       const double* __restrict__ T, S* F,
                                                       long long cells, double chi_fac) {
+    CTab* tab = (CTab*)tabp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
     const double nn = n[c], u = ux[c], w = D == 2 ? uy[c] : 0.0, th = T[c] - 1.0;
@@ -743,14 +881,15 @@ __global__ void __launch_bounds__(256) init_eq_kernel(const DevTables* __restric
 // Moments of a plane-set (Sec. II, Eq. Moments_discrete): n, n u from the phi
 // planes; (D + K) n T = sum_phi |p|^2 phi + sum_chi chi - n |u|^2.
 template <typename S, int D>
-__global__ void __launch_bounds__(256) moments_kernel(const DevTables* __restrict__ tab,
+__global__ void __launch_bounds__(256) moments_kernel(const DevTables* __restrict__ tabp,
                                                       const S* __restrict__ F, double* M,
                                                       long long cells, double dk) {
+    CTab* tab = (CTab*)tabp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
     Acc a{0.0, 0.0, 0.0, 0.0};
     const int np = tab->nplanes;
-    for (int v = 0; v < np; ++v) acc_add(a, tab->plane[v], (double)F[(size_t)v * cells + c]);
+    for (int v = 0; v < np; ++v) acc_add(a, load_desc(tab, v), (double)F[(size_t)v * cells + c]);
     const double nn = a.s0, ux = a.sx / nn, uy = a.sy / nn;
     if (D == 2) {
         M[c] = nn;
@@ -821,10 +960,16 @@ template <typename S, int KIND>
 hipError_t launch_stage_t(int d, const StageArgs& a, hipStream_t s) {
     const int ntiles = d == 2 ? a.ntx * a.nty : a.ntx;
     const int grid = 8 * ((ntiles + 7) / 8);
-    if (d == 2)
-        hipLaunchKernelGGL((stage2d_kernel<S, KIND>), dim3(grid), dim3(256), 0, s, a);
-    else
+    if (d == 2) {
+        constexpr int TY = kTile2Y, OWN = kOwn2;
+        constexpr int NT = 64 * TY / OWN;
+        if (a.qm == 16)
+            hipLaunchKernelGGL((stage2d_kernel<S, KIND, 16, TY, OWN>), dim3(grid), dim3(NT), 0, s, a);
+        else
+            hipLaunchKernelGGL((stage2d_kernel<S, KIND, 8, TY, OWN>), dim3(grid), dim3(NT), 0, s, a);
+    } else {
         hipLaunchKernelGGL((stage1d_kernel<S, KIND>), dim3(grid), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
