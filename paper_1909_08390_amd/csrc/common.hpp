@@ -54,8 +54,10 @@ struct PlaneStep {
     int kx, ky;               // node indices
     int hx;                   // node whose Horner row evaluates (kx, mirror)
     int first;                // 1: evaluate the pair now; 0: use the cached mirror
-    int mirror_is_next;       // 1 when the next step is kx's mirror (cache it)
-    int new_group;            // 1: ky (or the set) changed -> recompute the y factor
+    int hy;                   // node whose Horner row evaluates (ky, mirror)
+    int new_group;            // 1: ky (or the set) changed -> y factor changes
+    int yfirst;               // 1: evaluate the y pair now; 0: use the cached mirror
+    int new_set;              // 1: first step of a set (x-factor tables rebuilt)
 };
 
 // Constant tables of one context, in device memory.

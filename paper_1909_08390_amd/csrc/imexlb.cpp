@@ -287,29 +287,39 @@ imexlb_status imexlb_create(const imexlb_config* cfg, void* hip_stream, imexlb_c
         }
     t->nplanes = c->nplanes;
     t->nphi = c->nphi;
-    {   // processing order of the 2D passes: per set, ky-major; each x-node
-        // followed by its mirror (one Horner evaluation gives both factors)
+    {   // processing order of the 2D passes: per set, ky-major; every node
+        // (in x and in y) followed by its mirror, so that one Horner
+        // evaluation gives the factors of both
         int j = 0;
         for (int s = 0; s < 2; ++s) {
             const int base = s ? c->nphi : 0;
             const int nyg = d == 2 ? Q[s] : 1;
-            for (int ky = 0; ky < nyg; ++ky) {
-                bool group_start = true;
-                for (int k = 0; k < (Q[s] + 1) / 2; ++k) {
-                    const int pair[2] = {k, Q[s] - 1 - k};
-                    const int cnt = pair[0] == pair[1] ? 1 : 2;
-                    for (int e = 0; e < cnt; ++e, ++j) {
-                        PlaneStep& st = t->order[j];
-                        const int kx = pair[e];
-                        st.v = base + kx + Q[s] * ky;
-                        st.set = s;
-                        st.kx = kx;
-                        st.ky = ky;
-                        st.hx = k;
-                        st.first = e == 0;
-                        st.mirror_is_next = cnt == 2 && e == 0;
-                        st.new_group = group_start;
-                        group_start = false;
+            bool set_start = true;
+            for (int ly = 0; ly < (nyg + 1) / 2; ++ly) {
+                const int ypair[2] = {ly, nyg - 1 - ly};
+                const int ycnt = ypair[0] == ypair[1] ? 1 : 2;
+                for (int ey = 0; ey < ycnt; ++ey) {
+                    const int ky = ypair[ey];
+                    bool group_start = true;
+                    for (int k = 0; k < (Q[s] + 1) / 2; ++k) {
+                        const int pair[2] = {k, Q[s] - 1 - k};
+                        const int cnt = pair[0] == pair[1] ? 1 : 2;
+                        for (int e = 0; e < cnt; ++e, ++j) {
+                            PlaneStep& st = t->order[j];
+                            const int kx = pair[e];
+                            st.v = base + kx + Q[s] * ky;
+                            st.set = s;
+                            st.kx = kx;
+                            st.ky = ky;
+                            st.hx = k;
+                            st.first = e == 0;
+                            st.hy = ly;
+                            st.new_group = group_start;
+                            st.yfirst = group_start && ey == 0;
+                            st.new_set = set_start;
+                            group_start = false;
+                            set_start = false;
+                        }
                     }
                 }
             }

@@ -150,6 +150,54 @@ __device__ __forceinline__ void mp9_line(const R (&w)[L + 9], R (&dif)[L]) {
     for (int i = 0; i < L; ++i) dif[i] = fl[i + 1] - fl[i];
 }
 
+// Streaming form of mp9_line for a window held in LDS: window position m is
+// base[m * sd]; the flux difference of the node at position 5 + i is written
+// to out[i * ostep].  Only a 9-value window and 8 differences are live; the
+// limiter (the same two-case rule) is taken per face, skipped by the
+// wavefront when none of its lanes needs it.
+template <typename R, typename S, int L>
+__device__ __forceinline__ void mp9_sweep(const S* base, int sd, R* out, int ostep) {
+    constexpr R e0 = R(-4.0 / 2520.0), e1 = R(37.0 / 2520.0), e2 = R(-162.0 / 2520.0),
+                e3 = R(479.0 / 2520.0), e4 = R(1120.0 / 2520.0), e5 = R(-255.0 / 2520.0),
+                e6 = R(50.0 / 2520.0), e7 = R(-5.0 / 2520.0);
+    R w[L + 9];
+#pragma unroll
+    for (int m = 0; m < L + 9; ++m) w[m] = (R)base[m * sd];
+    R prev = R(0);
+#pragma unroll
+    for (int i = 0; i <= L; ++i) {
+        const int m = i + 4;
+        // differences d_j = w[j+1] - w[j] for j = m-4 .. m+3 (recomputed: cheap)
+        R d[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d[k] = w[m - 4 + k + 1] - w[m - 4 + k];
+        const R fs = w[m], fp = w[m + 1];
+        R s = e0 * d[0];
+        s = fma(e1, d[1], s);
+        s = fma(e2, d[2], s);
+        s = fma(e3, d[3], s);
+        s = fma(e4, d[4], s);
+        s = fma(e5, d[5], s);
+        s = fma(e6, d[6], s);
+        s = fma(e7, d[7], s);
+        R fl = fs + s;
+        const R ul = fma(R(4), d[3], fs);
+        const R fmp = med3(fs, fp, ul);
+        if ((fl - fs) * (fl - fmp) > R(0)) {
+            const R cm = d[3] - d[2], c0 = d[4] - d[3], cp = d[5] - d[4];
+            const R dm = minmod4(fma(R(4), cm, -c0), fma(R(4), c0, -cm), cm, c0);
+            const R d0 = minmod4(fma(R(4), c0, -cp), fma(R(4), cp, -c0), c0, cp);
+            const R lc = fma(R(4.0 / 3.0), dm, fma(R(0.5), d[3], fs));
+            const R md = fma(R(0.5), d[4] - d0, fs);
+            const R lo = fmax(fmin(fmin(fs, fp), md), fmin(fmin(fs, ul), lc));
+            const R hi = fmin(fmax(fmax(fs, fp), md), fmax(fmax(fs, ul), lc));
+            fl = fmin(fmax(fl, lo), hi);
+        }
+        if (i > 0) out[(i - 1) * ostep] = fl - prev;
+        prev = fl;
+    }
+}
+
 template <typename S>
 struct Vec4;
 template <>
@@ -259,7 +307,7 @@ __device__ __forceinline__ PlaneStep load_step(CTab* t, int j) {
     PlaneStep s;
     s.px = r.px; s.py = r.py; s.m0 = r.m0; s.mx = r.mx; s.my = r.my; s.me = r.me;
     s.v = r.v; s.set = r.set; s.kx = r.kx; s.ky = r.ky; s.hx = r.hx; s.first = r.first;
-    s.mirror_is_next = r.mirror_is_next; s.new_group = r.new_group;
+    s.hy = r.hy; s.new_group = r.new_group; s.yfirst = r.yfirst; s.new_set = r.new_set;
     return s;
 }
 
@@ -269,6 +317,35 @@ __device__ __forceinline__ PlaneDesc load_desc(CTab* t, int v) {
     s.px = r.px; s.py = r.py; s.m0 = r.m0; s.mx = r.mx; s.my = r.my; s.me = r.me;
     s.set = r.set; s.kx = r.kx; s.ky = r.ky; s.pad = 0;
     return s;
+}
+
+// g_pair with the Horner row already in registers (loaded once per plane
+// and shared by all cells of the thread).
+template <int QM>
+__device__ __forceinline__ void g_pair_r(const double (&c)[HornerLayout<QM>::total()], double u,
+                                         double th, double& g, double& gm) {
+    using H = HornerLayout<QM>;
+    const double v = u * u;
+    double ge = 0.0, go = 0.0;
+#pragma unroll
+    for (int s = H::S; s >= 0; --s) {
+        constexpr int dummy = 0;
+        (void)dummy;
+        const int oe = H::off(s), no = H::no(s), ne = H::ne(s);
+        double e = c[oe + ne - 1];
+#pragma unroll
+        for (int i = ne - 2; i >= 0; --i) e = fma(e, v, c[oe + i]);
+        double o = 0.0;
+        if (no > 0) {
+            o = c[oe + ne + no - 1];
+#pragma unroll
+            for (int i = no - 2; i >= 0; --i) o = fma(o, v, c[oe + ne + i]);
+        }
+        ge = (s == H::S) ? e : fma(ge, th, e);
+        go = (s == H::S) ? o : fma(go, th, o);
+    }
+    g = fma(u, go, ge);
+    gm = fma(-u, go, ge);
 }
 
 template <int QM>
@@ -320,6 +397,7 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
     __shared__ S tile[(TY + 10) * P];
     __shared__ R vfx[TY * VP];
     __shared__ R vfy[TY * VP];
+    __shared__ double gtab[(RELAX && QM == 8) ? 8 * (TX * TY + NH) : 1];
 
     int txi, tyi;
     if (!tile_of_block(a, txi, tyi)) return;
@@ -366,15 +444,27 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
         }
     }
 
+    // x-factor tables in LDS (orders up to 8): gtab[k * NLOAD + cid] holds
+    // g_x of node k at loaded cell cid; rebuilt at the start of each set.
+    constexpr bool TAB = RELAX && (QM == 8);
+    constexpr int NLOAD = TX * TY + NH;
+    int cid[NS];
+#pragma unroll
+    for (int i = 0; i < OWN; ++i) cid[i] = i * NT + tid;
+#pragma unroll
+    for (int jh = 0; jh < HS; ++jh) cid[OWN + jh] = TX * TY + jh * NT + tid;
+
     // Per loaded cell: u_x and T - 1 of the source moments, the y factor
-    // A = P_set g_y (P_phi = n, P_chi = (K + D - d) n T) of the current group,
-    // and the cached x factor of the mirrored node.
-    double sux[NS], sth[NS], sA[NS], sgm[NS];
+    // A = P_set g_y (P_phi = n, P_chi = (K + D - d) n T) of the current group
+    // and of the mirrored group, and (without tables) the cached x factor of
+    // the mirrored node.
+    double sux[NS], sth[NS], sA[NS], sAm[NS], sgm[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         sux[s] = 0.0;
         sth[s] = 0.0;
         sA[s] = 0.0;
+        sAm[s] = 0.0;
         sgm[s] = 0.0;
         if (RELAX && gcell[s] >= 0) {
             sux[s] = a.msrc[ps + gcell[s]];
@@ -382,12 +472,13 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
         }
     }
     // Stage 4 also needs E^n at its own cells (moments of F^n).
-    double nux[OWN], nth[OWN], nA[OWN], ngm[OWN];
+    double nux[OWN], nth[OWN], nA[OWN], nAm[OWN], ngm[OWN];
 #pragma unroll
     for (int i = 0; i < OWN; ++i) {
         nux[i] = 0.0;
         nth[i] = 0.0;
         nA[i] = 0.0;
+        nAm[i] = 0.0;
         ngm[i] = 0.0;
         if (KIND == kStage4) {
             nux[i] = a.mn[ps + gcell[i]];
@@ -410,7 +501,7 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
             for (int i = 0; i < OWN; ++i) pg[i] = sv[gcell[i]];
         }
 #pragma unroll
-        for (int j = 0; j < HS; ++j) pg[OWN + j] = gcell[OWN + j] >= 0 ? (double)sv[gcell[OWN + j]] : 0.0;
+        for (int jh = 0; jh < HS; ++jh) pg[OWN + jh] = gcell[OWN + jh] >= 0 ? (double)sv[gcell[OWN + jh]] : 0.0;
         if constexpr (KIND == kStage4 || KIND == kStage5) {
             const S* fbp = static_cast<const S*>(a.fbuf) + (size_t)v * ps;
             if (vec) {
@@ -422,6 +513,7 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
         }
     };
 
+    constexpr int NC = HornerLayout<QM>::total();
     const int np = tab->nplanes;
     fetch(tab->order[0].v);
     for (int j = 0; j < np; ++j) {
@@ -435,49 +527,113 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
         if (j + 1 < np) fetch(tab->order[j + 1].v);
 
         if constexpr (RELAX) {
-            if (st.new_group) {
-                CDp hy = tab->h[st.set][st.ky];
+            if constexpr (TAB) {
+                if (st.new_set) {  // x factors of every node of this set
+                    for (int k = 0; k < (Q + 1) / 2; ++k) {
+                        CDp hx = hrow<QM>(tab, st.set, k);
+                        double cf[NC];
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    if (gcell[s] >= 0) {
-                        const double n = a.msrc[gcell[s]];
-                        const double uy = a.msrc[2 * ps + gcell[s]];
-                        const double pre = st.set ? a.chi_fac * n * (sth[s] + 1.0) : n;
-                        sA[s] = pre * herm_factor(hy, Q, uy, sth[s]);
+                        for (int i = 0; i < NC; ++i) cf[i] = hx[i];
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) {
+                            if (gcell[s] >= 0) {
+                                double gp, gq;
+                                g_pair_r<QM>(cf, sux[s], sth[s], gp, gq);
+                                gtab[k * NLOAD + cid[s]] = gp;
+                                gtab[(Q - 1 - k) * NLOAD + cid[s]] = gq;
+                            }
+                        }
                     }
                 }
-                if constexpr (KIND == kStage4) {
+            }
+            if (st.new_group) {  // y factors of the group (and of its mirror)
+                if (st.yfirst) {
+                    CDp hy = hrow<QM>(tab, st.set, st.hy);
+                    double cf[NC];
 #pragma unroll
-                    for (int i = 0; i < OWN; ++i) {
-                        const double n = a.mn[gcell[i]];
-                        const double uy = a.mn[2 * ps + gcell[i]];
-                        const double pre = st.set ? a.chi_fac * n * (nth[i] + 1.0) : n;
-                        nA[i] = pre * herm_factor(hy, Q, uy, nth[i]);
+                    for (int i = 0; i < NC; ++i) cf[i] = hy[i];
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        if (gcell[s] >= 0) {
+                            const double n = a.msrc[gcell[s]];
+                            const double uy = a.msrc[2 * ps + gcell[s]];
+                            const double pre = st.set ? a.chi_fac * n * (sth[s] + 1.0) : n;
+                            double gp, gq;
+                            g_pair_r<QM>(cf, uy, sth[s], gp, gq);
+                            sA[s] = pre * gp;
+                            sAm[s] = pre * gq;
+                        }
                     }
+                    if constexpr (KIND == kStage4) {
+#pragma unroll
+                        for (int i = 0; i < OWN; ++i) {
+                            const double n = a.mn[gcell[i]];
+                            const double uy = a.mn[2 * ps + gcell[i]];
+                            const double pre = st.set ? a.chi_fac * n * (nth[i] + 1.0) : n;
+                            double gp, gq;
+                            g_pair_r<QM>(cf, uy, nth[i], gp, gq);
+                            nA[i] = pre * gp;
+                            nAm[i] = pre * gq;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) sA[s] = sAm[s];
+#pragma unroll
+                    for (int i = 0; i < OWN; ++i) nA[i] = nAm[i];
                 }
             }
         }
 
-        // relax on read into the LDS tile
+        // relax on read into the LDS tile.  x factors come from the LDS
+        // tables, or (orders above 8, and stage 4's own E^n) from one Horner
+        // evaluation per cell on the first plane of a mirror pair, the
+        // second plane using the cached mirror factor.
         double eown[OWN], enown[OWN];
         {
-            CDp hx = hrow<QM>(tab, st.set, st.hx);
+            double gxs[NS], gxn[OWN];
+            if constexpr (RELAX) {
+                if constexpr (TAB) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        gxs[s] = gcell[s] >= 0 ? gtab[st.kx * NLOAD + cid[s]] : 0.0;
+                }
+                if (st.first) {
+                    CDp hx = hrow<QM>(tab, st.set, st.hx);
+                    double cf[NC];
+#pragma unroll
+                    for (int i = 0; i < NC; ++i) cf[i] = hx[i];
+                    if constexpr (!TAB) {
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) {
+                            double gp = 0.0, gq = 0.0;
+                            if (gcell[s] >= 0) g_pair_r<QM>(cf, sux[s], sth[s], gp, gq);
+                            gxs[s] = gp;
+                            sgm[s] = gq;
+                        }
+                    }
+                    if constexpr (KIND == kStage4) {
+#pragma unroll
+                        for (int i = 0; i < OWN; ++i) {
+                            double gp, gq;
+                            g_pair_r<QM>(cf, nux[i], nth[i], gp, gq);
+                            gxn[i] = gp;
+                            ngm[i] = gq;
+                        }
+                    }
+                } else {
+                    if constexpr (!TAB) {
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) gxs[s] = sgm[s];
+                    }
+#pragma unroll
+                    for (int i = 0; i < OWN; ++i) gxn[i] = ngm[i];
+                }
+            }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 double e = 0.0;
-                if constexpr (RELAX) {
-                    if (gcell[s] >= 0) {
-                        double gx = sgm[s];
-                        if (st.first) {
-                            double gp, gq;
-                            g_pair<QM>(hx, sux[s], sth[s], gp, gq);
-                            const bool lo = st.kx == st.hx;  // kx is the row's own node
-                            gx = lo ? gp : gq;
-                            sgm[s] = lo ? gq : gp;
-                        }
-                        e = sA[s] * gx;
-                    }
-                }
+                if constexpr (RELAX) e = sA[s] * gxs[s];
                 if (s < OWN) eown[s] = e;
                 if (gcell[s] >= 0) {
                     const double val = RELAX ? fma(a.a_rel, g[s], a.b_rel * e) : g[s];
@@ -486,17 +642,7 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
             }
             if constexpr (KIND == kStage4) {
 #pragma unroll
-                for (int i = 0; i < OWN; ++i) {
-                    double gx = ngm[i];
-                    if (st.first) {
-                        double gp, gq;
-                        g_pair<QM>(hx, nux[i], nth[i], gp, gq);
-                        const bool lo = st.kx == st.hx;
-                        gx = lo ? gp : gq;
-                        ngm[i] = lo ? gq : gp;
-                    }
-                    enown[i] = nA[i] * gx;
-                }
+                for (int i = 0; i < OWN; ++i) enown[i] = nA[i] * gxn[i];
             }
         }
         __syncthreads();
@@ -506,20 +652,9 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
                 const int row = tid % TY, seg = tid / TY;
                 const bool fwd = st.px > 0.0;
                 const S* base = tile + (row + 5) * P + seg * L + (fwd ? 0 : L + 9);
-                const int sd = fwd ? 1 : -1;
-                R w[L + 9];
-#pragma unroll
-                for (int m = 0; m < L + 9; ++m) w[m] = base[m * sd];
-                R dif[L];
-                mp9_line<R, L>(w, dif);
                 R* o = vfx + row * VP + seg * L;
-                if (fwd) {
-#pragma unroll
-                    for (int i = 0; i < L; ++i) o[i] = dif[i];
-                } else {
-#pragma unroll
-                    for (int i = 0; i < L; ++i) o[i] = dif[L - 1 - i];
-                }
+                if (fwd) mp9_sweep<R, S, L>(base, 1, o, 1);
+                else mp9_sweep<R, S, L>(base, -1, o + L - 1, -1);
             }
         } else {             // y sweep: column (tid - NT/2) % 64, cells 8 seg .. +7
             if (st.py != 0.0) {
@@ -527,17 +662,9 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
                 const int col = i2 % TX, seg = i2 / TX;
                 const bool fwd = st.py > 0.0;
                 const S* base = tile + (seg * L + (fwd ? 0 : L + 9)) * P + col + 5;
-                const int sd = fwd ? P : -P;
-                R w[L + 9];
-#pragma unroll
-                for (int m = 0; m < L + 9; ++m) w[m] = base[m * sd];
-                R dif[L];
-                mp9_line<R, L>(w, dif);
-#pragma unroll
-                for (int i = 0; i < L; ++i) {
-                    const int r = fwd ? seg * L + i : seg * L + L - 1 - i;
-                    vfy[r * VP + col] = dif[i];
-                }
+                R* o = vfy + seg * L * VP + col;
+                if (fwd) mp9_sweep<R, S, L>(base, P, o, VP);
+                else mp9_sweep<R, S, L>(base, -P, o + (L - 1) * VP, -VP);
             }
         }
         __syncthreads();
