@@ -60,8 +60,18 @@ struct PlaneStep {
     int new_set;              // 1: first step of a set (x-factor tables rebuilt)
 };
 
+// PlaneStep packed for the kernels (6 dwords, prefetched into SGPRs):
+// bits: set | first<<1 | new_group<<2 | yfirst<<3 | new_set<<4 | kx<<5 |
+// ky<<10 | hx<<15 | hy<<20 (node indices < 32).
+struct PackedStep {
+    double px, py;
+    int v;
+    int bits;
+};
+
 // Constant tables of one context, in device memory.
 struct DevTables {
+    PackedStep step[kMaxPlanes];
     // h[set][k][l] = w_k He_l(p_k) / l!  (zero for l >= Q_set), so that the
     // one-axis equilibrium factor of Eq. (gExpanded) is g_k = sum_l h[k][l] a_l
     // with the Hermite coefficients a_l(u, T) of the local Maxwellian.
@@ -93,6 +103,12 @@ struct StageArgs {
     double dt, omega;
     double a_rel, b_rel;     // relax-on-read weights: F_i = a_rel G + b_rel E
     double a1, a2;           // 1/(1+c) and (1+2c)/(1+c)^2, c = alpha dt/tau
+    // Combined stage coefficients (w = dt/tau):
+    //  k[0] = (1 - alpha) w a2                              (pass 3)
+    //  k[1] = (1 - alpha) w a2 / 4 - beta w a1 - eta w a2,
+    //  k[2] = kappa w a1, k[3] = alpha w a2 / 6, k[4] = w a1 / 6   (pass 4)
+    //  k[5] = 2 w a1 / 3                                    (pass 5)
+    double k[6];
     double chi_fac;          // K + D - d
     double dk;               // D + K
 };

@@ -184,6 +184,17 @@ StageArgs base_args(const imexlb_ctx* c) {
     const double cc = kAlpha * a.omega;
     a.a1 = 1.0 / (1.0 + cc);
     a.a2 = (1.0 + 2.0 * cc) / ((1.0 + cc) * (1.0 + cc));
+    {
+        constexpr double be = 0.06042356519705, et = 0.12915286960590;  // Table I
+        const double ka = 0.5 - be - et - kAlpha;
+        const double w = a.omega;
+        a.k[0] = (1.0 - kAlpha) * w * a.a2;
+        a.k[1] = 0.25 * (1.0 - kAlpha) * w * a.a2 - be * w * a.a1 - et * w * a.a2;
+        a.k[2] = ka * w * a.a1;
+        a.k[3] = kAlpha * w * a.a2 / 6.0;
+        a.k[4] = w * a.a1 / 6.0;
+        a.k[5] = 2.0 * w * a.a1 / 3.0;
+    }
     a.chi_fac = (double)(k.K + kDTotal - k.d);
     a.dk = (double)(kDTotal + k.K);
     return a;
@@ -356,6 +367,12 @@ imexlb_status imexlb_create(const imexlb_config* cfg, void* hip_stream, imexlb_c
         st.mx = pd.mx;
         st.my = pd.my;
         st.me = pd.me;
+        PackedStep& ps = t->step[j];
+        ps.px = st.px;
+        ps.py = st.py;
+        ps.v = st.v;
+        ps.bits = st.set | (st.first << 1) | (st.new_group << 2) | (st.yfirst << 3) |
+                  (st.new_set << 4) | (st.kx << 5) | (st.ky << 10) | (st.hx << 15) | (st.hy << 20);
     }
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_tab, sizeof(DevTables));

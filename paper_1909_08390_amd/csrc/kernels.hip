@@ -348,6 +348,31 @@ __device__ __forceinline__ void g_pair_r(const double (&c)[HornerLayout<QM>::tot
     gm = fma(-u, go, ge);
 }
 
+// One entry of the plane order, unpacked from PackedStep.
+struct Step {
+    double px, py;
+    int v, bits;
+    __device__ int set() const { return bits & 1; }
+    __device__ bool first() const { return (bits >> 1) & 1; }
+    __device__ bool new_group() const { return (bits >> 2) & 1; }
+    __device__ bool yfirst() const { return (bits >> 3) & 1; }
+    __device__ bool new_set() const { return (bits >> 4) & 1; }
+    __device__ int kx() const { return (bits >> 5) & 31; }
+    __device__ int ky() const { return (bits >> 10) & 31; }
+    __device__ int hx() const { return (bits >> 15) & 31; }
+    __device__ int hy() const { return (bits >> 20) & 31; }
+};
+
+__device__ __forceinline__ Step load_pstep(CTab* t, int j) {
+    const PackedStep IMEXLB_CONST& r = t->step[j];
+    Step s;
+    s.px = r.px;
+    s.py = r.py;
+    s.v = r.v;
+    s.bits = r.bits;
+    return s;
+}
+
 template <int QM>
 __device__ __forceinline__ CDp hrow(CTab* t, int set, int k) {
     if constexpr (QM == 8) return t->hc8[set][k];
@@ -382,25 +407,28 @@ __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& 
 // results spread over all banks.
 // ---------------------------------------------------------------------------
 template <typename S, int KIND, int QM, int TY, int OWN>
-__global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
-    constexpr int TX = 64, NT = TX * TY / OWN, L = 2 * OWN;
-    constexpr int OPR = TX / OWN;         // threads per tile row
-    constexpr int P = TX + 11;            // tile pitch (odd)
-    constexpr int VP = TX + 1;            // VF buffer pitch (odd)
-    constexpr int NH = 10 * TY + 10 * TX; // cross-shaped halo
-    constexpr int HS = (NH + NT - 1) / NT;
-    constexpr int NS = OWN + HS;
-    constexpr bool RELAX = KIND != kAdvect;
+struct Stage2DShape {
+    static constexpr int TX = 64, NT = TX * TY / OWN, L = 2 * OWN;
+    static constexpr int OPR = TX / OWN;          // threads per tile row
+    static constexpr int P = TX + 11;             // tile pitch (odd)
+    static constexpr int VP = TX + 1;             // VF buffer pitch (odd)
+    static constexpr int NH = 10 * TY + 10 * TX;  // cross-shaped halo
+    static constexpr int HS = (NH + NT - 1) / NT;
+    static constexpr int NS = OWN + HS;
+    static constexpr bool RELAX = KIND != kAdvect;
+    static constexpr bool TAB = RELAX && (QM == 8);
+    static constexpr int NLOAD = TX * TY + NH;
+};
+
+template <typename S, int KIND, int QM, int TY, int OWN, bool VEC>
+__device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int tyi, S* tile, S* vfx,
+                                             S* vfy, double* gtab) {
+    using Sh = Stage2DShape<S, KIND, QM, TY, OWN>;
+    constexpr int TX = Sh::TX, NT = Sh::NT, L = Sh::L, OPR = Sh::OPR, P = Sh::P, VP = Sh::VP;
+    constexpr int NH = Sh::NH, HS = Sh::HS, NS = Sh::NS;
+    constexpr bool RELAX = Sh::RELAX;
     static_assert(TY * (TX / L) == NT / 2 && TX * (TY / L) == NT / 2, "sweep split");
     using R = S;
-
-    __shared__ S tile[(TY + 10) * P];
-    __shared__ R vfx[TY * VP];
-    __shared__ R vfy[TY * VP];
-    __shared__ double gtab[(RELAX && QM == 8) ? 8 * (TX * TY + NH) : 1];
-
-    int txi, tyi;
-    if (!tile_of_block(a, txi, tyi)) return;
     const int tid = threadIdx.x;
     const int x0 = txi * TX, y0 = tyi * TY;
     const int nx = a.nx, ny = a.ny;
@@ -409,15 +437,20 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
 
     const int orow = tid / OPR, ox = (tid % OPR) * OWN;
     const int oy = y0 + orow, ox0 = x0 + ox;
-    const bool vec = (x0 + TX <= nx) && (y0 + TY <= ny) && (nx % OWN == 0);
+    constexpr bool vec = VEC;
     const bool row_real = oy < ny;
 
+    // gcell: global cell read by each loaded slot (ghost nodes mapped by the
+    // boundary rule); slots past the end of the halo list read cell gcell[0]
+    // (valid, unused) so that every thread issues the same loads.
     int gcell[NS], lidx[NS];
+    bool sval[NS];
     {
         const int gy = bc_map(oy, ny, a.bcy) * nx;
 #pragma unroll
         for (int i = 0; i < OWN; ++i) {
             gcell[i] = gy + bc_map(ox0 + i, nx, a.bcx);
+            sval[i] = true;
             lidx[i] = (orow + 5) * P + ox + i + 5;
         }
 #pragma unroll
@@ -434,11 +467,12 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
                 lx = hh % TX + 5;
                 ly = k < 5 ? k : TY + k;
             }
+            sval[OWN + j] = h < NH;
             if (h < NH) {
                 gcell[OWN + j] = bc_map(y0 + ly - 5, ny, a.bcy) * nx + bc_map(x0 + lx - 5, nx, a.bcx);
                 lidx[OWN + j] = ly * P + lx;
             } else {
-                gcell[OWN + j] = -1;
+                gcell[OWN + j] = gcell[0];
                 lidx[OWN + j] = 0;
             }
         }
@@ -446,8 +480,8 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
 
     // x-factor tables in LDS (orders up to 8): gtab[k * NLOAD + cid] holds
     // g_x of node k at loaded cell cid; rebuilt at the start of each set.
-    constexpr bool TAB = RELAX && (QM == 8);
-    constexpr int NLOAD = TX * TY + NH;
+    constexpr bool TAB = Sh::TAB;
+    constexpr int NLOAD = Sh::NLOAD;
     int cid[NS];
 #pragma unroll
     for (int i = 0; i < OWN; ++i) cid[i] = i * NT + tid;
@@ -466,13 +500,21 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
         sA[s] = 0.0;
         sAm[s] = 0.0;
         sgm[s] = 0.0;
-        if (RELAX && gcell[s] >= 0) {
+        if (RELAX) {
             sux[s] = a.msrc[ps + gcell[s]];
             sth[s] = a.msrc[3 * ps + gcell[s]] - 1.0;
         }
     }
+    // n and u_y of the loaded cells (y factors), kept for the whole pass
+    double gn[NS], guy[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int c = gcell[s];
+        gn[s] = RELAX ? a.msrc[c] : 0.0;
+        guy[s] = RELAX ? a.msrc[2 * ps + c] : 0.0;
+    }
     // Stage 4 also needs E^n at its own cells (moments of F^n).
-    double nux[OWN], nth[OWN], nA[OWN], nAm[OWN], ngm[OWN];
+    double nux[OWN], nth[OWN], nA[OWN], nAm[OWN], ngm[OWN], gnn[OWN], gnuy[OWN];
 #pragma unroll
     for (int i = 0; i < OWN; ++i) {
         nux[i] = 0.0;
@@ -480,9 +522,13 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
         nA[i] = 0.0;
         nAm[i] = 0.0;
         ngm[i] = 0.0;
+        gnn[i] = 0.0;
+        gnuy[i] = 0.0;
         if (KIND == kStage4) {
             nux[i] = a.mn[ps + gcell[i]];
             nth[i] = a.mn[3 * ps + gcell[i]] - 1.0;
+            gnn[i] = a.mn[gcell[i]];
+            gnuy[i] = a.mn[2 * ps + gcell[i]];
         }
     }
     Acc acc[OWN];
@@ -494,17 +540,17 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
     double pg[NS], pf[OWN];
     auto fetch = [&](int v) {
         const S* __restrict__ sv = static_cast<const S*>(a.src) + (size_t)v * ps;
-        if (vec) {
+        if constexpr (VEC) {
             loadN<S, OWN>(sv + gcell[0], pg);
         } else {
 #pragma unroll
             for (int i = 0; i < OWN; ++i) pg[i] = sv[gcell[i]];
         }
 #pragma unroll
-        for (int jh = 0; jh < HS; ++jh) pg[OWN + jh] = gcell[OWN + jh] >= 0 ? (double)sv[gcell[OWN + jh]] : 0.0;
+        for (int jh = 0; jh < HS; ++jh) pg[OWN + jh] = (double)sv[gcell[OWN + jh]];
         if constexpr (KIND == kStage4 || KIND == kStage5) {
             const S* fbp = static_cast<const S*>(a.fbuf) + (size_t)v * ps;
-            if (vec) {
+            if constexpr (VEC) {
                 loadN<S, OWN>(fbp + gcell[0], pf);
             } else {
 #pragma unroll
@@ -515,28 +561,33 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
 
     constexpr int NC = HornerLayout<QM>::total();
     const int np = tab->nplanes;
-    fetch(tab->order[0].v);
+    Step s0 = load_pstep(tab, 0);
+    Step s1 = load_pstep(tab, np > 1 ? 1 : 0);
+    fetch(s0.v);
     for (int j = 0; j < np; ++j) {
-        const PlaneStep st = load_step(tab, j);
-        const int Q = tab->q[st.set];
+        const Step st = s0;
+        s0 = s1;
+        if (j + 2 < np) s1 = load_pstep(tab, j + 2);
+        const int Q = tab->q[st.set()];
         double g[NS], fb[OWN];
 #pragma unroll
         for (int s = 0; s < NS; ++s) g[s] = pg[s];
 #pragma unroll
         for (int i = 0; i < OWN; ++i) fb[i] = pf[i];
-        if (j + 1 < np) fetch(tab->order[j + 1].v);
+        const bool ygroup = RELAX && st.new_group() && st.yfirst();
+        fetch(s0.v);  // unconditional (the last iteration refetches) keeps the load count fixed
 
         if constexpr (RELAX) {
             if constexpr (TAB) {
-                if (st.new_set) {  // x factors of every node of this set
+                if (st.new_set()) {  // x factors of every node of this set
                     for (int k = 0; k < (Q + 1) / 2; ++k) {
-                        CDp hx = hrow<QM>(tab, st.set, k);
+                        CDp hx = hrow<QM>(tab, st.set(), k);
                         double cf[NC];
 #pragma unroll
                         for (int i = 0; i < NC; ++i) cf[i] = hx[i];
 #pragma unroll
                         for (int s = 0; s < NS; ++s) {
-                            if (gcell[s] >= 0) {
+                            if (sval[s]) {
                                 double gp, gq;
                                 g_pair_r<QM>(cf, sux[s], sth[s], gp, gq);
                                 gtab[k * NLOAD + cid[s]] = gp;
@@ -546,32 +597,28 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
                     }
                 }
             }
-            if (st.new_group) {  // y factors of the group (and of its mirror)
-                if (st.yfirst) {
-                    CDp hy = hrow<QM>(tab, st.set, st.hy);
+            if (st.new_group()) {  // y factors of the group (and of its mirror)
+                if (ygroup) {
+                    CDp hy = hrow<QM>(tab, st.set(), st.hy());
                     double cf[NC];
 #pragma unroll
                     for (int i = 0; i < NC; ++i) cf[i] = hy[i];
 #pragma unroll
                     for (int s = 0; s < NS; ++s) {
-                        if (gcell[s] >= 0) {
-                            const double n = a.msrc[gcell[s]];
-                            const double uy = a.msrc[2 * ps + gcell[s]];
-                            const double pre = st.set ? a.chi_fac * n * (sth[s] + 1.0) : n;
-                            double gp, gq;
-                            g_pair_r<QM>(cf, uy, sth[s], gp, gq);
-                            sA[s] = pre * gp;
-                            sAm[s] = pre * gq;
-                        }
+                        const double n = gn[s];
+                        const double pre = st.set() ? a.chi_fac * n * (sth[s] + 1.0) : n;
+                        double gp, gq;
+                        g_pair_r<QM>(cf, guy[s], sth[s], gp, gq);
+                        sA[s] = pre * gp;
+                        sAm[s] = pre * gq;
                     }
                     if constexpr (KIND == kStage4) {
 #pragma unroll
                         for (int i = 0; i < OWN; ++i) {
-                            const double n = a.mn[gcell[i]];
-                            const double uy = a.mn[2 * ps + gcell[i]];
-                            const double pre = st.set ? a.chi_fac * n * (nth[i] + 1.0) : n;
+                            const double n = gnn[i];
+                            const double pre = st.set() ? a.chi_fac * n * (nth[i] + 1.0) : n;
                             double gp, gq;
-                            g_pair_r<QM>(cf, uy, nth[i], gp, gq);
+                            g_pair_r<QM>(cf, gnuy[i], nth[i], gp, gq);
                             nA[i] = pre * gp;
                             nAm[i] = pre * gq;
                         }
@@ -596,10 +643,10 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
                 if constexpr (TAB) {
 #pragma unroll
                     for (int s = 0; s < NS; ++s)
-                        gxs[s] = gcell[s] >= 0 ? gtab[st.kx * NLOAD + cid[s]] : 0.0;
+                        gxs[s] = gtab[st.kx() * NLOAD + (sval[s] ? cid[s] : cid[0])];
                 }
-                if (st.first) {
-                    CDp hx = hrow<QM>(tab, st.set, st.hx);
+                if (st.first()) {
+                    CDp hx = hrow<QM>(tab, st.set(), st.hx());
                     double cf[NC];
 #pragma unroll
                     for (int i = 0; i < NC; ++i) cf[i] = hx[i];
@@ -607,7 +654,7 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
 #pragma unroll
                         for (int s = 0; s < NS; ++s) {
                             double gp = 0.0, gq = 0.0;
-                            if (gcell[s] >= 0) g_pair_r<QM>(cf, sux[s], sth[s], gp, gq);
+                            g_pair_r<QM>(cf, sux[s], sth[s], gp, gq);
                             gxs[s] = gp;
                             sgm[s] = gq;
                         }
@@ -635,7 +682,7 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
                 double e = 0.0;
                 if constexpr (RELAX) e = sA[s] * gxs[s];
                 if (s < OWN) eown[s] = e;
-                if (gcell[s] >= 0) {
+                if (sval[s]) {
                     const double val = RELAX ? fma(a.a_rel, g[s], a.b_rel * e) : g[s];
                     tile[lidx[s]] = (S)val;
                 }
@@ -689,29 +736,26 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
             S outv[OWN], fbv[OWN];
 #pragma unroll
             for (int i = 0; i < OWN; ++i) {
+                // stage algebra with the host-combined coefficients k[] (see
+                // StageArgs): same terms as the header, regrouped
                 if constexpr (KIND == kStage3) {
                     const double fn = g[i], en = eown[i];
-                    outv[i] = (S)(fn - a.dt * vf[i] - (1.0 - kAlpha) * a.omega * a.a2 * (fn - en));
+                    outv[i] = (S)fma(-a.k[0], fn - en, fma(-a.dt, vf[i], fn));
                     fbv[i] = outv[i];
                 } else if constexpr (KIND == kStage4) {
-                    const double fn = fb[i], en = enown[i];
-                    const double g3 = g[i], e3 = eown[i];
-                    const double dn = fn - en, d3 = g3 - e3;
-                    const double df1 = a.omega * a.a1 * dn;
-                    const double df2 = a.omega * a.a2 * dn;
-                    const double df3 = a.omega * a.a1 * d3;
-                    const double dtvf2 = fn - (1.0 - kAlpha) * df2 - g3;
-                    const double dtvf3 = a.dt * vf[i];
-                    outv[i] = (S)(fn - 0.25 * (dtvf2 + dtvf3) - kBeta * df1 - kEta * df2 - kKappa * df3);
-                    fbv[i] = (S)(fn - (dtvf2 + dtvf3) * (1.0 / 6.0) - (df2 + df3) * (1.0 / 6.0));
+                    const double fn = fb[i], g3 = g[i];
+                    const double dn = fn - enown[i], d3 = g3 - eown[i];
+                    const double s4 = fma(0.75, fn, fma(0.25, g3, fma(a.k[1], dn, fma(-a.k[2], d3, -0.25 * a.dt * vf[i]))));
+                    const double r = fma(5.0 / 6.0, fn, fma(1.0 / 6.0, g3, fma(-a.k[3], dn, fma(-a.k[4], d3, -(1.0 / 6.0) * a.dt * vf[i]))));
+                    outv[i] = (S)s4;
+                    fbv[i] = (S)r;
                 } else {  // kStage5
-                    const double df4 = a.omega * a.a1 * (g[i] - eown[i]);
-                    fbv[i] = (S)(fb[i] - (2.0 / 3.0) * (a.dt * vf[i] + df4));
+                    fbv[i] = (S)fma(-a.k[5], g[i] - eown[i], fma(-(2.0 / 3.0) * a.dt, vf[i], fb[i]));
                     outv[i] = fbv[i];
                 }
             }
             S* op = static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + own0;
-            if (vec) {
+            if constexpr (VEC) {
                 storeN<S, OWN>(op, outv);
             } else {
 #pragma unroll
@@ -720,7 +764,7 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
             }
             if constexpr (KIND == kStage4) {
                 S* fp = static_cast<S*>(a.fbuf) + own0;
-                if (vec) {
+                if constexpr (VEC) {
                     storeN<S, OWN>(fp, fbv);
                 } else {
 #pragma unroll
@@ -728,9 +772,19 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
                         if (row_real && ox0 + i < nx) fp[i] = fbv[i];
                 }
             }
-            const PlaneDesc pd{st.px, st.py, st.m0, st.mx, st.my, st.me, 0, 0, 0, 0};
+            if (st.set() == 0) {
 #pragma unroll
-            for (int i = 0; i < OWN; ++i) acc_add(acc[i], pd, (double)outv[i]);
+                for (int i = 0; i < OWN; ++i) {
+                    const double f = (double)outv[i];
+                    acc[i].s0 += f;
+                    acc[i].sx = fma(st.px, f, acc[i].sx);
+                    acc[i].sy = fma(st.py, f, acc[i].sy);
+                    acc[i].se = fma(fma(st.px, st.px, st.py * st.py), f, acc[i].se);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < OWN; ++i) acc[i].se += (double)outv[i];
+            }
         }
     }
 
@@ -749,6 +803,22 @@ __global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
             }
         }
     }
+}
+
+template <typename S, int KIND, int QM, int TY, int OWN>
+__global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
+    using Sh = Stage2DShape<S, KIND, QM, TY, OWN>;
+    __shared__ S tile[(TY + 10) * Sh::P];
+    __shared__ S vfx[TY * Sh::VP];
+    __shared__ S vfy[TY * Sh::VP];
+    __shared__ double gtab[Sh::TAB ? 8 * Sh::NLOAD : 1];
+    int txi, tyi;
+    if (!tile_of_block(a, txi, tyi)) return;
+    // interior tiles of a grid whose rows are multiples of OWN take the
+    // vector-access path; tiles at a ragged edge the element-wise one
+    const bool vec = ((txi + 1) * Sh::TX <= a.nx) && ((tyi + 1) * TY <= a.ny) && (a.nx % OWN == 0);
+    if (vec) stage2d_body<S, KIND, QM, TY, OWN, true>(a, txi, tyi, tile, vfx, vfy, gtab);
+    else stage2d_body<S, KIND, QM, TY, OWN, false>(a, txi, tyi, tile, vfx, vfy, gtab);
 }
 
 // ---------------------------------------------------------------------------
