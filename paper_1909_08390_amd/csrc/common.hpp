@@ -125,15 +125,20 @@ hipError_t launch_domain_sums(int d, const double* M, long long cells, double dk
                               double* partial, int nblocks, double* out4, hipStream_t s);
 hipError_t launch_check(int d, const double* M, long long cells, int* flag, hipStream_t s);
 
-// Tile shapes (cells) used by the stage kernels: 2D tiles of 64 x kTile2Y
-// cells, kOwn2 consecutive cells per thread (64 kTile2Y / kOwn2 threads).
+// Tile shapes (cells) used by the stage kernels: 2D tiles of kTile2X x
+// kTile2Y cells, kOwn2 consecutive cells per thread (kTile2X kTile2Y / kOwn2
+// threads).  32 x 16 keeps one FP64 work-group under 80 KB of LDS, so two
+// work-groups share a CU and one's barrier waits overlap the other's work.
 #ifndef IMEXLB_TILE2Y
 #define IMEXLB_TILE2Y 16
 #endif
 #ifndef IMEXLB_OWN2
 #define IMEXLB_OWN2 2
 #endif
-constexpr int kTile2X = 64, kTile2Y = IMEXLB_TILE2Y;
+#ifndef IMEXLB_TILE2X
+#define IMEXLB_TILE2X 32
+#endif
+constexpr int kTile2X = IMEXLB_TILE2X, kTile2Y = IMEXLB_TILE2Y;
 constexpr int kOwn2 = IMEXLB_OWN2;
 constexpr int kTile1X = 1024;
 // Tiles are visited in column bands of this many tiles (2D blocking of the

@@ -83,119 +83,100 @@ __device__ __forceinline__ R minmod4(R a, R b, R c, R d) {
     return fmax(mn, R(0)) + fmin(mx, R(0));
 }
 
-// MP-9 interface values along a line (Sec. IV) for an upwind-first window
-// w[0 .. L+8]: the face between window positions m and m+1 (m = 4 .. L+4)
-// is reconstructed from w[m-4 .. m+4] with w[m] the upwind node.  Returns
-// dif[i] = face(5+i) - face(4+i), the flux difference of the node at
-// window position 5+i (divide by delta s, multiply by |p|).
+// MP-9 interface value (Sec. IV) of the face between F_s and F_{s+1} for
+// flow towards +s, from the first differences dd[k] = F_{s-3+k} - F_{s-4+k}
+// (k = 0 .. 7) of the nine upwind-biased nodes.
 //
-// F^L is evaluated in difference form, F_s + sum_j e_j (F_{j+1} - F_j), with
-// e = (-4, 37, -162, 479, 1120, -255, 50, -5)/2520 (the paper's nine weights
-// re-expressed on first differences), so uniform data give F^L = F_s
-// exactly.  When (F^L - F_s)(F^L - F^MP) <= 0 the face is F^L; otherwise it
-// is F^L clipped to [F^min, F^max] (equal to F^L + minmod(F^min - F^L,
-// F^max - F^L), since F^min <= F_s <= F^max).  F^MP = median(F_s, F_{s+1},
-// F^UL) equals F_s + minmod(F_{s+1} - F_s, 4 (F_s - F_{s-1})).  The
-// limiter branch is skipped when no lane of the wavefront needs it.
+// F^L is evaluated in difference form: 2520 (F^L - F_s) = sum_k c_k dd[k]
+// with c = (-4, 37, -162, 479, 1120, -255, 50, -5), the paper's nine weights
+// (times 2520) re-expressed on first differences, so uniform data give
+// F^L = F_s exactly and every weight is a small integer.  F^MP = median(F_s,
+// F_{s+1}, F^UL) with F^UL = F_s + 4 (F_s - F_{s-1}) equals F_s + minmod(
+// F_{s+1} - F_s, 4 (F_s - F_{s-1})), so the monotonicity test
+// (F^L - F_s)(F^L - F^MP) <= 0 needs no median.  When it fails the face is
+// F^L clipped to [F^min, F^max] built from the M4 curvatures.  The clipping
+// work is kept inside its branch (opaque copies of its inputs stop the
+// compiler from hoisting the shared curvatures of neighbouring faces), so a
+// wavefront none of whose lanes needs it skips it.
+template <typename R>
+__device__ __forceinline__ void opaque(R& x) {
+    asm volatile("" : "+v"(x));
+}
+
+template <typename R>
+__device__ __forceinline__ R mp9_face(const R (&dd)[8], R fs, R fp) {
+    R s = R(-4) * dd[0];
+    s = fma(R(37), dd[1], s);
+    s = fma(R(-162), dd[2], s);
+    s = fma(R(479), dd[3], s);
+    s = fma(R(1120), dd[4], s);
+    s = fma(R(-255), dd[5], s);
+    s = fma(R(50), dd[6], s);
+    s = fma(R(-5), dd[7], s);
+    constexpr R inv = R(1.0 / 2520.0);
+    const R t = R(4) * dd[3];                                     // F^UL - F_s
+    const R mm = fmax(fmin(dd[4], t), R(0)) + fmin(fmax(dd[4], t), R(0));  // F^MP - F_s
+    R fl = fma(s, inv, fs);
+    if (s * fma(s, inv, -mm) > R(0)) {
+        R dm2 = dd[2], dm1 = dd[3], d0 = dd[4], dp1 = dd[5], f = fs, g = fp, u = t;
+        opaque(dm2);
+        opaque(dm1);
+        opaque(d0);
+        opaque(dp1);
+        opaque(f);
+        opaque(g);
+        opaque(u);
+        const R cm = dm1 - dm2, c0 = d0 - dm1, cp = dp1 - d0;    // curvatures at s-1, s, s+1
+        const R mdm = minmod4(fma(R(4), cm, -c0), fma(R(4), c0, -cm), cm, c0);  // d^M4 at s-1/2
+        const R md0 = minmod4(fma(R(4), c0, -cp), fma(R(4), cp, -c0), c0, cp);  // d^M4 at s+1/2
+        const R ul = f + u;
+        const R lc = fma(R(4.0 / 3.0), mdm, fma(R(0.5), dm1, f));
+        const R md = fma(R(0.5), d0 - md0, f);
+        const R lo = fmax(fmin(fmin(f, g), md), fmin(fmin(f, ul), lc));
+        const R hi = fmin(fmax(fmax(f, g), md), fmax(fmax(f, ul), lc));
+        fl = fmin(fmax(fl, lo), hi);
+    }
+    return fl;
+}
+
+// MP-9 along a line held in registers, upwind-first window w[0 .. L+8]: the
+// face between window positions m and m+1 (m = 4 .. L+4) is reconstructed
+// from w[m-4 .. m+4] with w[m] the upwind node.  Returns dif[i] = face(5+i)
+// - face(4+i), the flux difference of the node at window position 5+i
+// (divide by delta s, multiply by |p|).
 template <typename R, int L>
 __device__ __forceinline__ void mp9_line(const R (&w)[L + 9], R (&dif)[L]) {
-    constexpr R e0 = R(-4.0 / 2520.0), e1 = R(37.0 / 2520.0), e2 = R(-162.0 / 2520.0),
-                e3 = R(479.0 / 2520.0), e4 = R(1120.0 / 2520.0), e5 = R(-255.0 / 2520.0),
-                e6 = R(50.0 / 2520.0), e7 = R(-5.0 / 2520.0);
     R d[L + 8];
 #pragma unroll
     for (int j = 0; j < L + 8; ++j) d[j] = w[j + 1] - w[j];
-    R fl[L + 1], ul[L + 1];
-    bool need[L + 1];
-    bool slow = false;
-#pragma unroll
-    for (int i = 0; i <= L; ++i) {
-        const int m = i + 4;
-        const R fs = w[m];
-        R s = e0 * d[m - 4];
-        s = fma(e1, d[m - 3], s);
-        s = fma(e2, d[m - 2], s);
-        s = fma(e3, d[m - 1], s);
-        s = fma(e4, d[m], s);
-        s = fma(e5, d[m + 1], s);
-        s = fma(e6, d[m + 2], s);
-        s = fma(e7, d[m + 3], s);
-        fl[i] = fs + s;
-        ul[i] = fma(R(4), d[m - 1], fs);
-        const R fmp = med3(fs, w[m + 1], ul[i]);
-        need[i] = (fl[i] - fs) * (fl[i] - fmp) > R(0);
-        slow |= need[i];
-    }
-    if (slow) {
-        R C[L + 3];  // C_m = d_m - d_{m-1} at m = 3 .. L+5
-#pragma unroll
-        for (int k = 0; k < L + 3; ++k) C[k] = d[k + 3] - d[k + 2];
-        R D[L + 2];  // D(m) = minmod4 over the curvature pair (m, m+1), m = 3 .. L+4
-#pragma unroll
-        for (int k = 0; k < L + 2; ++k)
-            D[k] = minmod4(fma(R(4), C[k], -C[k + 1]), fma(R(4), C[k + 1], -C[k]), C[k], C[k + 1]);
-#pragma unroll
-        for (int i = 0; i <= L; ++i) {
-            const int m = i + 4;
-            const R fs = w[m], fp = w[m + 1];
-            const R lc = fma(R(4.0 / 3.0), D[i], fma(R(0.5), d[m - 1], fs));
-            const R md = fma(R(0.5), d[m] - D[i + 1], fs);
-            const R lo = fmax(fmin(fmin(fs, fp), md), fmin(fmin(fs, ul[i]), lc));
-            const R hi = fmin(fmax(fmax(fs, fp), md), fmax(fmax(fs, ul[i]), lc));
-            const R clipped = fmin(fmax(fl[i], lo), hi);
-            fl[i] = need[i] ? clipped : fl[i];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < L; ++i) dif[i] = fl[i + 1] - fl[i];
-}
-
-// Streaming form of mp9_line for a window held in LDS: window position m is
-// base[m * sd]; the flux difference of the node at position 5 + i is written
-// to out[i * ostep].  Only a 9-value window and 8 differences are live; the
-// limiter (the same two-case rule) is taken per face, skipped by the
-// wavefront when none of its lanes needs it.
-template <typename R, typename S, int L>
-__device__ __forceinline__ void mp9_sweep(const S* base, int sd, R* out, int ostep) {
-    constexpr R e0 = R(-4.0 / 2520.0), e1 = R(37.0 / 2520.0), e2 = R(-162.0 / 2520.0),
-                e3 = R(479.0 / 2520.0), e4 = R(1120.0 / 2520.0), e5 = R(-255.0 / 2520.0),
-                e6 = R(50.0 / 2520.0), e7 = R(-5.0 / 2520.0);
-    R w[L + 9];
-#pragma unroll
-    for (int m = 0; m < L + 9; ++m) w[m] = (R)base[m * sd];
     R prev = R(0);
 #pragma unroll
     for (int i = 0; i <= L; ++i) {
-        const int m = i + 4;
-        // differences d_j = w[j+1] - w[j] for j = m-4 .. m+3 (recomputed: cheap)
-        R d[8];
+        R dd[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) d[k] = w[m - 4 + k + 1] - w[m - 4 + k];
-        const R fs = w[m], fp = w[m + 1];
-        R s = e0 * d[0];
-        s = fma(e1, d[1], s);
-        s = fma(e2, d[2], s);
-        s = fma(e3, d[3], s);
-        s = fma(e4, d[4], s);
-        s = fma(e5, d[5], s);
-        s = fma(e6, d[6], s);
-        s = fma(e7, d[7], s);
-        R fl = fs + s;
-        const R ul = fma(R(4), d[3], fs);
-        const R fmp = med3(fs, fp, ul);
-        if ((fl - fs) * (fl - fmp) > R(0)) {
-            const R cm = d[3] - d[2], c0 = d[4] - d[3], cp = d[5] - d[4];
-            const R dm = minmod4(fma(R(4), cm, -c0), fma(R(4), c0, -cm), cm, c0);
-            const R d0 = minmod4(fma(R(4), c0, -cp), fma(R(4), cp, -c0), c0, cp);
-            const R lc = fma(R(4.0 / 3.0), dm, fma(R(0.5), d[3], fs));
-            const R md = fma(R(0.5), d[4] - d0, fs);
-            const R lo = fmax(fmin(fmin(fs, fp), md), fmin(fmin(fs, ul), lc));
-            const R hi = fmin(fmax(fmax(fs, fp), md), fmax(fmax(fs, ul), lc));
-            fl = fmin(fmax(fl, lo), hi);
-        }
-        if (i > 0) out[(i - 1) * ostep] = fl - prev;
+        for (int k = 0; k < 8; ++k) dd[k] = d[i + k];
+        const R fl = mp9_face<R>(dd, w[i + 4], w[i + 5]);
+        if (i > 0) dif[i - 1] = fl - prev;
         prev = fl;
     }
+}
+
+// mp9_line over a window held in LDS.  lo points at the lowest address of
+// the L + 9 window elements, STRIDE apart; FWD: window position m is
+// lo[m STRIDE] (flow towards higher addresses), else lo[(L + 8 - m) STRIDE].
+// The flux difference of the node at window position 5 + i goes to
+// out[i OSTRIDE] (FWD) or out[(L - 1 - i) OSTRIDE], i.e. out addresses the
+// node of lowest address either way.  All offsets are compile-time
+// constants.
+template <typename R, typename S, int L, int STRIDE, int OSTRIDE, bool FWD>
+__device__ __forceinline__ void mp9_sweep(const S* lo, R* out) {
+    R w[L + 9];
+#pragma unroll
+    for (int m = 0; m < L + 9; ++m) w[m] = (R)lo[(FWD ? m : L + 8 - m) * STRIDE];
+    R dif[L];
+    mp9_line<R, L>(w, dif);
+#pragma unroll
+    for (int i = 0; i < L; ++i) out[(FWD ? i : L - 1 - i) * OSTRIDE] = dif[i];
 }
 
 template <typename S>
@@ -394,13 +375,16 @@ __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& 
 }
 
 // ---------------------------------------------------------------------------
-// Two-dimensional stage pass.  Tile of 64 x TY cells, 16 TY threads.
-//  - own cells: thread t owns the 4 consecutive cells (4 (t % 16) .. +3) of
-//    row t / 16 (vector loads/stores, FP64 moment accumulators);
-//  - loaded cells: own cells plus the 5-cell cross halo (10 TY + 640 cells),
-//    spread over the threads; each is relaxed on read into the LDS tile;
-//  - sweeps: threads t < 8 TY slide the MP-9 window along x over 8 cells of a
-//    row, the others along y over 8 cells of a column;
+// Two-dimensional stage pass.  Tile of TX x TY cells, TX TY / OWN threads.
+//  - own cells: thread t owns the OWN consecutive cells (OWN (t % (TX/OWN))
+//    .. +OWN-1) of row t / (TX/OWN) (vector loads/stores on interior tiles,
+//    FP64 moment accumulators);
+//  - loaded cells: own cells plus the 5-cell cross halo (10 TY + 10 TX
+//    cells), spread over the threads; each is relaxed on read into the LDS
+//    tile;
+//  - sweeps: the first half of the threads slides the MP-9 window along x
+//    over L = 2 OWN cells of a row, the second half along y over L cells of
+//    a column;
 //  - per plane: fill LDS (next plane's global loads already in flight),
 //    barrier, sweeps, barrier, pointwise stage algebra + stores + moments.
 // LDS pitches are odd so the row-strided x windows and the column-strided
@@ -408,7 +392,7 @@ __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& 
 // ---------------------------------------------------------------------------
 template <typename S, int KIND, int QM, int TY, int OWN>
 struct Stage2DShape {
-    static constexpr int TX = 64, NT = TX * TY / OWN, L = 2 * OWN;
+    static constexpr int TX = kTile2X, NT = TX * TY / OWN, L = 2 * OWN;
     static constexpr int OPR = TX / OWN;          // threads per tile row
     static constexpr int P = TX + 11;             // tile pitch (odd)
     static constexpr int VP = TX + 1;             // VF buffer pitch (odd)
@@ -694,24 +678,22 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
         }
         __syncthreads();
 
-        if (tid < NT / 2) {  // x sweep: row tid % TY, cells 8 (tid / TY) .. +7
+        if (tid < NT / 2) {  // x sweep: row tid % TY, cells L (tid / TY) .. +L-1
             if (st.px != 0.0) {
                 const int row = tid % TY, seg = tid / TY;
-                const bool fwd = st.px > 0.0;
-                const S* base = tile + (row + 5) * P + seg * L + (fwd ? 0 : L + 9);
+                const S* lo = tile + (row + 5) * P + seg * L;
                 R* o = vfx + row * VP + seg * L;
-                if (fwd) mp9_sweep<R, S, L>(base, 1, o, 1);
-                else mp9_sweep<R, S, L>(base, -1, o + L - 1, -1);
+                if (st.px > 0.0) mp9_sweep<R, S, L, 1, 1, true>(lo, o);
+                else mp9_sweep<R, S, L, 1, 1, false>(lo + 1, o);
             }
-        } else {             // y sweep: column (tid - NT/2) % 64, cells 8 seg .. +7
+        } else {             // y sweep: column (tid - NT/2) % TX, cells L seg .. +L-1
             if (st.py != 0.0) {
                 const int i2 = tid - NT / 2;
                 const int col = i2 % TX, seg = i2 / TX;
-                const bool fwd = st.py > 0.0;
-                const S* base = tile + (seg * L + (fwd ? 0 : L + 9)) * P + col + 5;
+                const S* lo = tile + seg * L * P + col + 5;
                 R* o = vfy + seg * L * VP + col;
-                if (fwd) mp9_sweep<R, S, L>(base, P, o, VP);
-                else mp9_sweep<R, S, L>(base, -P, o + (L - 1) * VP, -VP);
+                if (st.py > 0.0) mp9_sweep<R, S, L, P, VP, true>(lo, o);
+                else mp9_sweep<R, S, L, P, VP, false>(lo + P, o);
             }
         }
         __syncthreads();
@@ -806,7 +788,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
 }
 
 template <typename S, int KIND, int QM, int TY, int OWN>
-__global__ void __launch_bounds__(64 * TY / OWN) stage2d_kernel(StageArgs a) {
+__global__ void __launch_bounds__(kTile2X * TY / OWN) stage2d_kernel(StageArgs a) {
     using Sh = Stage2DShape<S, KIND, QM, TY, OWN>;
     __shared__ S tile[(TY + 10) * Sh::P];
     __shared__ S vfx[TY * Sh::VP];
@@ -1159,7 +1141,7 @@ hipError_t launch_stage_t(int d, const StageArgs& a, hipStream_t s) {
     const int grid = 8 * ((ntiles + 7) / 8);
     if (d == 2) {
         constexpr int TY = kTile2Y, OWN = kOwn2;
-        constexpr int NT = 64 * TY / OWN;
+        constexpr int NT = kTile2X * TY / OWN;
         if (a.qm == 16)
             hipLaunchKernelGGL((stage2d_kernel<S, KIND, 16, TY, OWN>), dim3(grid), dim3(NT), 0, s, a);
         else
