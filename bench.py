@@ -14,6 +14,9 @@ the dominant pass, and the FP64 CPU oracle timed on a bounded patch.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +29,9 @@ if ROOT not in sys.path:
 PMAX8 = 4.144547186125894  # largest root of He_8
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E spec peak
 METRIC = "velocity-node updates/s per IMEX step, FP32 vs FP64, % of HBM roofline"
+# Kernel sources whose hash ties a committed counter summary to the code it measured.
+KERNEL_SOURCES = ("paper_1909_08390_amd/csrc/kernels.hip", "paper_1909_08390_amd/csrc/common.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_passes_riemann4096_hbm_traffic.txt")
 
 
 def log(*a):
@@ -38,6 +44,56 @@ def pass_bytes(planes, cells, elem, nf):
     ps = planes * cells * elem
     ms = nf * cells * 8
     return {"stage3": 2 * ps + 2 * ms, "stage4": 4 * ps + 3 * ms, "stage5": 3 * ps + 2 * ms}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(size):
+    """HBM bytes per launch of each stage pass from the committed counter
+    summary, keyed "f64 stage4" etc.; empty when the summary is missing, was
+    taken at another size or on other kernel sources."""
+    out = {}
+    if not os.path.exists(TRAFFIC_FILE):
+        return out
+    meta = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("source_sha256:"):
+                meta["sha"] = line.split(":", 1)[1].strip()
+            elif line.startswith("size:"):
+                meta["size"] = int(line.split(":", 1)[1])
+            elif line.startswith("pass "):
+                # pass <prec> <stage>: fetch_kib=.. write_kib=.. traffic_bytes=..
+                head, tail = line.split(":", 1)
+                _, prec, stage = head.split()
+                kv = dict(t.split("=") for t in tail.split())
+                out[f"{prec} {stage}"] = float(kv["traffic_bytes"])
+    if meta.get("sha") != kernel_source_hash() or meta.get("size") != size:
+        return {}
+    return out
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size (read mib MiB, write mib
+    MiB), the reference for the HBM byte counters."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"bench: copy calibration, 3 copies of {mib} MiB ({mib * (1 << 20)} bytes read + written)")
+    del src, dst
+    torch.cuda.empty_cache()
 
 
 def run_precision(I, W, N, storage, steps, warmup, seed):
@@ -75,10 +131,15 @@ def run_precision(I, W, N, storage, steps, warmup, seed):
         "seed_offset": k,
     }
     gbs4 = pb["stage4"] / (per["stage4"] * 1e-3) / 1e9
+    prec = "f32" if elem == 4 else "f64"
+    traffic = read_traffic(N).get(f"{prec} stage4")
     res["roofline"] = {"bound": "hbm", "kernel": "stage4 (stage2d_kernel<%s, 4>)" %
                        ("float" if elem == 4 else "double"),
                        "achieved": gbs4, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": gbs4 / HBM_PEAK_GBS, "traffic": None}
+                       "frac": gbs4 / HBM_PEAK_GBS, "traffic": traffic,
+                       "algorithmic_bytes_per_launch": pb["stage4"],
+                       "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                       "copy-calibrated)"}
     del s
     torch.cuda.empty_cache()
     return res, cfg, fields
@@ -102,6 +163,93 @@ def cpu_baseline(O, W, cfg, fields, side, steps):
                       f"IMEX step(s), single-threaded C (-O2), {dt:.1f} s"}
 
 
+def _kernel_key(name):
+    """("f64"|"f32", "stage3"|..) for a stage kernel name, else None."""
+    if "stage2d_kernel<" not in name and "stage1d_kernel<" not in name:
+        return None
+    args = name.split("<", 1)[1].split(">")[0].split(",")
+    prec = "f32" if args[0].strip() == "float" else "f64"
+    return prec, "stage" + args[1].strip()
+
+
+def summarize_stats(dirs, cmd):
+    """Text summary of rocprofv3 --kernel-trace --stats CSVs."""
+    rows = []
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
+            with open(f) as fh:
+                rows += list(csv.DictReader(fh))
+    print("# rocprofv3 kernel statistics (per-kernel launch durations)")
+    print(f"# command: {cmd}")
+    print(f"# kernel sources: source_sha256: {kernel_source_hash()}")
+    print(f"{'kernel':64s} {'calls':>6s} {'avg_ms':>10s} {'min_ms':>10s} {'max_ms':>10s} {'total_ms':>10s}")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"].replace("imexlb::(anonymous namespace)::", "")
+        if len(name) > 64:
+            name = name[:61] + "..."
+        print(f"{name:64s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e6:10.4f} "
+              f"{float(r['MinNs']) / 1e6:10.4f} {float(r['MaxNs']) / 1e6:10.4f} "
+              f"{float(r['TotalDurationNs']) / 1e6:10.3f}")
+
+
+def _pmc_dispatches(d, counter):
+    """{kernel name: [value of counter per dispatch]} from a --pmc run."""
+    acc = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                per = acc.setdefault(r["Kernel_Name"], {})
+                per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return {k: list(v.values()) for k, v in acc.items()}
+
+
+def _calib(vals):
+    """Mean counter value of the calibration copies: the copy dispatches of
+    at least half the largest one (small runtime copies are left out)."""
+    top = max(vals)
+    big = [v for v in vals if v >= 0.5 * top]
+    return sum(big) / len(big), len(big)
+
+
+def summarize_pmc(fetch_dir, write_dir, copy_mib, size, cmds):
+    """HBM traffic per launch of the stage passes from FETCH_SIZE and
+    WRITE_SIZE runs (KiB per dispatch), each scaled by the same counter on a
+    plain copy of copy_mib MiB."""
+    fetch_d = _pmc_dispatches(fetch_dir, "FETCH_SIZE")
+    write_d = _pmc_dispatches(write_dir, "WRITE_SIZE")
+    cb = copy_mib * (1 << 20)
+    copies = [k for k in fetch_d if "copy" in k.lower() and k in write_d]
+    ck = max(copies, key=lambda k: max(fetch_d[k]))
+    cf, nf = _calib(fetch_d[ck])
+    cw, nw = _calib(write_d[ck])
+    ff = cb / (cf * 1024.0)
+    fw = cb / (cw * 1024.0)
+    fetch = {k: sum(v) / len(v) for k, v in fetch_d.items()}
+    write = {k: sum(v) / len(v) for k, v in write_d.items()}
+    cells = size * size
+    print("# HBM traffic of the stage passes, 2D Riemann workload, "
+          f"{size}x{size} cells x 128 planes")
+    for c in cmds:
+        print(f"# command: {c}")
+    print(f"source_sha256: {kernel_source_hash()}")
+    print(f"size: {size}")
+    print(f"copy_kernel: {ck[:90]}")
+    print(f"copy_bytes: {cb}  copy_fetch_kib: {cf:.1f} (mean of {nf})  "
+          f"copy_write_kib: {cw:.1f} (mean of {nw})")
+    print(f"fetch_factor: {ff:.4f}  write_factor: {fw:.4f}")
+    for k in sorted(fetch):
+        key = _kernel_key(k)
+        if key is None or k not in write:
+            continue
+        prec, stage = key
+        t = fetch[k] * 1024.0 * ff + write[k] * 1024.0 * fw
+        alg = pass_bytes(128, cells, 4 if prec == "f32" else 8, 4)[stage]
+        print(f"pass {prec} {stage}: fetch_kib={fetch[k]:.1f} write_kib={write[k]:.1f} "
+              f"traffic_bytes={t:.4e} algorithmic_bytes={alg:.4e} ratio={t / alg:.3f}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,8 +260,24 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="first run a plain copy of MIB MiB (counter calibration)")
+    ap.add_argument("--summarize-stats", nargs="+", metavar="DIR",
+                    help="print a summary of rocprofv3 --stats CSVs and exit")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the HBM traffic summary of two --pmc runs and exit")
+    ap.add_argument("--cmd", action="append", default=[],
+                    help="command line recorded in a summary")
     args = ap.parse_args()
+
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats, " ; ".join(args.cmd))
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.copy_calib, args.size,
+                      args.cmd)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU figures are not "
@@ -127,6 +291,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        copy_calibration(args.copy_calib)
     log(f"bench: {args.size}^2 cells x 128 planes, FP64, {args.warmup} warmup + {args.steps} steps")
     r64, cfg, fields = run_precision(I, W, args.size, I.F64, args.steps, args.warmup, args.seed)
     log(f"bench: FP64 {r64['value']:.3e} VN/s, {r64['ms_per_step']:.2f} ms/step, passes {r64['pass_ms']}")
