@@ -53,7 +53,8 @@ typedef enum { IMEXLB_F64 = 0, IMEXLB_F32 = 1 } imexlb_storage;
  * in units of the domain size (Sec. II, non-dimensionalisation). */
 typedef struct {
     int d;              /* 1 or 2                                              */
-    int nx, ny;         /* cells per axis; ny must be 1 when d = 1             */
+    int nx, ny;         /* cells per axis; ny must be 1 when d = 1; one plane
+                           ((ny + 16) nx elements) must stay below 2 GiB       */
     double lx, ly;      /* domain lengths (> 0); ly ignored when d = 1         */
     int q_phi, q_chi;   /* Gauss-Hermite order per axis: 3 <= q_phi <= 16,
                            1 <= q_chi <= 16 (energy is exact only from q_phi = 3,

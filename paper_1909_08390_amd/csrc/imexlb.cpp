@@ -139,6 +139,14 @@ imexlb_status validate(const imexlb_config* c, std::string& why) {
     if (c->bc_x != IMEXLB_OUTFLOW && c->bc_x != IMEXLB_PERIODIC) { why = "bad bc_x"; return IMEXLB_EINVAL; }
     if (c->d == 2 && c->bc_y != IMEXLB_OUTFLOW && c->bc_y != IMEXLB_PERIODIC) { why = "bad bc_y"; return IMEXLB_EINVAL; }
     if (c->storage != IMEXLB_F64 && c->storage != IMEXLB_F32) { why = "bad storage"; return IMEXLB_EINVAL; }
+    {
+        // planes are addressed with 32-bit byte offsets (one tile row of slack)
+        const long long elem = c->storage == IMEXLB_F32 ? 4 : 8;
+        if (((long long)c->ny + kTile2Y) * c->nx * elem >= (1LL << 31)) {
+            why = "one plane must stay below 2 GiB";
+            return IMEXLB_EINVAL;
+        }
+    }
     return IMEXLB_OK;
 }
 

@@ -103,8 +103,11 @@ __device__ __forceinline__ void opaque(R& x) {
     asm volatile("" : "+v"(x));
 }
 
+// Linear part and monotonicity test of one face: returns F^L and sets q,
+// positive when the face must be clipped (q = (F^L - F_s)(F^L - F^MP)
+// times 2520), and t = 4 (F_s - F_{s-1}) = F^UL - F_s.
 template <typename R>
-__device__ __forceinline__ R mp9_face(const R (&dd)[8], R fs, R fp) {
+__device__ __forceinline__ R mp9_face_linear(const R (&dd)[8], R fs, R& t, R& q) {
     R s = R(-4) * dd[0];
     s = fma(R(37), dd[1], s);
     s = fma(R(-162), dd[2], s);
@@ -114,28 +117,39 @@ __device__ __forceinline__ R mp9_face(const R (&dd)[8], R fs, R fp) {
     s = fma(R(50), dd[6], s);
     s = fma(R(-5), dd[7], s);
     constexpr R inv = R(1.0 / 2520.0);
-    const R t = R(4) * dd[3];                                     // F^UL - F_s
+    t = R(4) * dd[3];
     const R mm = fmax(fmin(dd[4], t), R(0)) + fmin(fmax(dd[4], t), R(0));  // F^MP - F_s
-    R fl = fma(s, inv, fs);
-    if (s * fma(s, inv, -mm) > R(0)) {
-        R dm2 = dd[2], dm1 = dd[3], d0 = dd[4], dp1 = dd[5], f = fs, g = fp, u = t;
-        opaque(dm2);
-        opaque(dm1);
-        opaque(d0);
-        opaque(dp1);
-        opaque(f);
-        opaque(g);
-        opaque(u);
-        const R cm = dm1 - dm2, c0 = d0 - dm1, cp = dp1 - d0;    // curvatures at s-1, s, s+1
-        const R mdm = minmod4(fma(R(4), cm, -c0), fma(R(4), c0, -cm), cm, c0);  // d^M4 at s-1/2
-        const R md0 = minmod4(fma(R(4), c0, -cp), fma(R(4), cp, -c0), c0, cp);  // d^M4 at s+1/2
-        const R ul = f + u;
-        const R lc = fma(R(4.0 / 3.0), mdm, fma(R(0.5), dm1, f));
-        const R md = fma(R(0.5), d0 - md0, f);
-        const R lo = fmax(fmin(fmin(f, g), md), fmin(fmin(f, ul), lc));
-        const R hi = fmin(fmax(fmax(f, g), md), fmax(fmax(f, ul), lc));
-        fl = fmin(fmax(fl, lo), hi);
-    }
+    q = s * fma(s, inv, -mm);
+    return fma(s, inv, fs);
+}
+
+// The clipped face value: F^L limited to [F^min, F^max].
+template <typename R>
+__device__ __forceinline__ R mp9_face_clip(const R (&dd)[8], R fs, R fp, R t, R fl) {
+    R dm2 = dd[2], dm1 = dd[3], d0 = dd[4], dp1 = dd[5], f = fs, g = fp, u = t;
+    opaque(dm2);
+    opaque(dm1);
+    opaque(d0);
+    opaque(dp1);
+    opaque(f);
+    opaque(g);
+    opaque(u);
+    const R cm = dm1 - dm2, c0 = d0 - dm1, cp = dp1 - d0;    // curvatures at s-1, s, s+1
+    const R mdm = minmod4(fma(R(4), cm, -c0), fma(R(4), c0, -cm), cm, c0);  // d^M4 at s-1/2
+    const R md0 = minmod4(fma(R(4), c0, -cp), fma(R(4), cp, -c0), c0, cp);  // d^M4 at s+1/2
+    const R ul = f + u;
+    const R lc = fma(R(4.0 / 3.0), mdm, fma(R(0.5), dm1, f));
+    const R md = fma(R(0.5), d0 - md0, f);
+    const R lo = fmax(fmin(fmin(f, g), md), fmin(fmin(f, ul), lc));
+    const R hi = fmin(fmax(fmax(f, g), md), fmax(fmax(f, ul), lc));
+    return fmin(fmax(fl, lo), hi);
+}
+
+template <typename R>
+__device__ __forceinline__ R mp9_face(const R (&dd)[8], R fs, R fp) {
+    R t, q;
+    R fl = mp9_face_linear<R>(dd, fs, t, q);
+    if (q > R(0)) fl = mp9_face_clip<R>(dd, fs, fp, t, fl);
     return fl;
 }
 
@@ -143,22 +157,39 @@ __device__ __forceinline__ R mp9_face(const R (&dd)[8], R fs, R fp) {
 // face between window positions m and m+1 (m = 4 .. L+4) is reconstructed
 // from w[m-4 .. m+4] with w[m] the upwind node.  Returns dif[i] = face(5+i)
 // - face(4+i), the flux difference of the node at window position 5+i
-// (divide by delta s, multiply by |p|).
+// (divide by delta s, multiply by |p|).  The linear parts of all L + 1 faces
+// are evaluated first (independent chains the scheduler interleaves), then
+// the clipping of each face that needs it.
 template <typename R, int L>
 __device__ __forceinline__ void mp9_line(const R (&w)[L + 9], R (&dif)[L]) {
     R d[L + 8];
 #pragma unroll
     for (int j = 0; j < L + 8; ++j) d[j] = w[j + 1] - w[j];
-    R prev = R(0);
+    R fl[L + 1], t[L + 1], q[L + 1];
 #pragma unroll
     for (int i = 0; i <= L; ++i) {
         R dd[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) dd[k] = d[i + k];
-        const R fl = mp9_face<R>(dd, w[i + 4], w[i + 5]);
-        if (i > 0) dif[i - 1] = fl - prev;
-        prev = fl;
+        fl[i] = mp9_face_linear<R>(dd, w[i + 4], t[i], q[i]);
     }
+    // keep every linear part ahead of the first branch
+#pragma unroll
+    for (int i = 0; i <= L; ++i) {
+        opaque(fl[i]);
+        opaque(q[i]);
+    }
+#pragma unroll
+    for (int i = 0; i <= L; ++i) {
+        if (q[i] > R(0)) {
+            R dd[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) dd[k] = d[i + k];
+            fl[i] = mp9_face_clip<R>(dd, w[i + 4], w[i + 5], t[i], fl[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) dif[i] = fl[i + 1] - fl[i];
 }
 
 // mp9_line over a window held in LDS.  lo points at the lowest address of
@@ -238,6 +269,63 @@ __device__ __forceinline__ void storeN(S* p, const S* o) {
         v.w = o[3];
     }
     *reinterpret_cast<typename VecN<S, N>::T*>(p) = v;
+}
+
+// Raw buffer access to one plane: the plane base sits in SGPRs (a buffer
+// resource built per plane with scalar arithmetic) and each lane supplies a
+// 32-bit byte offset, so the per-plane address work is scalar.  Offsets
+// outside the plane read 0 and drop stores (hardware range check); the host
+// keeps every plane below 2^31 bytes.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format
+
+template <typename S>
+__device__ __forceinline__ Rsrc plane_rsrc(const S* p, long long cells) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(p), 0, (int)(cells * (long long)sizeof(S)),
+                                             kRawBufferWord3);
+}
+
+template <typename S>
+__device__ __forceinline__ double bload1(Rsrc r, int off) {
+    if constexpr (sizeof(S) == 8)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else
+        return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Two consecutive elements as one access.
+template <typename S>
+__device__ __forceinline__ void bload2(Rsrc r, int off, double* o) {
+    if constexpr (sizeof(S) == 8) {
+        const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+        o[0] = v.x;
+        o[1] = v.y;
+    } else {
+        const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void bstore1(Rsrc r, int off, S v) {
+    if constexpr (sizeof(S) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+
+template <typename S>
+__device__ __forceinline__ void bstore2(Rsrc r, int off, const S* v) {
+    if constexpr (sizeof(S) == 8) {
+        const double2 x = {v[0], v[1]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), r, off, 0, 0);
+    } else {
+        const float2 x = {v[0], v[1]};
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, off, 0, 0);
+    }
 }
 
 // Moments accumulated per cell in FP64 (Sec. II, Eq. Moments_discrete).
@@ -520,25 +608,31 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     for (int i = 0; i < OWN; ++i) acc[i] = Acc{0.0, 0.0, 0.0, 0.0};
 
     // Global loads of one plane: the source plane at the loaded cells and,
-    // for stages 4 and 5, the state buffer at the own cells.
+    // for stages 4 and 5, the state buffer at the own cells (byte offsets
+    // within the plane; own cells of interior tiles as one vector access).
+    static_assert(OWN == 2, "vector accesses assume two own cells");
+    int boff[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) boff[s] = gcell[s] * (int)sizeof(S);
+    const int own_off = (oy * nx + ox0) * (int)sizeof(S);
     double pg[NS], pf[OWN];
     auto fetch = [&](int v) {
-        const S* __restrict__ sv = static_cast<const S*>(a.src) + (size_t)v * ps;
+        const Rsrc rs = plane_rsrc(static_cast<const S*>(a.src) + (size_t)v * ps, ps);
         if constexpr (VEC) {
-            loadN<S, OWN>(sv + gcell[0], pg);
+            bload2<S>(rs, boff[0], pg);
         } else {
 #pragma unroll
-            for (int i = 0; i < OWN; ++i) pg[i] = sv[gcell[i]];
+            for (int i = 0; i < OWN; ++i) pg[i] = bload1<S>(rs, boff[i]);
         }
 #pragma unroll
-        for (int jh = 0; jh < HS; ++jh) pg[OWN + jh] = (double)sv[gcell[OWN + jh]];
+        for (int jh = 0; jh < HS; ++jh) pg[OWN + jh] = bload1<S>(rs, boff[OWN + jh]);
         if constexpr (KIND == kStage4 || KIND == kStage5) {
-            const S* fbp = static_cast<const S*>(a.fbuf) + (size_t)v * ps;
+            const Rsrc rf = plane_rsrc(static_cast<const S*>(a.fbuf) + (size_t)v * ps, ps);
             if constexpr (VEC) {
-                loadN<S, OWN>(fbp + gcell[0], pf);
+                bload2<S>(rf, boff[0], pf);
             } else {
 #pragma unroll
-                for (int i = 0; i < OWN; ++i) pf[i] = fbp[gcell[i]];
+                for (int i = 0; i < OWN; ++i) pf[i] = bload1<S>(rf, boff[i]);
             }
         }
     };
@@ -736,22 +830,22 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                     outv[i] = fbv[i];
                 }
             }
-            S* op = static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + own0;
+            const Rsrc ro = plane_rsrc(static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + (size_t)st.v * ps, ps);
             if constexpr (VEC) {
-                storeN<S, OWN>(op, outv);
+                bstore2<S>(ro, own_off, outv);
             } else {
 #pragma unroll
                 for (int i = 0; i < OWN; ++i)
-                    if (row_real && ox0 + i < nx) op[i] = outv[i];
+                    if (row_real && ox0 + i < nx) bstore1<S>(ro, own_off + i * (int)sizeof(S), outv[i]);
             }
             if constexpr (KIND == kStage4) {
-                S* fp = static_cast<S*>(a.fbuf) + own0;
+                const Rsrc rf = plane_rsrc(static_cast<S*>(a.fbuf) + (size_t)st.v * ps, ps);
                 if constexpr (VEC) {
-                    storeN<S, OWN>(fp, fbv);
+                    bstore2<S>(rf, own_off, fbv);
                 } else {
 #pragma unroll
                     for (int i = 0; i < OWN; ++i)
-                        if (row_real && ox0 + i < nx) fp[i] = fbv[i];
+                        if (row_real && ox0 + i < nx) bstore1<S>(rf, own_off + i * (int)sizeof(S), fbv[i]);
                 }
             }
             if (st.set() == 0) {
@@ -788,7 +882,8 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
 }
 
 template <typename S, int KIND, int QM, int TY, int OWN>
-__global__ void __launch_bounds__(kTile2X * TY / OWN) stage2d_kernel(StageArgs a) {
+__global__ void __launch_bounds__(kTile2X * TY / OWN) __attribute__((amdgpu_waves_per_eu(2)))
+stage2d_kernel(StageArgs a) {
     using Sh = Stage2DShape<S, KIND, QM, TY, OWN>;
     __shared__ S tile[(TY + 10) * Sh::P];
     __shared__ S vfx[TY * Sh::VP];
