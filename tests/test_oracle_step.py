@@ -13,9 +13,11 @@ import pytest
 import oracle as O
 from paper_1909_08390_amd import workloads as W
 
+from golden_data import table1
 from riemann_exact import sample as riemann_sample
 
-ALPHA, BETA, ETA = 0.24169426078821, 0.06042356519705, 0.12915286960590
+# Table I constants as printed (tests/golden/table1_imex_ssp3_433.txt)
+ALPHA, BETA, ETA = (table1()[k] for k in ("alpha", "beta", "eta"))
 
 
 def stability_function(z):
