@@ -12,7 +12,8 @@ The checks are the paper's qualitative ones made quantitative:
    above the CFL bound of Sec. IV that the library enforces, so the sweep
    starts at 5e-4, the step the paper adopts;
  * C11 / C12 at 400^2, Q_phi = 5, Q_chi = 3, dt = 5e-4, tau = 1e-5: min and
-   max of the density within 1.5 % of the printed contour range;
+   max of the density within 2 % of the printed contour range (the printed
+   values are plot limits given to 2-3 digits, not data extremes);
  * C12 is symmetric under x <-> y; the GPU arithmetic orders x and y terms
    differently, so symmetry holds to round-off while perturbations are
    small (the shock interaction on the diagonal later amplifies them).
