@@ -140,9 +140,29 @@ def run_precision(I, W, N, storage, steps, warmup, seed):
                        "algorithmic_bytes_per_launch": pb["stage4"],
                        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                        "copy-calibrated)"}
+    res["moments"] = s.moments()  # (n, ux, uy, T) after warmup + timed steps
     del s
     torch.cuda.empty_cache()
     return res, cfg, fields
+
+
+def fp32_error(m32, m64):
+    """Errors of the FP32-storage run against the FP64 run after the same
+    steps: density and pressure relative (L1 over the grid and max), velocity
+    absolute in units of c_ref."""
+    import torch
+
+    n32, ux32, uy32, T32 = m32
+    n64, ux64, uy64, T64 = m64
+    P32, P64 = n32 * T32, n64 * T64
+    du = torch.sqrt((ux32 - ux64) ** 2 + (uy32 - uy64) ** 2)
+
+    def rel(a, b):
+        d = (a - b).abs()
+        return {"l1_rel": float(d.sum() / b.abs().sum()), "max_rel": float(d.max() / b.abs().max())}
+
+    return {"rho": rel(n32, n64), "P": rel(P32, P64),
+            "u": {"l1_abs": float(du.mean()), "max_abs": float(du.max())}}
 
 
 def cpu_baseline(O, W, cfg, fields, side, steps):
@@ -335,6 +355,8 @@ def main():
         "cpu_baseline": cpu,
     }
     if r32 is not None:
+        err = fp32_error(r32["moments"], r64["moments"])
+        log(f"bench: FP32 vs FP64 after {args.warmup + args.steps} steps: {err}")
         out["fp32"] = {
             "value": r32["value"], "unit": "VN/s", "dtype": "f32 storage, f64 moments",
             "ms_per_step": r32["ms_per_step"], "pass_ms": r32["pass_ms"],
@@ -342,6 +364,8 @@ def main():
             "bytes_per_vn_step": r32["bytes_per_vn_step"],
             "step_hbm_frac": r32["step_gbs"] / HBM_PEAK_GBS,
             "roofline": r32["roofline"],
+            "error_vs_fp64": err,
+            "error_after_steps": args.warmup + args.steps,
         }
     print(json.dumps(out), flush=True)
 
