@@ -146,6 +146,86 @@ imexlb_status imexlb_check_state(const imexlb_ctx* ctx);
 const char* imexlb_status_string(imexlb_status s);
 const char* imexlb_last_error(const imexlb_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent 1D problems (shock tubes) of uneven size.
+ *
+ * Every tube is a d = 1 problem of the model above with its own cell count,
+ * length, K (so its own adiabatic index, Sec. II), tau, dt and boundary
+ * rule; all tubes share one velocity quadrature and one storage type.  One
+ * IMEX step of the whole batch is three launches (one per fused pass), each
+ * covering every tile of every tube; the tile width is chosen by
+ * imexlb_batch_tune() or set directly.
+ *
+ * Layout.  Tube i's plane-set starts at element state_offset[i] of the
+ * state buffer (multiples of 64 elements) and holds Q planes of nx_i cells,
+ * F_i[v][x], Q = q_phi + q_chi, plane order as above.  Macroscopic fields
+ * are FP64 arrays over all cells of all tubes: tube i's cells sit at
+ * cell_offset[i] .. cell_offset[i] + nx_i - 1 of an array of
+ * imexlb_batch_cells() values.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int nx;             /* cells (>= 1)                                        */
+    int K;              /* internal degrees of freedom (>= 0)                  */
+    double lx;          /* length (> 0)                                        */
+    double tau, dt;     /* relaxation time and time step (> 0; CFL <= 1)       */
+    int bc;             /* imexlb_bc at both ends                              */
+} imexlb_tube;
+
+typedef struct imexlb_batch imexlb_batch;
+
+/* Validate the tubes (same rules as imexlb_create per tube), build the
+ * shared quadrature tables and the tile table.  q_phi, q_chi and storage as
+ * in imexlb_config.  On success *out owns the batch.  Errors: EINVAL
+ * (count < 1, a bad tube, bad orders or storage), ENOMEM, EHIP. */
+imexlb_status imexlb_batch_create(const imexlb_tube* tubes, int count, int q_phi, int q_chi,
+                                  int storage, void* hip_stream, imexlb_batch** out);
+void imexlb_batch_destroy(imexlb_batch* b);
+imexlb_status imexlb_batch_set_stream(imexlb_batch* b, void* hip_stream);
+
+/* Sizes in bytes of the state and workspace buffers, the total cell count
+ * and the per-tube offsets (host arrays of count elements, either may be
+ * NULL). */
+size_t imexlb_batch_state_bytes(const imexlb_batch* b);
+size_t imexlb_batch_workspace_bytes(const imexlb_batch* b);
+long long imexlb_batch_cells(const imexlb_batch* b);
+imexlb_status imexlb_batch_layout(const imexlb_batch* b, long long* state_offset, long long* cell_offset);
+
+/* Hand over caller-owned device buffers (256-byte aligned). */
+imexlb_status imexlb_batch_bind(imexlb_batch* b, void* d_state, void* d_workspace);
+
+/* Every tube at its local equilibrium of the given fields (device arrays of
+ * imexlb_batch_cells() doubles): n, u, T. */
+imexlb_status imexlb_batch_set_equilibrium(imexlb_batch* b, const double* d_n, const double* d_u,
+                                           const double* d_T);
+/* Recompute the moments after the caller wrote the state buffer directly. */
+imexlb_status imexlb_batch_state_changed(imexlb_batch* b);
+
+/* nsteps IMEX steps of every tube (each with its own dt).  Asynchronous.
+ * The timed form synchronises and adds the milliseconds of passes 3, 4, 5
+ * (HIP events around each batched launch) to ms[0..2]. */
+imexlb_status imexlb_batch_step(imexlb_batch* b, int nsteps);
+imexlb_status imexlb_batch_step_timed(imexlb_batch* b, int nsteps, double ms[3]);
+
+/* Moments (n, u, T) of the current state, device arrays of
+ * imexlb_batch_cells() doubles. */
+imexlb_status imexlb_batch_moments(const imexlb_batch* b, double* d_n, double* d_u, double* d_T);
+
+/* Tile width (cells per work-group: 256, 512 or 1024) and tile order
+ * (0: tube by tube, 1: longest tubes first) of the batched launches. */
+imexlb_status imexlb_batch_set_tiling(imexlb_batch* b, int tile, int order);
+imexlb_status imexlb_batch_get_tiling(const imexlb_batch* b, int* tile, int* order);
+
+/* Autotuner: time every (tile, order) candidate over nsteps steps (after one
+ * untimed step) on the current state and keep the fastest.  The state and
+ * its moments are saved first and restored after each candidate, so the
+ * call leaves them unchanged; it allocates and frees a device copy of them.
+ * ms_out (optional, host, 6 values) receives the time per step of each
+ * candidate in the order (256,0) (256,1) (512,0) (512,1) (1024,0) (1024,1).
+ * Requires a bound state.  Synchronises. */
+imexlb_status imexlb_batch_tune(imexlb_batch* b, int nsteps, double* ms_out);
+
+const char* imexlb_batch_last_error(const imexlb_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

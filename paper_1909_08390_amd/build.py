@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libimexlb.so")
 
-SOURCES = [os.path.join(CSRC, "imexlb.cpp"), os.path.join(CSRC, "kernels.hip")]
+SOURCES = [os.path.join(CSRC, "imexlb.cpp"), os.path.join(CSRC, "batch.cpp"),
+           os.path.join(CSRC, "kernels.hip")]
 
 # Packed FP32 instructions are disabled for all device code (the compiler
 # would otherwise form v_pk_* ops from float code).

@@ -99,6 +99,7 @@ struct StageArgs {
     int nx, ny, bcx, bcy;
     int ntx, nty, tiles_per_xcd, qm;  // qm: padded Horner order (8 or 16)
     long long plane_stride;  // cells per plane
+    long long mstride;       // elements per moment field (1D kernels)
     double inv_dx, inv_dy;
     double dt, omega;
     double a_rel, b_rel;     // relax-on-read weights: F_i = a_rel G + b_rel E
@@ -113,17 +114,30 @@ struct StageArgs {
     double dk;               // D + K
 };
 
+// Host helpers shared by the single-grid and batched contexts (imexlb.cpp).
+bool quadrature_rule(int Q, double* p, double* w);
+hipError_t upload_tables(int d, const int Q[2], const double p[2][kQMax], const double w[2][kQMax],
+                         DevTables** d_tab, hipStream_t stream);
+void stage_coefficients(double dt, double tau, StageArgs& a);  // dt, omega, a1, a2, k[]
+void pass_args(const StageArgs& a, void* F, void* G3, void* G4, double* Mn, double* M3, double* M4,
+               StageArgs out[3]);
+
 // Launchers (kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_stage(int d, bool f32, int kind, const StageArgs& a, hipStream_t s);
 hipError_t launch_init_equilibrium(int d, bool f32, const DevTables* tab, const double* n,
                                    const double* ux, const double* uy, const double* T,
                                    void* F, double* M, long long cells, double chi_fac,
                                    hipStream_t s);
+// moments of F (plane stride cells) into M with field stride ms
 hipError_t launch_moments(int d, bool f32, const DevTables* tab, const void* F, double* M,
-                          long long cells, double dk, hipStream_t s);
+                          long long cells, long long ms, double dk, hipStream_t s);
 hipError_t launch_domain_sums(int d, const double* M, long long cells, double dk,
                               double* partial, int nblocks, double* out4, hipStream_t s);
 hipError_t launch_check(int d, const double* M, long long cells, int* flag, hipStream_t s);
+// Batched 1D passes: one launch covers every tile of every tube.  targs[i]
+// holds tube i's arguments for this pass; tiles[j] = (tube, first cell).
+hipError_t launch_stage1d_batch(bool f32, int kind, int qm, int tile, const StageArgs* targs,
+                                const int2* tiles, int ntiles, hipStream_t s);
 
 // Tile shapes (cells) used by the stage kernels: 2D tiles of kTile2X x
 // kTile2Y cells, kOwn2 consecutive cells per thread (kTile2X kTile2Y / kOwn2
@@ -141,6 +155,8 @@ hipError_t launch_check(int d, const double* M, long long cells, int* flag, hipS
 constexpr int kTile2X = IMEXLB_TILE2X, kTile2Y = IMEXLB_TILE2Y;
 constexpr int kOwn2 = IMEXLB_OWN2;
 constexpr int kTile1X = 1024;
+// Tile widths (cells) the batched 1D passes can be launched with.
+constexpr int kBatchTiles[3] = {256, 512, 1024};
 // Tiles are visited in column bands of this many tiles (2D blocking of the
 // work that runs concurrently on one XCD, so halos hit that XCD's L2).
 constexpr int kBand = 8;

@@ -124,6 +124,195 @@ bool gauss_hermite(int Q, double* p, double* w) {
     return true;
 }
 
+}  // namespace
+
+namespace imexlb {
+
+bool quadrature_rule(int Q, double* p, double* w) { return gauss_hermite(Q, p, w); }
+
+// Builds the constant tables of one quadrature (Sec. II) and copies them to
+// a new device allocation *d_tab (synchronous on s).
+hipError_t upload_tables(int d, const int Q[2], const double p[2][kQMax], const double w[2][kQMax],
+                         DevTables** d_tab, hipStream_t stream) {
+    *d_tab = nullptr;
+    DevTables* t = new (std::nothrow) DevTables();
+    if (!t) return hipErrorOutOfMemory;
+    const int nphi = d == 2 ? Q[0] * Q[0] : Q[0];
+    const int nplanes = nphi + (d == 2 ? Q[1] * Q[1] : Q[1]);
+    std::memset(t, 0, sizeof(*t));
+    for (int s = 0; s < 2; ++s) {
+        t->q[s] = Q[s];
+        for (int k = 0; k < Q[s]; ++k) {
+            long double fact = 1.0L;
+            for (int l = 0; l < Q[s]; ++l) {
+                if (l > 0) fact *= (long double)l;
+                t->h[s][k][l] = (double)((long double)w[s][k] * he(l, (long double)p[s][k]) / fact);
+            }
+        }
+    }
+    // Even/odd Horner rows: B_k[s][j] = w_k He_{j+2s}(p_k) / (2^s s! j!) for
+    // j + 2s < Q (the regrouped double sum of Eq. gExpanded), zero beyond.
+    auto horner_row = [&](int s, int k, int QM, double* row) {
+        const int S = (QM - 1) / 2;
+        int o = 0;
+        for (int ss = 0; ss <= S; ++ss) {
+            for (int par = 0; par < 2; ++par)
+                for (int j = par; j <= QM - 1 - 2 * ss; j += 2) {
+                    double val = 0.0;
+                    if (j + 2 * ss < Q[s]) {
+                        long double den = 1.0L;
+                        for (int i = 1; i <= ss; ++i) den *= 2.0L * (long double)i;  // 2^s s!
+                        for (int i = 2; i <= j; ++i) den *= (long double)i;          // j!
+                        val = (double)((long double)w[s][k] * he(j + 2 * ss, (long double)p[s][k]) / den);
+                    }
+                    row[o++] = val;
+                }
+        }
+    };
+    for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < Q[s]; ++k) {
+            horner_row(s, k, 8, t->hc8[s][k]);
+            horner_row(s, k, 16, t->hc16[s][k]);
+        }
+    t->nplanes = nplanes;
+    t->nphi = nphi;
+    {   // processing order of the 2D passes: per set, ky-major; every node
+        // (in x and in y) followed by its mirror, so that one Horner
+        // evaluation gives the factors of both
+        int j = 0;
+        for (int s = 0; s < 2; ++s) {
+            const int base = s ? nphi : 0;
+            const int nyg = d == 2 ? Q[s] : 1;
+            bool set_start = true;
+            for (int ly = 0; ly < (nyg + 1) / 2; ++ly) {
+                const int ypair[2] = {ly, nyg - 1 - ly};
+                const int ycnt = ypair[0] == ypair[1] ? 1 : 2;
+                for (int ey = 0; ey < ycnt; ++ey) {
+                    const int ky = ypair[ey];
+                    bool group_start = true;
+                    for (int k = 0; k < (Q[s] + 1) / 2; ++k) {
+                        const int pair[2] = {k, Q[s] - 1 - k};
+                        const int cnt = pair[0] == pair[1] ? 1 : 2;
+                        for (int e = 0; e < cnt; ++e, ++j) {
+                            PlaneStep& st = t->order[j];
+                            const int kx = pair[e];
+                            st.v = base + kx + Q[s] * ky;
+                            st.set = s;
+                            st.kx = kx;
+                            st.ky = ky;
+                            st.hx = k;
+                            st.first = e == 0;
+                            st.hy = ly;
+                            st.new_group = group_start;
+                            st.yfirst = group_start && ey == 0;
+                            st.new_set = set_start;
+                            group_start = false;
+                            set_start = false;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    int v = 0;
+    for (int s = 0; s < 2; ++s) {
+        const int ny_ = d == 2 ? Q[s] : 1;
+        for (int ky = 0; ky < ny_; ++ky)
+            for (int kx = 0; kx < Q[s]; ++kx, ++v) {
+                PlaneDesc& pd = t->plane[v];
+                pd.px = p[s][kx];
+                pd.py = d == 2 ? p[s][ky] : 0.0;
+                pd.set = s;
+                pd.kx = kx;
+                pd.ky = ky;
+                if (s == 0) {
+                    pd.m0 = 1.0;
+                    pd.mx = pd.px;
+                    pd.my = pd.py;
+                    pd.me = pd.px * pd.px + pd.py * pd.py;
+                } else {
+                    pd.m0 = pd.mx = pd.my = 0.0;
+                    pd.me = 1.0;
+                }
+            }
+    }
+    for (int j = 0; j < nplanes; ++j) {
+        PlaneStep& st = t->order[j];
+        const PlaneDesc& pd = t->plane[st.v];
+        st.px = pd.px;
+        st.py = pd.py;
+        st.m0 = pd.m0;
+        st.mx = pd.mx;
+        st.my = pd.my;
+        st.me = pd.me;
+        PackedStep& ps = t->step[j];
+        ps.px = st.px;
+        ps.py = st.py;
+        ps.v = st.v;
+        ps.bits = st.set | (st.first << 1) | (st.new_group << 2) | (st.yfirst << 3) |
+                  (st.new_set << 4) | (st.kx << 5) | (st.ky << 10) | (st.hx << 15) | (st.hy << 20);
+    }
+    hipError_t e = hipMalloc((void**)d_tab, sizeof(DevTables));
+    if (e == hipSuccess) e = hipMemcpyAsync(*d_tab, t, sizeof(DevTables), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    delete t;
+    if (e != hipSuccess && *d_tab) {
+        (void)hipFree(*d_tab);
+        *d_tab = nullptr;
+    }
+    return e;
+}
+
+void stage_coefficients(double dt, double tau, StageArgs& a) {
+    a.dt = dt;
+    a.omega = dt / tau;
+    const double cc = kAlpha * a.omega;
+    a.a1 = 1.0 / (1.0 + cc);
+    a.a2 = (1.0 + 2.0 * cc) / ((1.0 + cc) * (1.0 + cc));
+    constexpr double be = 0.06042356519705, et = 0.12915286960590;  // Table I
+    const double ka = 0.5 - be - et - kAlpha;
+    const double w = a.omega;
+    a.k[0] = (1.0 - kAlpha) * w * a.a2;
+    a.k[1] = 0.25 * (1.0 - kAlpha) * w * a.a2 - be * w * a.a1 - et * w * a.a2;
+    a.k[2] = ka * w * a.a1;
+    a.k[3] = kAlpha * w * a.a2 / 6.0;
+    a.k[4] = w * a.a1 / 6.0;
+    a.k[5] = 2.0 * w * a.a1 / 3.0;
+}
+
+// Pass 3 advects F2 = a2 F^n + b2 E^n; passes 4 and 5 advect
+// F3 = a1 G3 + c a1 E3 and F4 = a1 G4 + c a1 E4 (relax on read).
+void pass_args(const StageArgs& a, void* F, void* G3, void* G4, double* Mn, double* M3, double* M4,
+               StageArgs out[3]) {
+    const double cc = kAlpha * a.omega;
+    out[0] = out[1] = out[2] = a;
+    out[0].src = F;
+    out[0].msrc = Mn;
+    out[0].out = G3;
+    out[0].mout = M3;
+    out[0].a_rel = a.a2;
+    out[0].b_rel = cc * cc / ((1.0 + cc) * (1.0 + cc));
+    out[1].src = G3;
+    out[1].msrc = M3;
+    out[1].out = G4;
+    out[1].mout = M4;
+    out[1].fbuf = F;
+    out[1].mn = Mn;
+    out[1].a_rel = a.a1;
+    out[1].b_rel = cc * a.a1;
+    out[2].src = G4;
+    out[2].msrc = M4;
+    out[2].out = F;
+    out[2].mout = Mn;
+    out[2].fbuf = F;
+    out[2].a_rel = a.a1;
+    out[2].b_rel = cc * a.a1;
+}
+
+}  // namespace imexlb
+
+namespace {
+
 imexlb_status validate(const imexlb_config* c, std::string& why) {
     if (!c) { why = "config is NULL"; return IMEXLB_EINVAL; }
     if (c->d != 1 && c->d != 2) { why = "d must be 1 or 2"; return IMEXLB_EINVAL; }
@@ -185,24 +374,10 @@ StageArgs base_args(const imexlb_ctx* c) {
     a.tiles_per_xcd = (a.ntx * a.nty + 7) / 8;
     a.qm = (k.q_phi <= 8 && k.q_chi <= 8) ? 8 : 16;
     a.plane_stride = c->cells;
+    a.mstride = c->cells;
     a.inv_dx = k.nx / k.lx;
     a.inv_dy = k.d == 2 ? k.ny / k.ly : 0.0;
-    a.dt = k.dt;
-    a.omega = k.dt / k.tau;
-    const double cc = kAlpha * a.omega;
-    a.a1 = 1.0 / (1.0 + cc);
-    a.a2 = (1.0 + 2.0 * cc) / ((1.0 + cc) * (1.0 + cc));
-    {
-        constexpr double be = 0.06042356519705, et = 0.12915286960590;  // Table I
-        const double ka = 0.5 - be - et - kAlpha;
-        const double w = a.omega;
-        a.k[0] = (1.0 - kAlpha) * w * a.a2;
-        a.k[1] = 0.25 * (1.0 - kAlpha) * w * a.a2 - be * w * a.a1 - et * w * a.a2;
-        a.k[2] = ka * w * a.a1;
-        a.k[3] = kAlpha * w * a.a2 / 6.0;
-        a.k[4] = w * a.a1 / 6.0;
-        a.k[5] = 2.0 * w * a.a1 / 3.0;
-    }
+    stage_coefficients(k.dt, k.tau, a);
     a.chi_fac = (double)(k.K + kDTotal - k.d);
     a.dk = (double)(kDTotal + k.K);
     return a;
@@ -264,132 +439,15 @@ imexlb_status imexlb_create(const imexlb_config* cfg, void* hip_stream, imexlb_c
     c->cells = (long long)cfg->nx * c->cfg.ny;
     c->elem = cfg->storage == IMEXLB_F32 ? 4 : 8;
 
-    DevTables* t = new (std::nothrow) DevTables();
-    if (!t) {
+    hipError_t e = upload_tables(d, Q, c->p, c->w, &c->d_tab, c->stream);
+    if (e == hipErrorOutOfMemory) {
         delete c;
         return IMEXLB_ENOMEM;
     }
-    std::memset(t, 0, sizeof(*t));
-    for (int s = 0; s < 2; ++s) {
-        t->q[s] = Q[s];
-        for (int k = 0; k < Q[s]; ++k) {
-            long double fact = 1.0L;
-            for (int l = 0; l < Q[s]; ++l) {
-                if (l > 0) fact *= (long double)l;
-                t->h[s][k][l] = (double)((long double)c->w[s][k] * he(l, (long double)c->p[s][k]) / fact);
-            }
-        }
-    }
-    // Even/odd Horner rows: B_k[s][j] = w_k He_{j+2s}(p_k) / (2^s s! j!) for
-    // j + 2s < Q (the regrouped double sum of Eq. gExpanded), zero beyond.
-    auto horner_row = [&](int s, int k, int QM, double* row) {
-        const int S = (QM - 1) / 2;
-        int o = 0;
-        for (int ss = 0; ss <= S; ++ss) {
-            for (int par = 0; par < 2; ++par)
-                for (int j = par; j <= QM - 1 - 2 * ss; j += 2) {
-                    double val = 0.0;
-                    if (j + 2 * ss < Q[s]) {
-                        long double den = 1.0L;
-                        for (int i = 1; i <= ss; ++i) den *= 2.0L * (long double)i;  // 2^s s!
-                        for (int i = 2; i <= j; ++i) den *= (long double)i;          // j!
-                        val = (double)((long double)c->w[s][k] * he(j + 2 * ss, (long double)c->p[s][k]) / den);
-                    }
-                    row[o++] = val;
-                }
-        }
-    };
-    for (int s = 0; s < 2; ++s)
-        for (int k = 0; k < Q[s]; ++k) {
-            horner_row(s, k, 8, t->hc8[s][k]);
-            horner_row(s, k, 16, t->hc16[s][k]);
-        }
-    t->nplanes = c->nplanes;
-    t->nphi = c->nphi;
-    {   // processing order of the 2D passes: per set, ky-major; every node
-        // (in x and in y) followed by its mirror, so that one Horner
-        // evaluation gives the factors of both
-        int j = 0;
-        for (int s = 0; s < 2; ++s) {
-            const int base = s ? c->nphi : 0;
-            const int nyg = d == 2 ? Q[s] : 1;
-            bool set_start = true;
-            for (int ly = 0; ly < (nyg + 1) / 2; ++ly) {
-                const int ypair[2] = {ly, nyg - 1 - ly};
-                const int ycnt = ypair[0] == ypair[1] ? 1 : 2;
-                for (int ey = 0; ey < ycnt; ++ey) {
-                    const int ky = ypair[ey];
-                    bool group_start = true;
-                    for (int k = 0; k < (Q[s] + 1) / 2; ++k) {
-                        const int pair[2] = {k, Q[s] - 1 - k};
-                        const int cnt = pair[0] == pair[1] ? 1 : 2;
-                        for (int e = 0; e < cnt; ++e, ++j) {
-                            PlaneStep& st = t->order[j];
-                            const int kx = pair[e];
-                            st.v = base + kx + Q[s] * ky;
-                            st.set = s;
-                            st.kx = kx;
-                            st.ky = ky;
-                            st.hx = k;
-                            st.first = e == 0;
-                            st.hy = ly;
-                            st.new_group = group_start;
-                            st.yfirst = group_start && ey == 0;
-                            st.new_set = set_start;
-                            group_start = false;
-                            set_start = false;
-                        }
-                    }
-                }
-            }
-        }
-    }
-    int v = 0;
-    for (int s = 0; s < 2; ++s) {
-        const int ny_ = d == 2 ? Q[s] : 1;
-        for (int ky = 0; ky < ny_; ++ky)
-            for (int kx = 0; kx < Q[s]; ++kx, ++v) {
-                PlaneDesc& pd = t->plane[v];
-                pd.px = c->p[s][kx];
-                pd.py = d == 2 ? c->p[s][ky] : 0.0;
-                pd.set = s;
-                pd.kx = kx;
-                pd.ky = ky;
-                if (s == 0) {
-                    pd.m0 = 1.0;
-                    pd.mx = pd.px;
-                    pd.my = pd.py;
-                    pd.me = pd.px * pd.px + pd.py * pd.py;
-                } else {
-                    pd.m0 = pd.mx = pd.my = 0.0;
-                    pd.me = 1.0;
-                }
-            }
-    }
-    for (int j = 0; j < c->nplanes; ++j) {
-        PlaneStep& st = t->order[j];
-        const PlaneDesc& pd = t->plane[st.v];
-        st.px = pd.px;
-        st.py = pd.py;
-        st.m0 = pd.m0;
-        st.mx = pd.mx;
-        st.my = pd.my;
-        st.me = pd.me;
-        PackedStep& ps = t->step[j];
-        ps.px = st.px;
-        ps.py = st.py;
-        ps.v = st.v;
-        ps.bits = st.set | (st.first << 1) | (st.new_group << 2) | (st.yfirst << 3) |
-                  (st.new_set << 4) | (st.kx << 5) | (st.ky << 10) | (st.hx << 15) | (st.hy << 20);
-    }
-    hipError_t e = hipGetDevice(&c->device);
-    if (e == hipSuccess) e = hipMalloc((void**)&c->d_tab, sizeof(DevTables));
+    if (e == hipSuccess) e = hipGetDevice(&c->device);
     c->nred = kRedBlocks;
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_small, sizeof(double) * (4 * c->nred + 4));
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_flag, sizeof(int) * 64);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->d_tab, t, sizeof(DevTables), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    delete t;
     if (e != hipSuccess) {
         std::fprintf(stderr, "imexlb_create: %s\n", hipGetErrorString(e));
         imexlb_destroy(c);
@@ -458,7 +516,7 @@ imexlb_status imexlb_set_equilibrium(imexlb_ctx* c, const double* n, const doubl
     hipError_t e = launch_init_equilibrium(c->cfg.d, f32, c->d_tab, n, ux, uy, T, c->d_state, nullptr,
                                            c->cells, (double)(c->cfg.K + kDTotal - c->cfg.d), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "set_equilibrium");
-    e = launch_moments(c->cfg.d, f32, c->d_tab, c->d_state, work_m(c, 0), c->cells,
+    e = launch_moments(c->cfg.d, f32, c->d_tab, c->d_state, work_m(c, 0), c->cells, c->cells,
                        (double)(kDTotal + c->cfg.K), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "set_equilibrium moments");
     c->have_state = true;
@@ -474,7 +532,7 @@ imexlb_status imexlb_set_state(imexlb_ctx* c, const void* F) {
         e = hipMemcpyAsync(c->d_state, F, imexlb_state_bytes(c), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "set_state copy");
     e = launch_moments(c->cfg.d, c->cfg.storage == IMEXLB_F32, c->d_tab, c->d_state, work_m(c, 0),
-                       c->cells, (double)(kDTotal + c->cfg.K), c->stream);
+                       c->cells, c->cells, (double)(kDTotal + c->cfg.K), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "set_state moments");
     c->have_state = true;
     return IMEXLB_OK;
@@ -506,31 +564,9 @@ imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev) {
     double* Mn = work_m(c, 0);
     double* M3 = work_m(c, 1);
     double* M4 = work_m(c, 2);
-    const double cc = kAlpha * a.omega;
-    // pass 3 advects F2 = a2 F^n + b2 E^n; passes 4 and 5 advect
-    // F3 = a1 G3 + c a1 E3 and F4 = a1 G4 + c a1 E4.
-    StageArgs a3 = a, a4 = a, a5 = a;
-    a3.src = F;
-    a3.msrc = Mn;
-    a3.out = G3;
-    a3.mout = M3;
-    a3.a_rel = a.a2;
-    a3.b_rel = cc * cc / ((1.0 + cc) * (1.0 + cc));
-    a4.src = G3;
-    a4.msrc = M3;
-    a4.out = G4;
-    a4.mout = M4;
-    a4.fbuf = F;
-    a4.mn = Mn;
-    a4.a_rel = a.a1;
-    a4.b_rel = cc * a.a1;
-    a5.src = G4;
-    a5.msrc = M4;
-    a5.out = F;
-    a5.mout = Mn;
-    a5.fbuf = F;
-    a5.a_rel = a.a1;
-    a5.b_rel = cc * a.a1;
+    StageArgs pa[3];
+    pass_args(a, F, G3, G4, Mn, M3, M4, pa);
+    const StageArgs &a3 = pa[0], &a4 = pa[1], &a5 = pa[2];
     hipError_t e = hipSuccess;
     if (ev) e = hipEventRecord(ev[0], c->stream);
     for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
@@ -613,7 +649,7 @@ imexlb_status imexlb_compute_moments(const imexlb_ctx* c, const void* F, double*
     // computed into the M3 slot of the workspace, then copied out
     double* M = work_m(c, 1);
     hipError_t e = launch_moments(c->cfg.d, c->cfg.storage == IMEXLB_F32, c->d_tab, F, M, c->cells,
-                                  (double)(kDTotal + c->cfg.K), c->stream);
+                                  c->cells, (double)(kDTotal + c->cfg.K), c->stream);
     if (e != hipSuccess) return hip_fail(m, e, "compute_moments");
     const size_t b = (size_t)c->cells * sizeof(double);
     double* dst[4] = {n, ux, c->cfg.d == 2 ? uy : nullptr, T};

@@ -35,11 +35,6 @@ namespace {
 typedef const DevTables IMEXLB_CONST CTab;
 typedef const double IMEXLB_CONST* CDp;
 
-// Table I constants.
-constexpr double kAlpha = 0.24169426078821;
-constexpr double kBeta = 0.06042356519705;
-constexpr double kEta = 0.12915286960590;
-constexpr double kKappa = 0.5 - kBeta - kEta - kAlpha;
 
 // Ghost-node addressing (Sec. IV): outflow copies the boundary node,
 // periodic wraps.
@@ -145,14 +140,6 @@ __device__ __forceinline__ R mp9_face_clip(const R (&dd)[8], R fs, R fp, R t, R 
     return fmin(fmax(fl, lo), hi);
 }
 
-template <typename R>
-__device__ __forceinline__ R mp9_face(const R (&dd)[8], R fs, R fp) {
-    R t, q;
-    R fl = mp9_face_linear<R>(dd, fs, t, q);
-    if (q > R(0)) fl = mp9_face_clip<R>(dd, fs, fp, t, fl);
-    return fl;
-}
-
 // MP-9 along a line held in registers, upwind-first window w[0 .. L+8]: the
 // face between window positions m and m+1 (m = 4 .. L+4) is reconstructed
 // from w[m-4 .. m+4] with w[m] the upwind node.  Returns dif[i] = face(5+i)
@@ -208,67 +195,6 @@ __device__ __forceinline__ void mp9_sweep(const S* lo, R* out) {
     mp9_line<R, L>(w, dif);
 #pragma unroll
     for (int i = 0; i < L; ++i) out[(FWD ? i : L - 1 - i) * OSTRIDE] = dif[i];
-}
-
-template <typename S>
-struct Vec4;
-template <>
-struct Vec4<double> {
-    using T = double4;
-};
-template <>
-struct Vec4<float> {
-    using T = float4;
-};
-
-template <typename S>
-__device__ __forceinline__ void load4(const S* p, double (&o)[4]) {
-    const typename Vec4<S>::T v = *reinterpret_cast<const typename Vec4<S>::T*>(p);
-    o[0] = v.x;
-    o[1] = v.y;
-    o[2] = v.z;
-    o[3] = v.w;
-}
-
-template <typename S>
-__device__ __forceinline__ void store4(S* p, const S (&o)[4]) {
-    typename Vec4<S>::T v;
-    v.x = o[0];
-    v.y = o[1];
-    v.z = o[2];
-    v.w = o[3];
-    *reinterpret_cast<typename Vec4<S>::T*>(p) = v;
-}
-
-// N consecutive elements (N = 2 or 4) as one vector access.
-template <typename S, int N>
-struct VecN;
-template <> struct VecN<double, 2> { using T = double2; };
-template <> struct VecN<float, 2> { using T = float2; };
-template <> struct VecN<double, 4> { using T = double4; };
-template <> struct VecN<float, 4> { using T = float4; };
-
-template <typename S, int N>
-__device__ __forceinline__ void loadN(const S* p, double* o) {
-    const typename VecN<S, N>::T v = *reinterpret_cast<const typename VecN<S, N>::T*>(p);
-    o[0] = v.x;
-    o[1] = v.y;
-    if constexpr (N == 4) {
-        o[2] = v.z;
-        o[3] = v.w;
-    }
-}
-
-template <typename S, int N>
-__device__ __forceinline__ void storeN(S* p, const S* o) {
-    typename VecN<S, N>::T v;
-    v.x = o[0];
-    v.y = o[1];
-    if constexpr (N == 4) {
-        v.z = o[2];
-        v.w = o[3];
-    }
-    *reinterpret_cast<typename VecN<S, N>::T*>(p) = v;
 }
 
 // Raw buffer access to one plane: the plane base sits in SGPRs (a buffer
@@ -369,15 +295,6 @@ __device__ __forceinline__ void g_pair(CDp c, double u, double th,
     }
     g = fma(u, go, ge);
     gm = fma(-u, go, ge);
-}
-
-__device__ __forceinline__ PlaneStep load_step(CTab* t, int j) {
-    const PlaneStep IMEXLB_CONST& r = t->order[j];
-    PlaneStep s;
-    s.px = r.px; s.py = r.py; s.m0 = r.m0; s.mx = r.mx; s.my = r.my; s.me = r.me;
-    s.v = r.v; s.set = r.set; s.kx = r.kx; s.ky = r.ky; s.hx = r.hx; s.first = r.first;
-    s.hy = r.hy; s.new_group = r.new_group; s.yfirst = r.yfirst; s.new_set = r.new_set;
-    return s;
 }
 
 __device__ __forceinline__ PlaneDesc load_desc(CTab* t, int v) {
@@ -509,7 +426,6 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
 
     const int orow = tid / OPR, ox = (tid % OPR) * OWN;
     const int oy = y0 + orow, ox0 = x0 + ox;
-    constexpr bool vec = VEC;
     const bool row_real = oy < ny;
 
     // gcell: global cell read by each loaded slot (ghost nodes mapped by the
@@ -899,213 +815,261 @@ stage2d_kernel(StageArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// One-dimensional stage pass.  Tile of 1024 cells, 256 threads, 4 cells per
-// thread; moments (n, u_x, T).
+// One-dimensional stage pass over a tile of TX cells, TX / 4 threads, 4
+// consecutive cells per thread (one or two vector accesses).
+//  - loaded cells: the 4 own cells of every thread plus the 10 halo cells
+//    (threads 0..9); cells past the end of the grid map through the
+//    boundary rule and act as the ghost nodes of Sec. IV;
+//  - planes run set by set with every node followed by its mirror, so one
+//    even/odd Horner evaluation per loaded cell gives the x factors of both
+//    (the second plane uses the cached mirror factor);
+//  - per plane: relax on read into one of two LDS tiles (the next plane's
+//    global loads already in flight), one barrier, MP-9 sweep of the
+//    thread's own 4 cells (flux differences stay in registers), pointwise
+//    stage algebra, stores, FP64 moment accumulation.
+// The arguments come by reference so that the batched kernel can read them
+// from a per-tube table with scalar loads.
 // ---------------------------------------------------------------------------
-template <typename S, int KIND>
-__global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
-    constexpr int NT = 256, L = 4, TX = kTile1X;
-    constexpr int P = TX + 10;
-    constexpr int NS = L + 1;
+template <typename S>
+__device__ __forceinline__ void bload4(Rsrc r, int off, double* o) {
+    if constexpr (sizeof(S) == 8) {
+        bload2<S>(r, off, o);
+        bload2<S>(r, off + 16, o + 2);
+    } else {
+        const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void bstore4(Rsrc r, int off, const S* v) {
+    if constexpr (sizeof(S) == 8) {
+        bstore2<S>(r, off, v);
+        bstore2<S>(r, off + 16, v + 2);
+    } else {
+        const float4 x = {v[0], v[1], v[2], v[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), r, off, 0, 0);
+    }
+}
+
+template <typename S, int KIND, int QM, int TX, typename A>
+__device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 10]) {
+    constexpr int L = 4, NT = TX / L, NS = L + 1;
     constexpr bool RELAX = KIND != kAdvect;
-    static_assert(NT * L == TX, "tile / thread mismatch");
+    static_assert(NT * L == TX && NT >= 10, "tile / thread mismatch");
     using R = S;
-
-    __shared__ S tile[2][P];
-
     const int tid = threadIdx.x;
-    const int logical = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
-    if (logical >= a.ntx) return;
-    const int x0 = logical * TX;
-    const int nx = a.nx;
-    const long long ps = a.plane_stride;
+    const int nx = a.nx, bcx = a.bcx;
+    const long long ps = a.plane_stride, ms = a.mstride;
+    const double* msrc = a.msrc;
     CTab* tab = (CTab*)a.tab;
     const int ox0 = x0 + tid * L;
-    const bool vec = (x0 + TX <= nx) && (nx % 4 == 0);
+    const bool vec = (x0 + TX <= nx) && (nx % L == 0);
 
+    // loaded slots: own cells 0..3, halo slot 4 (threads 0..9; the others
+    // load cell gcell[0] again so that every thread issues the same loads)
     int gcell[NS], lidx[NS];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-        gcell[i] = bc_map(ox0 + i, nx, a.bcx);
+        gcell[i] = bc_map(ox0 + i, nx, bcx);
         lidx[i] = tid * L + i + 5;
     }
-    if (tid < 10) {
+    const bool hval = tid < 10;
+    {
         const int lx = tid < 5 ? tid : TX + tid;
-        gcell[L] = bc_map(x0 + lx - 5, nx, a.bcx);
-        lidx[L] = lx;
-    } else {
-        gcell[L] = -1;
-        lidx[L] = 0;
+        gcell[L] = hval ? bc_map(x0 + lx - 5, nx, bcx) : gcell[0];
+        lidx[L] = hval ? lx : 0;
     }
+    int boff[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) boff[s] = gcell[s] * (int)sizeof(S);
+    const int own_off = ox0 * (int)sizeof(S);
 
-    double sux[NS], sth[NS], sA[NS];
+    // source moments at the loaded cells, F^n moments at the own cells (stage 4)
+    // sP: the set prefactor P_phi = n, turned into P_chi = (K + D - d) n T
+    // at the start of the chi set
+    double sux[NS], sth[NS], sP[NS], sgm[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        sux[s] = 0.0;
-        sth[s] = 0.0;
-        sA[s] = 0.0;
-        if (RELAX && gcell[s] >= 0) {
-            sux[s] = a.msrc[ps + gcell[s]];
-            sth[s] = a.msrc[2 * ps + gcell[s]] - 1.0;
-        }
+        sux[s] = RELAX ? msrc[ms + gcell[s]] : 0.0;
+        sth[s] = RELAX ? msrc[2 * ms + gcell[s]] - 1.0 : 0.0;
+        sP[s] = RELAX ? msrc[gcell[s]] : 0.0;
+        sgm[s] = 0.0;
     }
-    double nux[L], nth[L], nA[L];
+    double nux[L], nth[L], nP[L], ngm[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-        nux[i] = 0.0;
-        nth[i] = 0.0;
-        nA[i] = 0.0;
-        if (KIND == kStage4) {
-            nux[i] = a.mn[ps + gcell[i]];
-            nth[i] = a.mn[2 * ps + gcell[i]] - 1.0;
-        }
+        nux[i] = KIND == kStage4 ? a.mn[ms + gcell[i]] : 0.0;
+        nth[i] = KIND == kStage4 ? a.mn[2 * ms + gcell[i]] - 1.0 : 0.0;
+        nP[i] = KIND == kStage4 ? a.mn[gcell[i]] : 0.0;
+        ngm[i] = 0.0;
     }
     Acc acc[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) acc[i] = Acc{0.0, 0.0, 0.0, 0.0};
 
-    int parity = 0;
-    for (int set = 0; set < 2; ++set) {
-        const int Q = tab->q[set];
-        const int vbase = set ? tab->nphi : 0;
-        if constexpr (RELAX) {
+    double pg[NS], pf[L];
+    auto fetch = [&](int v) {
+        const Rsrc rs = plane_rsrc(static_cast<const S*>(a.src) + (size_t)v * ps, ps);
+        if (vec) {
+            bload4<S>(rs, boff[0], pg);
+        } else {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                if (gcell[s] >= 0) {
-                    const double n = a.msrc[gcell[s]];
-                    sA[s] = set ? a.chi_fac * n * (sth[s] + 1.0) : n;
-                }
-            }
-            if constexpr (KIND == kStage4) {
+            for (int i = 0; i < L; ++i) pg[i] = bload1<S>(rs, boff[i]);
+        }
+        pg[L] = bload1<S>(rs, boff[L]);
+        if constexpr (KIND == kStage4 || KIND == kStage5) {
+            const Rsrc rf = plane_rsrc(static_cast<const S*>(a.fbuf) + (size_t)v * ps, ps);
+            if (vec) {
+                bload4<S>(rf, boff[0], pf);
+            } else {
 #pragma unroll
-                for (int i = 0; i < L; ++i) {
-                    const double n = a.mn[gcell[i]];
-                    nA[i] = set ? a.chi_fac * n * (nth[i] + 1.0) : n;
-                }
+                for (int i = 0; i < L; ++i) pf[i] = bload1<S>(rf, boff[i]);
             }
         }
-        for (int kx = 0; kx < Q; ++kx) {
-            const int v = vbase + kx;
-            const PlaneDesc pd = load_desc(tab, v);
-            CDp hx = tab->h[set][kx];
-            const S* __restrict__ sv = static_cast<const S*>(a.src) + (size_t)v * ps;
-            S* buf = tile[parity];
-            parity ^= 1;
+    };
 
-            double gown[L], eown[L];
-            if (vec) {
-                load4<S>(sv + gcell[0], gown);
+    constexpr int NC = HornerLayout<QM>::total();
+    const int np = tab->nplanes;
+    Step s0 = load_pstep(tab, 0);
+    Step s1 = load_pstep(tab, np > 1 ? 1 : 0);
+    fetch(s0.v);
+    for (int j = 0; j < np; ++j) {
+        const Step st = s0;
+        s0 = s1;
+        if (j + 2 < np) s1 = load_pstep(tab, j + 2);
+        double g[NS], fb[L];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) g[s] = pg[s];
+#pragma unroll
+        for (int i = 0; i < L; ++i) fb[i] = pf[i];
+        fetch(s0.v);  // unconditional (the last iteration refetches)
+        S* buf = tile[j & 1];
+
+        double e[NS], en[L];
+        if constexpr (RELAX) {
+            if (st.new_set() && st.set() == 1) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) sP[s] = a.chi_fac * sP[s] * (sth[s] + 1.0);
+                if constexpr (KIND == kStage4) {
+#pragma unroll
+                    for (int i = 0; i < L; ++i) nP[i] = a.chi_fac * nP[i] * (nth[i] + 1.0);
+                }
+            }
+            double gx[NS], gxn[L];
+            if (st.first()) {
+                CDp hx = hrow<QM>(tab, st.set(), st.hx());
+                double cf[NC];
+#pragma unroll
+                for (int i = 0; i < NC; ++i) cf[i] = hx[i];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) g_pair_r<QM>(cf, sux[s], sth[s], gx[s], sgm[s]);
+                if constexpr (KIND == kStage4) {
+#pragma unroll
+                    for (int i = 0; i < L; ++i) g_pair_r<QM>(cf, nux[i], nth[i], gxn[i], ngm[i]);
+                }
             } else {
 #pragma unroll
-                for (int i = 0; i < L; ++i) gown[i] = sv[gcell[i]];
+                for (int s = 0; s < NS; ++s) gx[s] = sgm[s];
+#pragma unroll
+                for (int i = 0; i < L; ++i) gxn[i] = ngm[i];
             }
-            const double ghalo = gcell[L] >= 0 ? (double)sv[gcell[L]] : 0.0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) e[s] = sP[s] * gx[s];
+#pragma unroll
+            for (int i = 0; i < L; ++i) en[i] = KIND == kStage4 ? nP[i] * gxn[i] : 0.0;
+        } else {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) e[s] = 0.0;
+#pragma unroll
+            for (int i = 0; i < L; ++i) en[i] = 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < L; ++s) buf[lidx[s]] = (S)(RELAX ? fma(a.a_rel, g[s], a.b_rel * e[s]) : g[s]);
+        if (hval) buf[lidx[L]] = (S)(RELAX ? fma(a.a_rel, g[L], a.b_rel * e[L]) : g[L]);
+        __syncthreads();
+
+        // MP-9 over the own cells: window of L + 9 values around them
+        double vf[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) vf[i] = 0.0;
+        if (st.px != 0.0) {
+            R w[L + 9], dif[L];
+            const S* lo = buf + tid * L;
+            if (st.px > 0.0) {
+#pragma unroll
+                for (int m = 0; m < L + 9; ++m) w[m] = (R)lo[m];
+                mp9_line<R, L>(w, dif);
+            } else {
+#pragma unroll
+                for (int m = 0; m < L + 9; ++m) w[m] = (R)lo[L + 9 - m];
+                R dr[L];
+                mp9_line<R, L>(w, dr);
+#pragma unroll
+                for (int i = 0; i < L; ++i) dif[i] = dr[L - 1 - i];
+            }
+            const double sx = fabs(st.px) * a.inv_dx;
+#pragma unroll
+            for (int i = 0; i < L; ++i) vf[i] = (double)dif[i] * sx;
+        }
+
+        if constexpr (KIND == kAdvect) {
+            double* o = static_cast<double*>(a.out) + (size_t)st.v * ps + ox0;
+#pragma unroll
+            for (int i = 0; i < L; ++i)
+                if (ox0 + i < nx) o[i] = vf[i];
+        } else {
+            S outv[L], fbv[L];
 #pragma unroll
             for (int i = 0; i < L; ++i) {
-                double val = gown[i];
-                eown[i] = 0.0;
-                if constexpr (RELAX) {
-                    eown[i] = sA[i] * herm_factor(hx, Q, sux[i], sth[i]);
-                    val = fma(a.a_rel, gown[i], a.b_rel * eown[i]);
-                }
-                buf[lidx[i]] = (S)val;
-            }
-            if (gcell[L] >= 0) {
-                double val = ghalo;
-                if constexpr (RELAX) {
-                    const double e = sA[L] * herm_factor(hx, Q, sux[L], sth[L]);
-                    val = fma(a.a_rel, ghalo, a.b_rel * e);
-                }
-                buf[lidx[L]] = (S)val;
-            }
-            __syncthreads();
-
-            R difx[L];
-#pragma unroll
-            for (int i = 0; i < L; ++i) difx[i] = R(0);
-            if (pd.px != 0.0) {
-                const bool fwd = pd.px > 0.0;
-                const S* base = buf + tid * L + (fwd ? 0 : L + 9);
-                const int st = fwd ? 1 : -1;
-                R w[L + 9];
-#pragma unroll
-                for (int m = 0; m < L + 9; ++m) w[m] = base[m * st];
-                R dif[L];
-                mp9_line<R, L>(w, dif);
-                if (fwd) {
-#pragma unroll
-                    for (int i = 0; i < L; ++i) difx[i] = dif[i];
-                } else {
-#pragma unroll
-                    for (int i = 0; i < L; ++i) difx[i] = dif[L - 1 - i];
+                if constexpr (KIND == kStage3) {
+                    const double fn = g[i];
+                    outv[i] = (S)fma(-a.k[0], fn - e[i], fma(-a.dt, vf[i], fn));
+                    fbv[i] = outv[i];
+                } else if constexpr (KIND == kStage4) {
+                    const double fn = fb[i], g3 = g[i];
+                    const double dn = fn - en[i], d3 = g3 - e[i];
+                    const double s4 = fma(0.75, fn, fma(0.25, g3, fma(a.k[1], dn, fma(-a.k[2], d3, -0.25 * a.dt * vf[i]))));
+                    const double r = fma(5.0 / 6.0, fn, fma(1.0 / 6.0, g3, fma(-a.k[3], dn, fma(-a.k[4], d3, -(1.0 / 6.0) * a.dt * vf[i]))));
+                    outv[i] = (S)s4;
+                    fbv[i] = (S)r;
+                } else {  // kStage5
+                    fbv[i] = (S)fma(-a.k[5], g[i] - e[i], fma(-(2.0 / 3.0) * a.dt, vf[i], fb[i]));
+                    outv[i] = fbv[i];
                 }
             }
-            const double sx = fabs(pd.px) * a.inv_dx;
-            double vf[L];
-#pragma unroll
-            for (int i = 0; i < L; ++i) vf[i] = (double)difx[i] * sx;
-
-            const size_t own0 = (size_t)v * ps + ox0;
-            if constexpr (KIND == kAdvect) {
-                double* o = static_cast<double*>(a.out) + own0;
+            const Rsrc ro = plane_rsrc(static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + (size_t)st.v * ps, ps);
+            if (vec) {
+                bstore4<S>(ro, own_off, outv);
+            } else {
 #pragma unroll
                 for (int i = 0; i < L; ++i)
-                    if (ox0 + i < nx) o[i] = vf[i];
-            } else {
-                S outv[L], fbv[L];
-                double fb[L];
-                if constexpr (KIND == kStage4 || KIND == kStage5) {
-                    const S* fbp = static_cast<const S*>(a.fbuf) + (size_t)v * ps;
-                    if (vec) {
-                        load4<S>(fbp + gcell[0], fb);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < L; ++i) fb[i] = fbp[gcell[i]];
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < L; ++i) {
-                    if constexpr (KIND == kStage3) {
-                        const double fn = gown[i], en = eown[i];
-                        outv[i] = (S)(fn - a.dt * vf[i] - (1.0 - kAlpha) * a.omega * a.a2 * (fn - en));
-                    } else if constexpr (KIND == kStage4) {
-                        const double fn = fb[i];
-                        const double en = nA[i] * herm_factor(hx, Q, nux[i], nth[i]);
-                        const double g3 = gown[i], e3 = eown[i];
-                        const double dn = fn - en, d3 = g3 - e3;
-                        const double df1 = a.omega * a.a1 * dn;
-                        const double df2 = a.omega * a.a2 * dn;
-                        const double df3 = a.omega * a.a1 * d3;
-                        const double dtvf2 = fn - (1.0 - kAlpha) * df2 - g3;
-                        const double dtvf3 = a.dt * vf[i];
-                        outv[i] = (S)(fn - 0.25 * (dtvf2 + dtvf3) - kBeta * df1 - kEta * df2 - kKappa * df3);
-                        fbv[i] = (S)(fn - (dtvf2 + dtvf3) * (1.0 / 6.0) - (df2 + df3) * (1.0 / 6.0));
-                    } else {
-                        const double df4 = a.omega * a.a1 * (gown[i] - eown[i]);
-                        fbv[i] = (S)(fb[i] - (2.0 / 3.0) * (a.dt * vf[i] + df4));
-                    }
-                }
-                S* op = static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + own0;
-                const S(&ov)[L] = (KIND == kStage5) ? fbv : outv;
+                    if (ox0 + i < nx) bstore1<S>(ro, own_off + i * (int)sizeof(S), outv[i]);
+            }
+            if constexpr (KIND == kStage4) {
+                const Rsrc rf = plane_rsrc(static_cast<S*>(a.fbuf) + (size_t)st.v * ps, ps);
                 if (vec) {
-                    store4<S>(op, ov);
+                    bstore4<S>(rf, own_off, fbv);
                 } else {
 #pragma unroll
                     for (int i = 0; i < L; ++i)
-                        if (ox0 + i < nx) op[i] = ov[i];
+                        if (ox0 + i < nx) bstore1<S>(rf, own_off + i * (int)sizeof(S), fbv[i]);
                 }
-                if constexpr (KIND == kStage4) {
-                    S* fp = static_cast<S*>(a.fbuf) + own0;
-                    if (vec) {
-                        store4<S>(fp, fbv);
-                    } else {
+            }
+            if (st.set() == 0) {
 #pragma unroll
-                        for (int i = 0; i < L; ++i)
-                            if (ox0 + i < nx) fp[i] = fbv[i];
-                    }
+                for (int i = 0; i < L; ++i) {
+                    const double f = (double)outv[i];
+                    acc[i].s0 += f;
+                    acc[i].sx = fma(st.px, f, acc[i].sx);
+                    acc[i].se = fma(st.px * st.px, f, acc[i].se);
                 }
+            } else {
 #pragma unroll
-                for (int i = 0; i < L; ++i) acc_add(acc[i], pd, (double)ov[i]);
+                for (int i = 0; i < L; ++i) acc[i].se += (double)outv[i];
             }
         }
     }
@@ -1119,11 +1083,33 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
                 const double T = (acc[i].se - n * ux * ux) / (a.dk * n);
                 const size_t c = (size_t)ox0 + i;
                 a.mout[c] = n;
-                a.mout[ps + c] = ux;
-                a.mout[2 * ps + c] = T;
+                a.mout[ms + c] = ux;
+                a.mout[2 * ms + c] = T;
             }
         }
     }
+}
+
+template <typename S, int KIND, int QM, int TX>
+__global__ void __launch_bounds__(TX / 4) __attribute__((amdgpu_waves_per_eu(2)))
+stage1d_kernel(StageArgs a) {
+    __shared__ S tile[2][TX + 10];
+    const int logical = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
+    if (logical >= a.ntx) return;
+    stage1d_body<S, KIND, QM, TX>(a, logical * TX, tile);
+}
+
+// Batched form: block j runs tile tiles[j] = (tube, first cell) with that
+// tube's arguments for this pass.
+typedef const StageArgs IMEXLB_CONST CArgs;
+template <typename S, int KIND, int QM, int TX>
+__global__ void __launch_bounds__(TX / 4) __attribute__((amdgpu_waves_per_eu(2)))
+stage1d_batch_kernel(const StageArgs* targs, const int2* tiles, int ntiles) {
+    __shared__ S tile[2][TX + 10];
+    if ((int)blockIdx.x >= ntiles) return;
+    const int IMEXLB_CONST* tp = (const int IMEXLB_CONST*)tiles + 2 * blockIdx.x;
+    CArgs& a = ((CArgs*)targs)[tp[0]];
+    stage1d_body<S, KIND, QM, TX>(a, tp[1], tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -1157,7 +1143,7 @@ __global__ void __launch_bounds__(256) init_eq_kernel(const DevTables* __restric
 template <typename S, int D>
 __global__ void __launch_bounds__(256) moments_kernel(const DevTables* __restrict__ tabp,
                                                       const S* __restrict__ F, double* M,
-                                                      long long cells, double dk) {
+                                                      long long cells, long long ms, double dk) {
     CTab* tab = (CTab*)tabp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
@@ -1167,13 +1153,13 @@ __global__ void __launch_bounds__(256) moments_kernel(const DevTables* __restric
     const double nn = a.s0, ux = a.sx / nn, uy = a.sy / nn;
     if (D == 2) {
         M[c] = nn;
-        M[cells + c] = ux;
-        M[2 * cells + c] = uy;
-        M[3 * cells + c] = (a.se - nn * (ux * ux + uy * uy)) / (dk * nn);
+        M[ms + c] = ux;
+        M[2 * ms + c] = uy;
+        M[3 * ms + c] = (a.se - nn * (ux * ux + uy * uy)) / (dk * nn);
     } else {
         M[c] = nn;
-        M[cells + c] = ux;
-        M[2 * cells + c] = (a.se - nn * ux * ux) / (dk * nn);
+        M[ms + c] = ux;
+        M[2 * ms + c] = (a.se - nn * ux * ux) / (dk * nn);
     }
 }
 
@@ -1242,7 +1228,11 @@ hipError_t launch_stage_t(int d, const StageArgs& a, hipStream_t s) {
         else
             hipLaunchKernelGGL((stage2d_kernel<S, KIND, 8, TY, OWN>), dim3(grid), dim3(NT), 0, s, a);
     } else {
-        hipLaunchKernelGGL((stage1d_kernel<S, KIND>), dim3(grid), dim3(256), 0, s, a);
+        constexpr int TX = kTile1X;
+        if (a.qm == 16)
+            hipLaunchKernelGGL((stage1d_kernel<S, KIND, 16, TX>), dim3(grid), dim3(TX / 4), 0, s, a);
+        else
+            hipLaunchKernelGGL((stage1d_kernel<S, KIND, 8, TX>), dim3(grid), dim3(TX / 4), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -1255,6 +1245,38 @@ hipError_t launch_stage(int d, bool f32, int kind, const StageArgs& a, hipStream
         case kStage3: return f32 ? launch_stage_t<float, kStage3>(d, a, s) : launch_stage_t<double, kStage3>(d, a, s);
         case kStage4: return f32 ? launch_stage_t<float, kStage4>(d, a, s) : launch_stage_t<double, kStage4>(d, a, s);
         case kStage5: return f32 ? launch_stage_t<float, kStage5>(d, a, s) : launch_stage_t<double, kStage5>(d, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+
+template <typename S, int KIND, int QM>
+hipError_t launch_batch_t(int tile, const StageArgs* targs, const int2* tiles, int ntiles, hipStream_t s) {
+    switch (tile) {
+        case 256: hipLaunchKernelGGL((stage1d_batch_kernel<S, KIND, QM, 256>), dim3(ntiles), dim3(64), 0, s, targs, tiles, ntiles); break;
+        case 512: hipLaunchKernelGGL((stage1d_batch_kernel<S, KIND, QM, 512>), dim3(ntiles), dim3(128), 0, s, targs, tiles, ntiles); break;
+        case 1024: hipLaunchKernelGGL((stage1d_batch_kernel<S, KIND, QM, 1024>), dim3(ntiles), dim3(256), 0, s, targs, tiles, ntiles); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename S, int KIND>
+hipError_t launch_batch_q(int qm, int tile, const StageArgs* targs, const int2* tiles, int ntiles, hipStream_t s) {
+    return qm == 16 ? launch_batch_t<S, KIND, 16>(tile, targs, tiles, ntiles, s)
+                    : launch_batch_t<S, KIND, 8>(tile, targs, tiles, ntiles, s);
+}
+
+}  // namespace
+
+hipError_t launch_stage1d_batch(bool f32, int kind, int qm, int tile, const StageArgs* targs,
+                                const int2* tiles, int ntiles, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (kind) {
+        case kStage3: return f32 ? launch_batch_q<float, kStage3>(qm, tile, targs, tiles, ntiles, s) : launch_batch_q<double, kStage3>(qm, tile, targs, tiles, ntiles, s);
+        case kStage4: return f32 ? launch_batch_q<float, kStage4>(qm, tile, targs, tiles, ntiles, s) : launch_batch_q<double, kStage4>(qm, tile, targs, tiles, ntiles, s);
+        case kStage5: return f32 ? launch_batch_q<float, kStage5>(qm, tile, targs, tiles, ntiles, s) : launch_batch_q<double, kStage5>(qm, tile, targs, tiles, ntiles, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1276,14 +1298,14 @@ hipError_t launch_init_equilibrium(int d, bool f32, const DevTables* tab, const 
 }
 
 hipError_t launch_moments(int d, bool f32, const DevTables* tab, const void* F, double* M,
-                          long long cells, double dk, hipStream_t s) {
+                          long long cells, long long ms, double dk, hipStream_t s) {
     const int grid = (int)((cells + 255) / 256);
     if (d == 2) {
-        if (f32) hipLaunchKernelGGL((moments_kernel<float, 2>), dim3(grid), dim3(256), 0, s, tab, (const float*)F, M, cells, dk);
-        else hipLaunchKernelGGL((moments_kernel<double, 2>), dim3(grid), dim3(256), 0, s, tab, (const double*)F, M, cells, dk);
+        if (f32) hipLaunchKernelGGL((moments_kernel<float, 2>), dim3(grid), dim3(256), 0, s, tab, (const float*)F, M, cells, ms, dk);
+        else hipLaunchKernelGGL((moments_kernel<double, 2>), dim3(grid), dim3(256), 0, s, tab, (const double*)F, M, cells, ms, dk);
     } else {
-        if (f32) hipLaunchKernelGGL((moments_kernel<float, 1>), dim3(grid), dim3(256), 0, s, tab, (const float*)F, M, cells, dk);
-        else hipLaunchKernelGGL((moments_kernel<double, 1>), dim3(grid), dim3(256), 0, s, tab, (const double*)F, M, cells, dk);
+        if (f32) hipLaunchKernelGGL((moments_kernel<float, 1>), dim3(grid), dim3(256), 0, s, tab, (const float*)F, M, cells, ms, dk);
+        else hipLaunchKernelGGL((moments_kernel<double, 1>), dim3(grid), dim3(256), 0, s, tab, (const double*)F, M, cells, ms, dk);
     }
     return hipGetLastError();
 }

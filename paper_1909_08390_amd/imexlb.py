@@ -30,6 +30,15 @@ class CConfig(ctypes.Structure):
                 ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("storage", ctypes.c_int)]
 
 
+class CTube(ctypes.Structure):
+    """Mirror of ``imexlb_tube``."""
+    _fields_ = [("nx", ctypes.c_int), ("K", ctypes.c_int), ("lx", ctypes.c_double),
+                ("tau", ctypes.c_double), ("dt", ctypes.c_double), ("bc", ctypes.c_int)]
+
+
+BATCH_TILINGS = [(256, 0), (256, 1), (512, 0), (512, 1), (1024, 0), (1024, 1)]
+
+
 class ImexlbError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"imexlb status {status}: {msg}")
@@ -74,6 +83,31 @@ def lib():
         L.imexlb_status_string.restype = ctypes.c_char_p
         L.imexlb_last_error.argtypes = [_vp]
         L.imexlb_last_error.restype = ctypes.c_char_p
+        _ll = ctypes.c_longlong
+        L.imexlb_batch_create.argtypes = [ctypes.POINTER(CTube), ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+        L.imexlb_batch_destroy.argtypes = [_vp]
+        L.imexlb_batch_destroy.restype = None
+        L.imexlb_batch_set_stream.argtypes = [_vp, _vp]
+        L.imexlb_batch_state_bytes.argtypes = [_vp]
+        L.imexlb_batch_state_bytes.restype = ctypes.c_size_t
+        L.imexlb_batch_workspace_bytes.argtypes = [_vp]
+        L.imexlb_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.imexlb_batch_cells.argtypes = [_vp]
+        L.imexlb_batch_cells.restype = _ll
+        L.imexlb_batch_layout.argtypes = [_vp, ctypes.POINTER(_ll), ctypes.POINTER(_ll)]
+        L.imexlb_batch_bind.argtypes = [_vp, _vp, _vp]
+        L.imexlb_batch_set_equilibrium.argtypes = [_vp, _vp, _vp, _vp]
+        L.imexlb_batch_state_changed.argtypes = [_vp]
+        L.imexlb_batch_step.argtypes = [_vp, ctypes.c_int]
+        L.imexlb_batch_step_timed.argtypes = [_vp, ctypes.c_int, _dp]
+        L.imexlb_batch_moments.argtypes = [_vp, _vp, _vp, _vp]
+        L.imexlb_batch_set_tiling.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+        L.imexlb_batch_get_tiling.argtypes = [_vp, ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_int)]
+        L.imexlb_batch_tune.argtypes = [_vp, ctypes.c_int, _dp]
+        L.imexlb_batch_last_error.argtypes = [_vp]
+        L.imexlb_batch_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -252,3 +286,141 @@ class Solver:
 
     def check_state(self) -> int:
         return self.L.imexlb_check_state(self._h)
+
+
+@dataclass
+class TubeSpec:
+    """One tube of a batch (mirrors ``imexlb_tube``)."""
+    nx: int
+    K: int = 2
+    lx: float = 1.0
+    tau: float = 1e-5
+    dt: float = 1e-4
+    bc: int = OUTFLOW
+
+    def c(self) -> CTube:
+        return CTube(self.nx, self.K, self.lx, self.tau, self.dt, self.bc)
+
+
+def batch_validate(tubes, q_phi=8, q_chi=8, storage=F32) -> int:
+    """Status of ``imexlb_batch_create`` (EINVAL before any device work)."""
+    L = lib()
+    arr = (CTube * max(len(tubes), 1))(*[t.c() for t in tubes])
+    h = _vp()
+    st = L.imexlb_batch_create(arr, len(tubes), q_phi, q_chi, storage, None, ctypes.byref(h))
+    if st == OK:
+        L.imexlb_batch_destroy(h)
+    return st
+
+
+class Batch:
+    """Many 1D tubes of uneven size advanced together (one launch per pass),
+    bound to caller-owned torch device buffers."""
+
+    def __init__(self, tubes, q_phi=8, q_chi=8, storage=F32, device="cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.tubes = list(tubes)
+        self.q_phi, self.q_chi, self.storage = q_phi, q_chi, storage
+        self.planes = q_phi + q_chi
+        self.device = torch.device(device)
+        self.L = lib()
+        self._h = _vp()
+        arr = (CTube * len(self.tubes))(*[t.c() for t in self.tubes])
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self._check(self.L.imexlb_batch_create(arr, len(self.tubes), q_phi, q_chi, storage,
+                                                   _vp(self.stream.cuda_stream),
+                                                   ctypes.byref(self._h)), "batch_create")
+            self.state_dtype = torch.float32 if storage == F32 else torch.float64
+            esz = 4 if storage == F32 else 8
+            sb = self.L.imexlb_batch_state_bytes(self._h)
+            # zeroed so that the padding between tubes holds defined values
+            self.state = torch.zeros(sb // esz, dtype=self.state_dtype, device=self.device)
+            self.workspace = torch.empty(self.L.imexlb_batch_workspace_bytes(self._h),
+                                         dtype=torch.uint8, device=self.device)
+            self._check(self.L.imexlb_batch_bind(self._h, _vp(self.state.data_ptr()),
+                                                 _vp(self.workspace.data_ptr())), "batch_bind")
+        self.cells = self.L.imexlb_batch_cells(self._h)
+        so = (ctypes.c_longlong * len(self.tubes))()
+        co = (ctypes.c_longlong * len(self.tubes))()
+        self._check(self.L.imexlb_batch_layout(self._h, so, co), "batch_layout")
+        self.state_offset = list(so)
+        self.cell_offset = list(co)
+
+    def _check(self, st: int, what: str):
+        if st != OK:
+            msg = self.L.imexlb_batch_last_error(self._h).decode() if self._h else ""
+            base = self.L.imexlb_status_string(st).decode()
+            raise ImexlbError(st, f"{what}: {base} {msg}".strip())
+
+    def close(self):
+        if self._h:
+            self.L.imexlb_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tube_state(self, i):
+        """View of tube i's plane-set, shape (planes, nx)."""
+        o, nx = self.state_offset[i], self.tubes[i].nx
+        return self.state[o:o + self.planes * nx].view(self.planes, nx)
+
+    def concat(self, per_tube):
+        """One FP64 device array over all cells from per-tube arrays."""
+        torch = self.torch
+        return torch.cat([torch.as_tensor(a, dtype=torch.float64).reshape(-1)
+                          for a in per_tube]).to(self.device).contiguous()
+
+    def split(self, field):
+        return [field[c:c + t.nx] for c, t in zip(self.cell_offset, self.tubes)]
+
+    def set_equilibrium(self, n, u, T):
+        """n, u, T: per-tube lists of arrays, or arrays over all cells."""
+        f = [self.concat(x) if isinstance(x, (list, tuple)) else
+             self.torch.as_tensor(x, dtype=self.torch.float64, device=self.device).contiguous()
+             for x in (n, u, T)]
+        self._keep = f
+        self._check(self.L.imexlb_batch_set_equilibrium(self._h, *[_vp(t.data_ptr()) for t in f]),
+                    "batch_set_equilibrium")
+
+    def state_changed(self):
+        self._check(self.L.imexlb_batch_state_changed(self._h), "batch_state_changed")
+
+    def step(self, nsteps: int = 1):
+        self._check(self.L.imexlb_batch_step(self._h, int(nsteps)), "batch_step")
+
+    def step_timed(self, nsteps: int):
+        ms = np.zeros(3)
+        self._check(self.L.imexlb_batch_step_timed(self._h, int(nsteps), ms.ctypes.data_as(_dp)),
+                    "batch_step_timed")
+        return ms
+
+    def moments(self):
+        """(n, u, T) device tensors over all cells."""
+        torch = self.torch
+        out = [torch.zeros(self.cells, dtype=torch.float64, device=self.device) for _ in range(3)]
+        self._check(self.L.imexlb_batch_moments(self._h, *[_vp(t.data_ptr()) for t in out]),
+                    "batch_moments")
+        return tuple(out)
+
+    def set_tiling(self, tile: int, order: int = 0):
+        self._check(self.L.imexlb_batch_set_tiling(self._h, int(tile), int(order)), "batch_set_tiling")
+
+    def tiling(self):
+        t, o = ctypes.c_int(), ctypes.c_int()
+        self._check(self.L.imexlb_batch_get_tiling(self._h, ctypes.byref(t), ctypes.byref(o)),
+                    "batch_get_tiling")
+        return t.value, o.value
+
+    def tune(self, nsteps: int = 5):
+        """Autotune the tiling; returns {(tile, order): ms per step}."""
+        ms = np.zeros(len(BATCH_TILINGS))
+        self._check(self.L.imexlb_batch_tune(self._h, int(nsteps), ms.ctypes.data_as(_dp)),
+                    "batch_tune")
+        return dict(zip(BATCH_TILINGS, ms.tolist()))

@@ -163,8 +163,11 @@ class Tube:
     right: tuple
 
 
-def batch_tubes(count: int = 256, seed: int = 0, nx_range=(256, 4096)):
-    """Seeded uneven shock tubes: Nx uniform, K in {0, 2}, tau log-uniform."""
+def batch_tubes(count: int = 256, seed: int = 0, nx_range=(256, 4096), t_window=T_WINDOW):
+    """Seeded uneven shock tubes: Nx uniform, K in {0, 2}, tau log-uniform,
+    left/right (n, u, P) with n, P in [0.05, 2], |u| <= 0.5.  A side whose
+    temperature P/n falls outside t_window is drawn again from the same
+    stream (the truncated equilibria are unstable far from T = 1)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     tubes = []
     for _ in range(count):
@@ -173,9 +176,24 @@ def batch_tubes(count: int = 256, seed: int = 0, nx_range=(256, 4096)):
         tau = float(10.0 ** rng.uniform(-6.0, -2.0))
         st = []
         for _side in range(2):
-            rho = float(rng.uniform(0.05, 2.0))
-            u = float(rng.uniform(-0.5, 0.5))
-            P = float(rng.uniform(0.05, 2.0))
+            while True:
+                rho = float(rng.uniform(0.05, 2.0))
+                u = float(rng.uniform(-0.5, 0.5))
+                P = float(rng.uniform(0.05, 2.0))
+                if t_window is None or t_window[0] <= P / rho <= t_window[1]:
+                    break
             st.append((rho, u, P))
         tubes.append(Tube(nx, K, tau, st[0], st[1]))
     return tubes
+
+PMAX8 = 4.144547186125894  # largest root of He_8
+
+
+def tube_fields(t: Tube):
+    """(n, u, T) of a tube's shock problem, membrane at x = 1/2."""
+    return sod_1d(t.nx, left=t.left, right=t.right)
+
+
+def tube_dt(nx: int, cfl: float = 0.5, pmax: float = PMAX8, lx: float = 1.0) -> float:
+    """Time step with max|p| dt / dx = cfl."""
+    return cfl * lx / (nx * pmax)

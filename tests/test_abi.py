@@ -70,3 +70,25 @@ def test_null_arguments():
     assert L.imexlb_create(None, None, None) == I.EINVAL
     assert L.imexlb_step(None, 1) == I.EINVAL
     assert L.imexlb_bind(None, None, None) == I.EINVAL
+
+
+BAD_TUBES = [
+    [],                                   # no tube
+    [dict(nx=0)],
+    [dict(nx=100, K=-1)],
+    [dict(nx=100, tau=0.0)],
+    [dict(nx=100, dt=0.0)],
+    [dict(nx=100, lx=0.0)],
+    [dict(nx=100, bc=3)],
+    [dict(nx=64), dict(nx=400, dt=1e-2)],  # CFL of the second tube > 1 (Sec. IV)
+]
+
+
+@pytest.mark.parametrize("tubes", BAD_TUBES)
+def test_batch_create_rejects_bad_tubes(tubes):
+    assert I.batch_validate([I.TubeSpec(**t) for t in tubes]) == I.EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(q_phi=2), dict(q_chi=0), dict(q_phi=17), dict(storage=5)])
+def test_batch_create_rejects_bad_quadrature_or_storage(kw):
+    assert I.batch_validate([I.TubeSpec(nx=64)], **kw) == I.EINVAL
