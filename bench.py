@@ -270,6 +270,88 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, size, cmds):
               f"traffic_bytes={t:.4e} algorithmic_bytes={alg:.4e} ratio={t / alg:.3f}")
 
 
+def batch_pass_bytes(vn, elem):
+    """Algorithmic HBM bytes of the three 1D passes over vn velocity nodes
+    (16 planes, 3 FP64 moment fields)."""
+    m = 3 * 8 / 16.0
+    return {"stage3": vn * (2 * elem + 2 * m), "stage4": vn * (4 * elem + 3 * m),
+            "stage5": vn * (3 * elem + 2 * m)}
+
+
+def run_batch(args):
+    """Batched 1D shock tubes: 256 seeded tubes of 256..4096 cells, K 0/2,
+    tau 1e-6..1e-2, 8 + 8 velocities, FP32 storage, CFL 0.5 each."""
+    import torch
+
+    from paper_1909_08390_amd import imexlb as I
+    from paper_1909_08390_amd import workloads as W
+
+    tubes = W.batch_tubes(args.tubes, seed=args.seed)
+    specs = [I.TubeSpec(nx=t.nx, K=t.K, lx=1.0, tau=t.tau, dt=W.tube_dt(t.nx)) for t in tubes]
+    storage = I.F64 if args.batch_f64 else I.F32
+    b = I.Batch(specs, 8, 8, storage)
+    f = [W.tube_fields(t) for t in tubes]
+    b.set_equilibrium([x[0] for x in f], [x[1] for x in f], [x[2] for x in f])
+    tune = b.tune(5)
+    log(f"bench: batch tuner ms/step {tune}, chosen {b.tiling()}")
+    if args.warmup:
+        b.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = b.step_timed(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n = b.moments()[0]
+    ok = bool(torch.isfinite(n).all()) and float(n.min()) > 0
+    cells = b.cells
+    vn = cells * 16
+    elem = 4 if storage == I.F32 else 8
+    pb = batch_pass_bytes(vn, elem)
+    per = {k: ms[i] / args.steps for i, k in enumerate(("stage3", "stage4", "stage5"))}
+    gbs4 = pb["stage4"] / (per["stage4"] * 1e-3) / 1e9
+    value = vn * args.steps / wall
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        # the oracle on the first tubes of the batch until ~10 s of work
+        done, vns, t_cpu, used = 0, 0, 0.0, []
+        for t, sp in zip(tubes, specs):
+            oc = O.Config(d=1, nx=t.nx, lx=1.0, q_phi=8, q_chi=8, K=t.K, tau=t.tau, dt=sp.dt)
+            fn, fu, fT = W.tube_fields(t)
+            F = O.equilibrium(oc, fn, fu, None, fT)
+            c0 = time.perf_counter()
+            O.step(oc, F, args.cpu_steps)
+            t_cpu += time.perf_counter() - c0
+            vns += t.nx * 16 * args.cpu_steps
+            used.append(t.nx)
+            done += 1
+            if t_cpu > 10.0:
+                break
+        cpu = {"value": vns / t_cpu, "unit": "VN/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {done} tubes of the batch (nx {used}), {args.cpu_steps} IMEX "
+                         f"steps each, single-threaded C (-O2), {t_cpu:.1f} s"}
+    out = {
+        "metric": METRIC, "value": value, "unit": "VN/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 storage, f64 moments" if elem == 4 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(tubes)} batched 1D shock tubes, Nx 256..4096 (sum {cells}), "
+                               "K in {0,2}, tau 1e-6..1e-2, 8+8 velocities, CFL 0.5, outflow",
+                   "cells": cells, "planes": 16, "seed": args.seed,
+                   "tiling": {"tile": b.tiling()[0], "order": b.tiling()[1]},
+                   "tuner_ms_per_step": {f"{k[0]},{k[1]}": v for k, v in tune.items()}},
+        "roofline": {"bound": "hbm", "kernel": "stage4 (stage1d_batch_kernel)", "achieved": gbs4,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs4 / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_launch": pb["stage4"],
+                     "note": "working set (~%.0f MB) fits the 256 MB last-level cache"
+                             % ((b.state.numel() * elem * 3) / 1e6)},
+        "pass_ms": per,
+        "state_ok": ok,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +371,10 @@ def main():
                     help="print the HBM traffic summary of two --pmc runs and exit")
     ap.add_argument("--cmd", action="append", default=[],
                     help="command line recorded in a summary")
+    ap.add_argument("--workload", choices=["riemann2d", "batch"], default="riemann2d",
+                    help="riemann2d: the 4096^2 2D step (default); batch: 256 1D tubes")
+    ap.add_argument("--tubes", type=int, default=256)
+    ap.add_argument("--batch-f64", action="store_true")
     args = ap.parse_args()
 
     if args.summarize_stats:
@@ -313,6 +399,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calib:
         copy_calibration(args.copy_calib)
+    if args.workload == "batch":
+        run_batch(args)
+        return
     log(f"bench: {args.size}^2 cells x 128 planes, FP64, {args.warmup} warmup + {args.steps} steps")
     r64, cfg, fields = run_precision(I, W, args.size, I.F64, args.steps, args.warmup, args.seed)
     log(f"bench: FP64 {r64['value']:.3e} VN/s, {r64['ms_per_step']:.2f} ms/step, passes {r64['pass_ms']}")
