@@ -159,6 +159,6 @@ constexpr int kTile1X = 1024;
 constexpr int kBatchTiles[3] = {256, 512, 1024};
 // Tiles are visited in column bands of this many tiles (2D blocking of the
 // work that runs concurrently on one XCD, so halos hit that XCD's L2).
-constexpr int kBand = 8;
+constexpr int kBand = 2;
 
 }  // namespace imexlb

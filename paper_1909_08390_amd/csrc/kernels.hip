@@ -65,16 +65,44 @@ __device__ __forceinline__ double herm_factor(CDp h, int Q, double u,
     return g;
 }
 
+// Median, three-way min / max.  FP32 has single instructions for them
+// (v_med3_f32, v_min3_f32, v_max3_f32); FP64 composes two-way min / max.
 template <typename R>
 __device__ __forceinline__ R med3(R a, R b, R c) {
-    return fmax(fmin(a, b), fmin(fmax(a, b), c));
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_fmed3f(a, b, c);
+    else return fmax(fmin(a, b), fmin(fmax(a, b), c));
+}
+
+template <typename R>
+__device__ __forceinline__ R min3(R a, R b, R c) {
+    return fmin(fmin(a, b), c);
+}
+
+template <typename R>
+__device__ __forceinline__ R max3(R a, R b, R c) {
+    return fmax(fmax(a, b), c);
+}
+
+// x clipped to [lo, hi] (lo <= hi).
+template <typename R>
+__device__ __forceinline__ R clamp(R x, R lo, R hi) {
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_fmed3f(x, lo, hi);
+    else return fmin(fmax(x, lo), hi);
+}
+
+// Two-argument minmod: the signed smaller magnitude when both share a sign,
+// else 0; equal to the median of (0, a, b).
+template <typename R>
+__device__ __forceinline__ R minmod2(R a, R b) {
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_fmed3f(R(0), a, b);
+    else return fmax(fmin(a, b), R(0)) + fmin(fmax(a, b), R(0));
 }
 
 // Four-argument minmod: signed smallest magnitude when all share a sign.
 template <typename R>
 __device__ __forceinline__ R minmod4(R a, R b, R c, R d) {
-    const R mn = fmin(fmin(a, b), fmin(c, d));
-    const R mx = fmax(fmax(a, b), fmax(c, d));
+    const R mn = min3(a, b, fmin(c, d));
+    const R mx = max3(a, b, fmax(c, d));
     return fmax(mn, R(0)) + fmin(mx, R(0));
 }
 
@@ -113,7 +141,7 @@ __device__ __forceinline__ R mp9_face_linear(const R (&dd)[8], R fs, R& t, R& q)
     s = fma(R(-5), dd[7], s);
     constexpr R inv = R(1.0 / 2520.0);
     t = R(4) * dd[3];
-    const R mm = fmax(fmin(dd[4], t), R(0)) + fmin(fmax(dd[4], t), R(0));  // F^MP - F_s
+    const R mm = minmod2(dd[4], t);  // F^MP - F_s
     q = s * fma(s, inv, -mm);
     return fma(s, inv, fs);
 }
@@ -135,9 +163,9 @@ __device__ __forceinline__ R mp9_face_clip(const R (&dd)[8], R fs, R fp, R t, R 
     const R ul = f + u;
     const R lc = fma(R(4.0 / 3.0), mdm, fma(R(0.5), dm1, f));
     const R md = fma(R(0.5), d0 - md0, f);
-    const R lo = fmax(fmin(fmin(f, g), md), fmin(fmin(f, ul), lc));
-    const R hi = fmin(fmax(fmax(f, g), md), fmax(fmax(f, ul), lc));
-    return fmin(fmax(fl, lo), hi);
+    const R lo = fmax(min3(f, g, md), min3(f, ul, lc));   // F^min <= F_s
+    const R hi = fmin(max3(f, g, md), max3(f, ul, lc));   // F^max >= F_s
+    return clamp(fl, lo, hi);
 }
 
 // MP-9 along a line held in registers, upwind-first window w[0 .. L+8]: the
