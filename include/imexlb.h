@@ -142,6 +142,54 @@ imexlb_status imexlb_domain_sums(const imexlb_ctx* ctx, double out[4]);
  * IMEXLB_OK or IMEXLB_ENONPHYS.  Synchronises the stream. */
 imexlb_status imexlb_check_state(const imexlb_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Adjoint (reverse mode) of the step, for gradients of a loss of the
+ * final state with respect to an earlier state or to initial fields.
+ *
+ * Adjoint variables are FP64 plane-sets lam[v][y][x] (the derivative of the
+ * loss with respect to each population), whatever the storage type.  The
+ * adjoint step recomputes the stage sources of the step from its input
+ * state (Sec. III, Table I) in a caller-owned adjoint workspace and then
+ * runs the stages backwards: MP-9 advection transposed (a face that the
+ * monotonicity test clips takes the derivative of the clip branch, Sec. IV),
+ * equilibrium and moment Jacobians transposed (Sec. II), and the relaxation
+ * weights.  It is exact (up to rounding) wherever the limiter decisions are
+ * locally constant; at a decision boundary it returns one one-sided
+ * derivative.
+ * ------------------------------------------------------------------------ */
+
+/* Size of, and binding of, the adjoint workspace (256-byte aligned device
+ * buffer): three plane-sets of the storage type, four FP64 moment sets and
+ * four FP64 plane-sets. */
+size_t imexlb_adjoint_workspace_bytes(const imexlb_ctx* ctx);
+imexlb_status imexlb_adjoint_bind(imexlb_ctx* ctx, void* d_adj_workspace);
+
+/* lam_n = (dF^{n+1}/dF^n)^T lam_np1 for one step taken from the state d_Fn
+ * (storage type, ABI layout; not modified).  lam_np1 and lam_n are distinct
+ * FP64 plane-sets.  Asynchronous.  Errors: ESTATE without an adjoint
+ * workspace, EINVAL for NULL or aliased buffers. */
+imexlb_status imexlb_adjoint_step(imexlb_ctx* ctx, const void* d_Fn, const double* d_lam_np1,
+                                  double* d_lam_n);
+
+/* dF = V^T dA: the transpose of the MP-9 advection operator of
+ * imexlb_advect at the FP64 plane-set d_F (Sec. IV), for an FP64 plane-set
+ * dA; the linearisation follows the limiter decisions at d_F. */
+imexlb_status imexlb_advect_adjoint(const imexlb_ctx* ctx, const double* d_F, const double* d_dA,
+                                    double* d_dF);
+
+/* lam = (dM/dF)^T dM: the adjoint of the moments (n, u_x, u_y, T) of the
+ * plane-set d_F (Sec. II, Eq. Moments_discrete) for given moment adjoints
+ * (FP64 fields; d_duy ignored when d = 1). */
+imexlb_status imexlb_moments_adjoint(imexlb_ctx* ctx, const void* d_F, const double* d_dn,
+                                     const double* d_dux, const double* d_duy, const double* d_dT,
+                                     double* d_lam);
+
+/* Adjoint of imexlb_set_equilibrium: (dn, du_x, du_y, dT) = (dE/d(n,u,T))^T lam
+ * for the equilibrium of the fields (n, u_x, u_y, T) (Sec. II, Eq. gExpanded). */
+imexlb_status imexlb_equilibrium_adjoint(imexlb_ctx* ctx, const double* d_n, const double* d_ux,
+                                         const double* d_uy, const double* d_T, const double* d_lam,
+                                         double* d_dn, double* d_dux, double* d_duy, double* d_dT);
+
 /* Static text for a status; the context's last error message. */
 const char* imexlb_status_string(imexlb_status s);
 const char* imexlb_last_error(const imexlb_ctx* ctx);

@@ -1,0 +1,377 @@
+// Adjoint (reverse-mode) kernels of the IMEX-SSP3(4,3,3) step for gfx950.
+//
+// The reverse sweep through the stages of Table I (orchestrated in
+// adjoint.cpp) needs four operations, each the transpose of a forward
+// building block:
+//   * materialise a stage value  F_i = a S_i + b E(M_i)   (relax on read, Sec. III);
+//   * MP-9 advection transposed: dF = V^T dA, with V the flux difference of
+//     Sec. IV.  A face value is linear in its nine upwind-biased nodes with
+//     the weights of F^L unless the monotonicity test clips it; a clipped
+//     face takes the derivative of the branch the clip selected (F^min or
+//     F^max, through the minmod selections), evaluated with nine-component
+//     dual numbers.  Gather form: each cell sums the contributions of the
+//     faces whose stencils read it (ghost nodes route to the cell they copy);
+//   * the equilibrium Jacobian transposed: dM = (dE/dM)^T dE per cell, with
+//     dg/du = sum_l h_l l a_{l-1} and dg/dT = sum_l h_l l (l-1)/2 a_{l-2}
+//     (Eq. gExpanded; the a_l are Appell polynomials in u with variance T-1);
+//   * the moment Jacobian transposed: dF_v = dM . dM/dF_v (Sec. II,
+//     Eq. Moments_discrete).
+// All adjoint arrays are FP64 plane-sets F[v][cell] and FP64 moment sets
+// M[field][cell] (d + 2 fields: n, u_x, [u_y], T).
+#include "common.hpp"
+#include "device.hpp"
+
+namespace imexlb {
+namespace {
+
+constexpr int kAdjBlock = 256;
+
+// Up to four FP64 plane-sets combined as sum_j c_j Y_j.
+struct Lin4 {
+    const double* y[4];
+    double c[4];
+    int n;
+};
+
+__device__ __forceinline__ double lin_at(const Lin4& L, size_t i) {
+    double r = 0.0;
+    for (int j = 0; j < L.n; ++j) r = fma(L.c[j], L.y[j][i], r);
+    return r;
+}
+
+// g, dg/du, dg/dT of one axis factor (runtime order Q <= kQMax).
+__device__ __forceinline__ void herm_factor_d(CDp h, int Q, double u, double th, double& g, double& gu,
+                                              double& gT) {
+    double am2 = 0.0, am1 = 0.0, a = 1.0;  // a_{l-2}, a_{l-1}, a_l
+    g = 0.0;
+    gu = 0.0;
+    gT = 0.0;
+    for (int l = 0; l < Q; ++l) {
+        if (l == 1) {
+            am2 = am1;
+            am1 = a;
+            a = u;
+        } else if (l > 1) {
+            const double an = fma(u, a, (double)(l - 1) * th * am1);
+            am2 = am1;
+            am1 = a;
+            a = an;
+        }
+        g = fma(h[l], a, g);
+        if (l >= 1) gu = fma(h[l] * (double)l, am1, gu);
+        if (l >= 2) gT = fma(h[l] * (0.5 * l * (l - 1)), am2, gT);
+    }
+}
+
+// ---------------------------------------------------------------- dual numbers
+// Value and gradient over the nine window nodes of one MP-9 face.
+struct D9 {
+    double v;
+    double d[9];
+};
+
+__device__ __forceinline__ D9 dsub(const D9& a, const D9& b) {
+    D9 r;
+    r.v = a.v - b.v;
+    for (int k = 0; k < 9; ++k) r.d[k] = a.d[k] - b.d[k];
+    return r;
+}
+
+// fma(s, a, b) with scalar s (value rounded as the forward's fma)
+__device__ __forceinline__ D9 dfma(double s, const D9& a, const D9& b) {
+    D9 r;
+    r.v = fma(s, a.v, b.v);
+    for (int k = 0; k < 9; ++k) r.d[k] = fma(s, a.d[k], b.d[k]);
+    return r;
+}
+
+__device__ __forceinline__ const D9& dmin(const D9& a, const D9& b) { return b.v < a.v ? b : a; }
+__device__ __forceinline__ const D9& dmax(const D9& a, const D9& b) { return b.v > a.v ? b : a; }
+
+// minmod4 with the derivative of the selected argument (0 when signs differ)
+__device__ __forceinline__ D9 dminmod4(const D9& a, const D9& b, const D9& c, const D9& e) {
+    const D9& mn = dmin(dmin(a, b), dmin(c, e));
+    const D9& mx = dmax(dmax(a, b), dmax(c, e));
+    D9 r;
+    if (mn.v > 0.0) return mn;
+    if (mx.v < 0.0) return mx;
+    r.v = 0.0;
+    for (int k = 0; k < 9; ++k) r.d[k] = 0.0;
+    return r;
+}
+
+// Weights of F^L on the nine nodes F_{s-4} .. F_{s+4} (Sec. IV), times 2520.
+__device__ __forceinline__ double linear_weight(int k) {
+    constexpr double c[9] = {4.0, -41.0, 199.0, -641.0, 1879.0, 1375.0, -305.0, 55.0, -5.0};
+    return c[k] * (1.0 / 2520.0);
+}
+
+// d(face)/d(w[k]) for the upwind-first window w[0..8] (w[4] = F_s): the same
+// decision as the forward (mp9_face_linear), the linear weights when the
+// face is not clipped, else the derivative of the clip.
+__device__ double face_jacobian(const double (&w)[9], int k) {
+    double dd[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dd[j] = w[j + 1] - w[j];
+    double t, q;
+    const double fl = mp9_face_linear<double>(dd, w[4], t, q);
+    if (!(q > 0.0)) return linear_weight(k);
+    D9 W[9];
+    for (int i = 0; i < 9; ++i) {
+        W[i].v = w[i];
+        for (int j = 0; j < 9; ++j) W[i].d[j] = i == j ? 1.0 : 0.0;
+    }
+    D9 Dd[8];
+    for (int j = 0; j < 8; ++j) Dd[j] = dsub(W[j + 1], W[j]);
+    // F^L: value as the forward, gradient the linear weights
+    D9 FL;
+    FL.v = fl;
+    for (int j = 0; j < 9; ++j) FL.d[j] = linear_weight(j);
+    const D9 &f = W[4], &g = W[5];
+    D9 u;  // F^UL = F_s + 4 (F_s - F_{s-1})
+    u.v = f.v + t;
+    for (int j = 0; j < 9; ++j) u.d[j] = f.d[j] + 4.0 * Dd[3].d[j];
+    const D9 cm = dsub(Dd[3], Dd[2]), c0 = dsub(Dd[4], Dd[3]), cp = dsub(Dd[5], Dd[4]);
+    auto lin2 = [](double a, const D9& x, double b, const D9& y) {  // a x + b y, as fma(a, x, b*y)
+        D9 r;
+        r.v = fma(a, x.v, b * y.v);
+        for (int j = 0; j < 9; ++j) r.d[j] = a * x.d[j] + b * y.d[j];
+        return r;
+    };
+    const D9 mdm = dminmod4(lin2(4.0, cm, -1.0, c0), lin2(4.0, c0, -1.0, cm), cm, c0);
+    const D9 md0 = dminmod4(lin2(4.0, c0, -1.0, cp), lin2(4.0, cp, -1.0, c0), c0, cp);
+    const D9 lc = dfma(4.0 / 3.0, mdm, dfma(0.5, Dd[3], f));
+    const D9 md = dfma(0.5, dsub(Dd[4], md0), f);
+    const D9& lo = dmax(dmin(dmin(f, g), md), dmin(dmin(f, u), lc));
+    const D9& hi = dmin(dmax(dmax(f, g), md), dmax(dmax(f, u), lc));
+    if (FL.v < lo.v) return lo.d[k];
+    if (FL.v > hi.v) return hi.d[k];
+    return FL.d[k];
+}
+
+// Adjoint contribution along one axis to node t of a line of n nodes
+// (stride st): sum over the faces whose stencils read t (or a ghost node
+// that copies t) of d(face)/d(node) * d(face), where d(face s) =
+// p/ds (dA_s - dA_{s+1}) for the face between s and s+1 and dA is zero
+// outside the line (outflow) or wraps (periodic).
+__device__ double adj_axis(const double* F, const Lin4& dA, size_t base, long long st, int n, int bc, int t,
+                           double p, double inv_ds) {
+    if (p == 0.0) return 0.0;
+    const bool fwd = p > 0.0;
+    int vlo = t, vhi = t;
+    if (bc == 0) {
+        if (t == 0) vlo = -5;
+        if (t == n - 1) vhi = n + 4;
+    }
+    auto dAat = [&](int i) -> double {
+        if (bc == 0) {
+            if (i < 0 || i >= n) return 0.0;
+        } else {
+            i = bc_map(i, n, 1);
+        }
+        return lin_at(dA, base + (size_t)i * st);
+    };
+    double acc = 0.0;
+    for (int tv = vlo; tv <= vhi; ++tv) {
+        double w17[17];  // nodes tv-8 .. tv+8
+        for (int i = 0; i < 17; ++i) w17[i] = F[base + (size_t)bc_map(tv - 8 + i, n, bc) * st];
+        for (int k = 0; k < 9; ++k) {
+            const int s = fwd ? tv + 4 - k : tv - 5 + k;  // face between s and s+1
+            if (bc == 0 && (s < -1 || s > n - 1)) continue;
+            double fw[9];
+            for (int kk = 0; kk < 9; ++kk) {
+                const int pos = fwd ? s - 4 + kk : s + 5 - kk;
+                fw[kk] = w17[pos - tv + 8];
+            }
+            const double dface = p * inv_ds * (dAat(s) - dAat(s + 1));
+            acc = fma(face_jacobian(fw, k), dface, acc);
+        }
+    }
+    return acc;
+}
+
+// out[v][c] (=|+=) V^T dA at every node, both axes in 2D.
+template <int D>
+__global__ void __launch_bounds__(kAdjBlock) advect_adjoint_kernel(const DevTables* __restrict__ tabp,
+                                                                   const double* __restrict__ F, Lin4 dA,
+                                                                   double* out, int nx, int ny, int bcx,
+                                                                   int bcy, double inv_dx, double inv_dy,
+                                                                   int accumulate) {
+    CTab* tab = (CTab*)tabp;
+    const long long cells = (long long)nx * ny;
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (c >= cells) return;
+    const double px = tab->plane[v].px, py = tab->plane[v].py;
+    const int x = (int)(c % nx), y = (int)(c / nx);
+    const size_t pl = (size_t)v * cells;
+    double r = adj_axis(F, dA, pl + (size_t)y * nx, 1, nx, bcx, x, px, inv_dx);
+    if (D == 2) r += adj_axis(F, dA, pl + (size_t)x, nx, ny, bcy, y, py, inv_dy);
+    out[pl + c] = accumulate ? out[pl + c] + r : r;
+}
+
+// out = a src + b E(M) as FP64 (stage value rebuilt from its moments).
+template <typename S, int D>
+__global__ void __launch_bounds__(kAdjBlock) materialise_kernel(const DevTables* __restrict__ tabp,
+                                                                const S* __restrict__ src,
+                                                                const double* __restrict__ M, double a,
+                                                                double b, double* out, long long cells,
+                                                                double chi_fac) {
+    CTab* tab = (CTab*)tabp;
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const double nn = M[c], u = M[cells + c], w = D == 2 ? M[2 * cells + c] : 0.0;
+    const double th = M[(D + 1) * cells + c] - 1.0;
+    int v = 0;
+    for (int set = 0; set < 2; ++set) {
+        const int Q = tab->q[set];
+        const double pre = set ? chi_fac * nn * (th + 1.0) : nn;
+        for (int ky = 0; ky < (D == 2 ? Q : 1); ++ky) {
+            const double gy = D == 2 ? pre * herm_factor(tab->h[set][ky], Q, w, th) : pre;
+            for (int kx = 0; kx < Q; ++kx, ++v) {
+                const size_t i = (size_t)v * cells + c;
+                out[i] = fma(a, (double)src[i], b * gy * herm_factor(tab->h[set][kx], Q, u, th));
+            }
+        }
+    }
+}
+
+// dM = (dE/dM)^T dE per cell, dE = sum_j c_j Y_j.  Moments (n, u, T) of M.
+template <int D>
+__global__ void __launch_bounds__(kAdjBlock) eq_adjoint_kernel(const DevTables* __restrict__ tabp,
+                                                               const double* __restrict__ M, Lin4 dE,
+                                                               double* dM, long long cells, double chi_fac) {
+    CTab* tab = (CTab*)tabp;
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const double nn = M[c], u = M[cells + c], w = D == 2 ? M[2 * cells + c] : 0.0;
+    const double T = M[(D + 1) * cells + c], th = T - 1.0;
+    double dn = 0.0, dux = 0.0, duy = 0.0, dT = 0.0;
+    int v = 0;
+    for (int set = 0; set < 2; ++set) {
+        const int Q = tab->q[set];
+        const double pre = set ? chi_fac * nn * T : nn;       // P_phi = n, P_chi = (K+D-d) n T
+        const double pre_n = set ? chi_fac * T : 1.0;
+        const double pre_T = set ? chi_fac * nn : 0.0;
+        for (int ky = 0; ky < (D == 2 ? Q : 1); ++ky) {
+            double gy = 1.0, gyu = 0.0, gyT = 0.0;
+            if (D == 2) herm_factor_d(tab->h[set][ky], Q, w, th, gy, gyu, gyT);
+            for (int kx = 0; kx < Q; ++kx, ++v) {
+                double gx, gxu, gxT;
+                herm_factor_d(tab->h[set][kx], Q, u, th, gx, gxu, gxT);
+                const double e = lin_at(dE, (size_t)v * cells + c);
+                dn = fma(e, pre_n * gx * gy, dn);
+                dux = fma(e, pre * gxu * gy, dux);
+                if (D == 2) duy = fma(e, pre * gx * gyu, duy);
+                dT = fma(e, pre_T * gx * gy + pre * (gxT * gy + gx * gyT), dT);
+            }
+        }
+    }
+    dM[c] = dn;
+    dM[cells + c] = dux;
+    if (D == 2) dM[2 * cells + c] = duy;
+    dM[(D + 1) * cells + c] = dT;
+}
+
+// out (=|+=) sum_j c_j Y_j + (dM/dF)^T dM per plane (dM may be NULL).
+// n = sum_phi F, n u = sum_phi p F, (D+K) n T = sum_phi |p|^2 F + sum_chi F - n |u|^2:
+//   dn/dF = [phi], du/dF = [phi] (p - u)/n,
+//   dT/dF = ([phi] |p - u|^2 + [chi]) / ((D+K) n) - [phi] T / n.
+template <int D>
+__global__ void __launch_bounds__(kAdjBlock) mom_adjoint_kernel(const DevTables* __restrict__ tabp,
+                                                                const double* __restrict__ M,
+                                                                const double* __restrict__ dM, Lin4 Y,
+                                                                double* out, long long cells, double dk,
+                                                                int accumulate) {
+    CTab* tab = (CTab*)tabp;
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    double nn = 1.0, u = 0.0, w = 0.0, T = 0.0, gn = 0.0, gu = 0.0, gw = 0.0, gT = 0.0;
+    if (dM) {
+        nn = M[c];
+        u = M[cells + c];
+        w = D == 2 ? M[2 * cells + c] : 0.0;
+        T = M[(D + 1) * cells + c];
+        gn = dM[c];
+        gu = dM[cells + c];
+        gw = D == 2 ? dM[2 * cells + c] : 0.0;
+        gT = dM[(D + 1) * cells + c];
+    }
+    const double inv_n = 1.0 / nn, inv_dkn = 1.0 / (dk * nn);
+    const int np = tab->nplanes;
+    for (int v = 0; v < np; ++v) {
+        const size_t i = (size_t)v * cells + c;
+        double r = lin_at(Y, i);
+        if (dM) {
+            const double px = tab->plane[v].px, py = tab->plane[v].py;
+            if (tab->plane[v].set == 0) {
+                const double ex = px - u, ey = py - w;
+                r += gn + (gu * ex + gw * ey) * inv_n + gT * ((ex * ex + ey * ey) * inv_dkn - T * inv_n);
+            } else {
+                r += gT * inv_dkn;
+            }
+        }
+        out[i] = accumulate ? out[i] + r : r;
+    }
+}
+
+Lin4 make_lin(int n, const double* const* y, const double* cf) {
+    Lin4 L;
+    L.n = n;
+    for (int j = 0; j < 4; ++j) {
+        L.y[j] = j < n ? y[j] : nullptr;
+        L.c[j] = j < n ? cf[j] : 0.0;
+    }
+    return L;
+}
+
+}  // namespace
+
+hipError_t launch_materialise(int d, bool f32, const DevTables* tab, const void* src, const double* M,
+                              double a, double b, double* out, long long cells, double chi_fac,
+                              hipStream_t s) {
+    const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
+    if (d == 2) {
+        if (f32) hipLaunchKernelGGL((materialise_kernel<float, 2>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const float*)src, M, a, b, out, cells, chi_fac);
+        else hipLaunchKernelGGL((materialise_kernel<double, 2>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const double*)src, M, a, b, out, cells, chi_fac);
+    } else {
+        if (f32) hipLaunchKernelGGL((materialise_kernel<float, 1>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const float*)src, M, a, b, out, cells, chi_fac);
+        else hipLaunchKernelGGL((materialise_kernel<double, 1>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const double*)src, M, a, b, out, cells, chi_fac);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const double* F, int ny_in,
+                                 const double* const* y, const double* cf, double* out, int nx, int ny,
+                                 int bcx, int bcy, double inv_dx, double inv_dy, bool accumulate,
+                                 hipStream_t s) {
+    const Lin4 L = make_lin(ny_in, y, cf);
+    const long long cells = (long long)nx * ny;
+    const dim3 grid((unsigned)((cells + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
+    if (d == 2)
+        hipLaunchKernelGGL((advect_adjoint_kernel<2>), grid, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, ny, bcx, bcy, inv_dx, inv_dy, (int)accumulate);
+    else
+        hipLaunchKernelGGL((advect_adjoint_kernel<1>), grid, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, 1, bcx, 0, inv_dx, 0.0, (int)accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_eq_adjoint(int d, const DevTables* tab, const double* M, int ny_in, const double* const* y,
+                             const double* cf, double* dM, long long cells, double chi_fac, hipStream_t s) {
+    const Lin4 L = make_lin(ny_in, y, cf);
+    const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
+    if (d == 2) hipLaunchKernelGGL((eq_adjoint_kernel<2>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
+    else hipLaunchKernelGGL((eq_adjoint_kernel<1>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
+    return hipGetLastError();
+}
+
+hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, const double* dM, int ny_in,
+                              const double* const* y, const double* cf, double* out, long long cells,
+                              double dk, bool accumulate, hipStream_t s) {
+    const Lin4 L = make_lin(ny_in, y, cf);
+    const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
+    if (d == 2) hipLaunchKernelGGL((mom_adjoint_kernel<2>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dM, L, out, cells, dk, (int)accumulate);
+    else hipLaunchKernelGGL((mom_adjoint_kernel<1>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dM, L, out, cells, dk, (int)accumulate);
+    return hipGetLastError();
+}
+
+}  // namespace imexlb

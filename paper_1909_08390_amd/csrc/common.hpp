@@ -134,6 +134,21 @@ hipError_t launch_moments(int d, bool f32, const DevTables* tab, const void* F, 
 hipError_t launch_domain_sums(int d, const double* M, long long cells, double dk,
                               double* partial, int nblocks, double* out4, hipStream_t s);
 hipError_t launch_check(int d, const double* M, long long cells, int* flag, hipStream_t s);
+// Adjoint building blocks (adjoint.hip).  y / cf: up to four FP64
+// plane-sets combined as sum_j cf[j] y[j].
+hipError_t launch_materialise(int d, bool f32, const DevTables* tab, const void* src, const double* M,
+                              double a, double b, double* out, long long cells, double chi_fac,
+                              hipStream_t s);
+hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const double* F, int ny_in,
+                                 const double* const* y, const double* cf, double* out, int nx, int ny,
+                                 int bcx, int bcy, double inv_dx, double inv_dy, bool accumulate,
+                                 hipStream_t s);
+hipError_t launch_eq_adjoint(int d, const DevTables* tab, const double* M, int ny_in, const double* const* y,
+                             const double* cf, double* dM, long long cells, double chi_fac, hipStream_t s);
+hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, const double* dM, int ny_in,
+                              const double* const* y, const double* cf, double* out, long long cells,
+                              double dk, bool accumulate, hipStream_t s);
+
 // Batched 1D passes: one launch covers every tile of every tube.  targs[i]
 // holds tube i's arguments for this pass; tiles[j] = (tube, first cell).
 hipError_t launch_stage1d_batch(bool f32, int kind, int qm, int tile, const StageArgs* targs,

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
 
@@ -29,6 +30,7 @@ struct imexlb_ctx {
     int nred = 0;
     void* d_state = nullptr;
     void* d_work = nullptr;
+    void* d_adj = nullptr;       // adjoint workspace (caller-owned)
     bool have_state = false;
     std::string err;
 };
@@ -700,6 +702,183 @@ imexlb_status imexlb_check_state(const imexlb_ctx* c) {
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(m, e, "check_state");
     return h ? fail(m, IMEXLB_ENONPHYS, "check_state: non-physical moments") : IMEXLB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adjoint of one IMEX step (reverse sweep through the stages of Table I).
+// ---------------------------------------------------------------------------
+namespace {
+
+// Adjoint workspace: F scratch | G3 | G4 (storage type) | M^n | M3 | M4 | dM
+// (FP64 moment sets) | X1 | X2 | X3 | X4 (FP64 plane-sets).
+struct AdjLayout {
+    size_t ps, ms, pd;  // bytes: storage plane-set, FP64 moment set, FP64 plane-set
+    size_t total() const { return 3 * ps + 4 * ms + 4 * pd; }
+};
+
+AdjLayout adj_layout(const imexlb_ctx* c) {
+    AdjLayout L;
+    L.ps = align256((size_t)c->nplanes * c->cells * c->elem);
+    L.ms = align256((size_t)c->nf * c->cells * sizeof(double));
+    L.pd = align256((size_t)c->nplanes * c->cells * sizeof(double));
+    return L;
+}
+
+void* adj_s(const imexlb_ctx* c, int i) { return (char*)c->d_adj + (size_t)i * adj_layout(c).ps; }
+double* adj_m(const imexlb_ctx* c, int i) {
+    const AdjLayout L = adj_layout(c);
+    return (double*)((char*)c->d_adj + 3 * L.ps + (size_t)i * L.ms);
+}
+double* adj_x(const imexlb_ctx* c, int i) {
+    const AdjLayout L = adj_layout(c);
+    return (double*)((char*)c->d_adj + 3 * L.ps + 4 * L.ms + (size_t)i * L.pd);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t imexlb_adjoint_workspace_bytes(const imexlb_ctx* c) { return c ? adj_layout(c).total() : 0; }
+
+imexlb_status imexlb_adjoint_bind(imexlb_ctx* c, void* d_adj) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!d_adj) return fail(c, IMEXLB_EINVAL, "adjoint_bind: NULL buffer");
+    if ((uintptr_t)d_adj & 255) return fail(c, IMEXLB_EINVAL, "adjoint_bind: buffer must be 256-byte aligned");
+    c->d_adj = d_adj;
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_adjoint_step(imexlb_ctx* c, const void* Fn, const double* lam1, double* lam0) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!c->d_adj) return fail(c, IMEXLB_ESTATE, "adjoint_step: no adjoint workspace bound");
+    if (!Fn || !lam1 || !lam0) return fail(c, IMEXLB_EINVAL, "adjoint_step: NULL buffer");
+    if ((const void*)lam1 == (const void*)lam0) return fail(c, IMEXLB_EINVAL, "adjoint_step: lam1 and lam0 alias");
+    const int d = c->cfg.d;
+    const bool f32 = c->cfg.storage == IMEXLB_F32;
+    const long long cells = c->cells;
+    const double chi = (double)(c->cfg.K + kDTotal - d), dk = (double)(kDTotal + c->cfg.K);
+    hipStream_t s = c->stream;
+    // forward recompute of the stage sources: G3 = S_3, G4 = S_4 and moments
+    void* Fs = adj_s(c, 0);
+    void* G3 = adj_s(c, 1);
+    void* G4 = adj_s(c, 2);
+    double *Mn = adj_m(c, 0), *M3 = adj_m(c, 1), *M4 = adj_m(c, 2), *dM = adj_m(c, 3);
+    double *X1 = adj_x(c, 0), *X2 = adj_x(c, 1), *X3 = adj_x(c, 2), *X4 = adj_x(c, 3);
+    StageArgs a = base_args(c);
+    StageArgs pa[3];
+    pass_args(a, Fs, G3, G4, Mn, M3, M4, pa);
+    hipError_t e = hipMemcpyAsync(Fs, Fn, imexlb_state_bytes(c), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_moments(d, f32, c->d_tab, Fn, Mn, cells, cells, dk, s);
+    if (e == hipSuccess) e = launch_stage(d, f32, kStage3, pa[0], s);
+    if (e == hipSuccess) e = launch_stage(d, f32, kStage4, pa[1], s);
+    // coefficients (w = dt/tau, cc = alpha w)
+    const double dt = a.dt, w = a.omega, cc = kAlpha * w, a1 = a.a1, a2 = a.a2;
+    const double b2 = cc * cc / ((1.0 + cc) * (1.0 + cc));
+    constexpr double be = 0.06042356519705, et = 0.12915286960590;  // Table I
+    const double ka = 0.5 - be - et - kAlpha;
+    const int np = c->nplanes, nx = c->cfg.nx, ny = d == 2 ? c->cfg.ny : 1;
+    const double idx = a.inv_dx, idy = a.inv_dy;
+    auto adv = [&](const double* F, std::initializer_list<const double*> ys, std::initializer_list<double> cs,
+                   double* out) {
+        return launch_advect_adjoint(d, c->d_tab, np, F, (int)ys.size(), ys.begin(), cs.begin(), out, nx, ny,
+                                     c->cfg.bc_x, c->cfg.bc_y, idx, idy, false, s);
+    };
+    auto eqt = [&](const double* M, std::initializer_list<const double*> ys, std::initializer_list<double> cs) {
+        return launch_eq_adjoint(d, c->d_tab, M, (int)ys.size(), ys.begin(), cs.begin(), dM, cells, chi, s);
+    };
+    auto momt = [&](const double* M, std::initializer_list<const double*> ys, std::initializer_list<double> cs,
+                    double* out) {
+        return launch_mom_adjoint(d, c->d_tab, M, dM, (int)ys.size(), ys.begin(), cs.begin(), out, cells, dk,
+                                  false, s);
+    };
+    const double* L = lam1;
+    // stage 4: F4 = a1 S4 + c a1 E4, dA4 = -(2/3) dt L, d(dF4) = -(2/3) L
+    if (e == hipSuccess) e = launch_materialise(d, f32, c->d_tab, G4, M4, a1, cc * a1, X1, cells, chi, s);
+    if (e == hipSuccess) e = adv(X1, {L}, {-(2.0 / 3.0) * dt}, X2);
+    if (e == hipSuccess) e = eqt(M4, {X2, L}, {cc * a1, (2.0 / 3.0) * w * a1});
+    if (e == hipSuccess) e = momt(M4, {X2, L}, {a1, -(2.0 / 3.0) * w * a1}, X3);  // X3 = dS4
+    // stage 3: dA3 = -(1/6) dt L - dt/4 dS4, d(dF3) = -(1/6) L - kappa dS4
+    if (e == hipSuccess) e = launch_materialise(d, f32, c->d_tab, G3, M3, a1, cc * a1, X1, cells, chi, s);
+    if (e == hipSuccess) e = adv(X1, {L, X3}, {-dt / 6.0, -0.25 * dt}, X2);
+    if (e == hipSuccess) e = eqt(M3, {X2, L, X3}, {cc * a1, w * a1 / 6.0, ka * w * a1});
+    if (e == hipSuccess) e = momt(M3, {X2, L, X3}, {a1, -w * a1 / 6.0, -ka * w * a1}, X1);  // X1 = dS3
+    // stages 2 and 1: F2 = a2 F^n + b2 E^n, dA2 = -(1/6) dt L - dt/4 dS4 - dt dS3,
+    // d(dF1) = -beta dS4, d(dF2) = -(1/6) L - eta dS4 - (1 - alpha) dS3
+    if (e == hipSuccess) e = launch_materialise(d, f32, c->d_tab, Fn, Mn, a2, b2, X2, cells, chi, s);
+    if (e == hipSuccess) e = adv(X2, {L, X3, X1}, {-dt / 6.0, -0.25 * dt, -dt}, X4);
+    if (e == hipSuccess)
+        e = eqt(Mn, {X4, X3, L, X1}, {b2, w * a1 * be + w * a2 * et, w * a2 / 6.0, w * a2 * (1.0 - kAlpha)});
+    if (e == hipSuccess)
+        e = momt(Mn, {L, X3, X1, X4},
+                 {1.0 - w * a2 / 6.0, 1.0 - w * a1 * be - w * a2 * et, 1.0 - w * a2 * (1.0 - kAlpha), a2}, lam0);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_advect_adjoint(const imexlb_ctx* c, const double* F, const double* dA, double* dF) {
+    if (!c) return IMEXLB_EINVAL;
+    imexlb_ctx* m = const_cast<imexlb_ctx*>(c);
+    if (!F || !dA || !dF) return fail(m, IMEXLB_EINVAL, "advect_adjoint: NULL buffer");
+    const StageArgs a = base_args(c);
+    const double* ys[1] = {dA};
+    const double cs[1] = {1.0};
+    hipError_t e = launch_advect_adjoint(c->cfg.d, c->d_tab, c->nplanes, F, 1, ys, cs, dF, c->cfg.nx,
+                                         c->cfg.d == 2 ? c->cfg.ny : 1, c->cfg.bc_x, c->cfg.bc_y, a.inv_dx,
+                                         a.inv_dy, false, c->stream);
+    if (e != hipSuccess) return hip_fail(m, e, "advect_adjoint");
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_moments_adjoint(imexlb_ctx* c, const void* F, const double* dn, const double* dux,
+                                     const double* duy, const double* dT, double* lam) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!c->d_adj) return fail(c, IMEXLB_ESTATE, "moments_adjoint: no adjoint workspace bound");
+    const int d = c->cfg.d;
+    if (!F || !dn || !dux || !dT || (d == 2 && !duy) || !lam)
+        return fail(c, IMEXLB_EINVAL, "moments_adjoint: NULL buffer");
+    const long long cells = c->cells;
+    const size_t fb = (size_t)cells * sizeof(double);
+    double *M = adj_m(c, 0), *dM = adj_m(c, 3);
+    hipStream_t s = c->stream;
+    hipError_t e = launch_moments(d, c->cfg.storage == IMEXLB_F32, c->d_tab, F, M, cells, cells,
+                                  (double)(kDTotal + c->cfg.K), s);
+    const double* src[4] = {dn, dux, d == 2 ? duy : dT, dT};
+    for (int f = 0; f < c->nf && e == hipSuccess; ++f)
+        e = hipMemcpyAsync(dM + (size_t)f * cells, src[f], fb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = launch_mom_adjoint(d, c->d_tab, M, dM, 0, nullptr, nullptr, lam, cells, (double)(kDTotal + c->cfg.K),
+                               false, s);
+    if (e != hipSuccess) return hip_fail(c, e, "moments_adjoint");
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_equilibrium_adjoint(imexlb_ctx* c, const double* n, const double* ux, const double* uy,
+                                         const double* T, const double* lam, double* dn, double* dux,
+                                         double* duy, double* dT) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!c->d_adj) return fail(c, IMEXLB_ESTATE, "equilibrium_adjoint: no adjoint workspace bound");
+    const int d = c->cfg.d;
+    if (!n || !ux || !T || !lam || !dn || !dux || !dT || (d == 2 && (!uy || !duy)))
+        return fail(c, IMEXLB_EINVAL, "equilibrium_adjoint: NULL buffer");
+    const long long cells = c->cells;
+    const size_t fb = (size_t)cells * sizeof(double);
+    double *M = adj_m(c, 0), *dM = adj_m(c, 3);
+    hipStream_t s = c->stream;
+    const double* src[4] = {n, ux, d == 2 ? uy : T, T};
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < c->nf && e == hipSuccess; ++f)
+        e = hipMemcpyAsync(M + (size_t)f * cells, src[f], fb, hipMemcpyDeviceToDevice, s);
+    const double* ys[1] = {lam};
+    const double cs[1] = {1.0};
+    if (e == hipSuccess)
+        e = launch_eq_adjoint(d, c->d_tab, M, 1, ys, cs, dM, cells, (double)(c->cfg.K + kDTotal - d), s);
+    double* dst[4] = {dn, dux, d == 2 ? duy : dT, dT};
+    for (int f = 0; f < c->nf && e == hipSuccess; ++f)
+        e = hipMemcpyAsync(dst[f], dM + (size_t)f * cells, fb, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "equilibrium_adjoint");
+    return IMEXLB_OK;
 }
 
 }  // extern "C"

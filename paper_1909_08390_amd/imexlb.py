@@ -83,6 +83,13 @@ def lib():
         L.imexlb_status_string.restype = ctypes.c_char_p
         L.imexlb_last_error.argtypes = [_vp]
         L.imexlb_last_error.restype = ctypes.c_char_p
+        L.imexlb_adjoint_workspace_bytes.argtypes = [_vp]
+        L.imexlb_adjoint_workspace_bytes.restype = ctypes.c_size_t
+        L.imexlb_adjoint_bind.argtypes = [_vp, _vp]
+        L.imexlb_adjoint_step.argtypes = [_vp, _vp, _vp, _vp]
+        L.imexlb_moments_adjoint.argtypes = [_vp] * 7
+        L.imexlb_advect_adjoint.argtypes = [_vp] * 4
+        L.imexlb_equilibrium_adjoint.argtypes = [_vp] * 10
         _ll = ctypes.c_longlong
         L.imexlb_batch_create.argtypes = [ctypes.POINTER(CTube), ctypes.c_int, ctypes.c_int,
                                           ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)]
@@ -286,6 +293,65 @@ class Solver:
 
     def check_state(self) -> int:
         return self.L.imexlb_check_state(self._h)
+
+    # --------------------------------------------------------------- adjoint
+    def adjoint_bind(self):
+        """Allocate and bind the adjoint workspace (once)."""
+        if getattr(self, "adj_workspace", None) is None:
+            torch = self.torch
+            nb = self.L.imexlb_adjoint_workspace_bytes(self._h)
+            self.adj_workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            self._check(self.L.imexlb_adjoint_bind(self._h, _vp(self.adj_workspace.data_ptr())),
+                        "adjoint_bind")
+
+    def _dev_planes64(self, x):
+        t = self.torch.as_tensor(x, dtype=self.torch.float64, device=self.device).contiguous()
+        assert tuple(t.shape) == tuple(self.cfg.shape)
+        return t
+
+    def adjoint_step(self, Fn, lam1):
+        """(dF^{n+1}/dF^n)^T lam1 for the step taken from state Fn."""
+        self.adjoint_bind()
+        Fn = self.torch.as_tensor(Fn, dtype=self.state_dtype, device=self.device).contiguous()
+        lam1 = self._dev_planes64(lam1)
+        lam0 = self.torch.empty_like(lam1)
+        self._check(self.L.imexlb_adjoint_step(self._h, _vp(Fn.data_ptr()), _vp(lam1.data_ptr()),
+                                               _vp(lam0.data_ptr())), "adjoint_step")
+        return lam0
+
+    def advect_adjoint(self, F, dA):
+        """V^T dA at the FP64 plane-set F (transpose of advect)."""
+        F = self._dev_planes64(F)
+        dA = self._dev_planes64(dA)
+        dF = self.torch.empty_like(dA)
+        self._check(self.L.imexlb_advect_adjoint(self._h, _vp(F.data_ptr()), _vp(dA.data_ptr()),
+                                                 _vp(dF.data_ptr())), "advect_adjoint")
+        return dF
+
+    def moments_adjoint(self, F, dn, dux, duy, dT):
+        self.adjoint_bind()
+        torch = self.torch
+        F = torch.as_tensor(F, dtype=self.state_dtype, device=self.device).contiguous()
+        f = [self._dev64(x if x is not None else np.zeros(self.cfg.field_shape))
+             for x in (dn, dux, duy, dT)]
+        lam = torch.empty(self.cfg.shape, dtype=torch.float64, device=self.device)
+        self._check(self.L.imexlb_moments_adjoint(self._h, _vp(F.data_ptr()),
+                                                  *[_vp(t.data_ptr()) for t in f],
+                                                  _vp(lam.data_ptr())), "moments_adjoint")
+        return lam
+
+    def equilibrium_adjoint(self, n, ux, uy, T, lam):
+        """Gradients (dn, dux, duy, dT) of <lam, E(n, u, T)>."""
+        self.adjoint_bind()
+        torch = self.torch
+        f = [self._dev64(x if x is not None else np.zeros(self.cfg.field_shape)) for x in (n, ux, uy, T)]
+        lam = self._dev_planes64(lam)
+        out = [torch.empty(self.cfg.field_shape, dtype=torch.float64, device=self.device) for _ in range(4)]
+        self._check(self.L.imexlb_equilibrium_adjoint(self._h, *[_vp(t.data_ptr()) for t in f],
+                                                      _vp(lam.data_ptr()),
+                                                      *[_vp(t.data_ptr()) for t in out]),
+                    "equilibrium_adjoint")
+        return tuple(out)
 
 
 @dataclass
