@@ -352,6 +352,53 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_adjoint(args):
+    """Gradient of a density loss through a checkpointed rollout: 512^2
+    periodic, 8 x 8 velocities per distribution, 200 steps, checkpoints every
+    20 steps, FP32 storage; seeded Fourier density, u = 0, P = 1."""
+    import torch
+
+    from paper_1909_08390_amd import adjoint as A
+    from paper_1909_08390_amd import imexlb as I
+    from paper_1909_08390_amd import workloads as W
+
+    N, steps, every = args.adj_size, args.adj_steps, 20
+    dt = 0.5 / N / PMAX8
+    cfg = I.Config(d=2, nx=N, ny=N, q_phi=8, q_chi=8, K=2, tau=1e-6, dt=dt, bc_x=I.PERIODIC,
+                   bc_y=I.PERIODIC, storage=I.F32)
+    s = I.Solver(cfg)
+    n0 = torch.as_tensor(W.fourier_density(N, N, seed=args.seed), device="cuda")
+    target = torch.as_tensor(W.fourier_density(N, N, seed=args.seed + 1), device="cuda")
+    A.density_loss_gradient(s, n0, target, 2, every=every)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    zero = torch.zeros_like(n0)
+    s.set_equilibrium(n0, zero, zero, 1.0 / n0)
+    s.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss, grad = A.density_loss_gradient(s, n0, target, steps, every=every)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    vn = N * N * cfg.planes * steps
+    out = {
+        "metric": "velocity-node updates/s per IMEX step, forward + adjoint (gradient)",
+        "value": vn / t_grad, "unit": "VN/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": 1e3 * t_grad / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 storage, f64 moments and adjoint", "data": "synthetic",
+        "config": {"workload": f"2D periodic {N}x{N}, 8x8 velocities per f and g, {steps} steps, "
+                               f"checkpoint every {every}; loss 1/2 sum (n - n*)^2, gradient "
+                               "w.r.t. the initial density (u = 0, P = 1)",
+                   "cells": N * N, "planes": cfg.planes, "seed": args.seed},
+        "forward_only_ms_per_step": 1e3 * t_fwd / steps,
+        "gradient_over_forward": t_grad / t_fwd,
+        "loss": loss,
+        "grad_norm": float(grad.norm()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,8 +418,11 @@ def main():
                     help="print the HBM traffic summary of two --pmc runs and exit")
     ap.add_argument("--cmd", action="append", default=[],
                     help="command line recorded in a summary")
-    ap.add_argument("--workload", choices=["riemann2d", "batch"], default="riemann2d",
-                    help="riemann2d: the 4096^2 2D step (default); batch: 256 1D tubes")
+    ap.add_argument("--workload", choices=["riemann2d", "batch", "adjoint"], default="riemann2d",
+                    help="riemann2d: the 4096^2 2D step (default); batch: 256 1D tubes; "
+                         "adjoint: gradient through a 512^2 rollout")
+    ap.add_argument("--adj-size", type=int, default=512)
+    ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--tubes", type=int, default=256)
     ap.add_argument("--batch-f64", action="store_true")
     args = ap.parse_args()
@@ -401,6 +451,9 @@ def main():
         copy_calibration(args.copy_calib)
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "adjoint":
+        run_adjoint(args)
         return
     log(f"bench: {args.size}^2 cells x 128 planes, FP64, {args.warmup} warmup + {args.steps} steps")
     r64, cfg, fields = run_precision(I, W, args.size, I.F64, args.steps, args.warmup, args.seed)

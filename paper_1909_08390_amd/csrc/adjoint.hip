@@ -7,10 +7,10 @@
 //   * MP-9 advection transposed: dF = V^T dA, with V the flux difference of
 //     Sec. IV.  A face value is linear in its nine upwind-biased nodes with
 //     the weights of F^L unless the monotonicity test clips it; a clipped
-//     face takes the derivative of the branch the clip selected (F^min or
-//     F^max, through the minmod selections), evaluated with nine-component
-//     dual numbers.  Gather form: each cell sums the contributions of the
-//     faces whose stencils read it (ghost nodes route to the cell they copy);
+//     face takes the derivative of the candidate the clip selected (F^min or
+//     F^max, through the minmod selections).  Gather form: each cell sums
+//     the contributions of the faces whose stencils read it (ghost nodes
+//     route to the cell they copy);
 //   * the equilibrium Jacobian transposed: dM = (dE/dM)^T dE per cell, with
 //     dg/du = sum_l h_l l a_{l-1} and dg/dT = sum_l h_l l (l-1)/2 a_{l-2}
 //     (Eq. gExpanded; the a_l are Appell polynomials in u with variance T-1);
@@ -63,41 +63,55 @@ __device__ __forceinline__ void herm_factor_d(CDp h, int Q, double u, double th,
     }
 }
 
-// ---------------------------------------------------------------- dual numbers
-// Value and gradient over the nine window nodes of one MP-9 face.
-struct D9 {
-    double v;
-    double d[9];
-};
-
-__device__ __forceinline__ D9 dsub(const D9& a, const D9& b) {
-    D9 r;
-    r.v = a.v - b.v;
-    for (int k = 0; k < 9; ++k) r.d[k] = a.d[k] - b.d[k];
-    return r;
+// ---------------------------------------------------- clipped-face derivative
+// Index of the smallest / largest of four values, the first on ties (the
+// order the forward's nested min / max resolves them).
+__device__ __forceinline__ int argmin4(const double (&x)[4]) {
+    int i = 0;
+    if (x[1] < x[i]) i = 1;
+    if (x[2] < x[i]) i = 2;
+    if (x[3] < x[i]) i = 3;
+    return i;
+}
+__device__ __forceinline__ int argmax4(const double (&x)[4]) {
+    int i = 0;
+    if (x[1] > x[i]) i = 1;
+    if (x[2] > x[i]) i = 2;
+    if (x[3] > x[i]) i = 3;
+    return i;
 }
 
-// fma(s, a, b) with scalar s (value rounded as the forward's fma)
-__device__ __forceinline__ D9 dfma(double s, const D9& a, const D9& b) {
-    D9 r;
-    r.v = fma(s, a.v, b.v);
-    for (int k = 0; k < 9; ++k) r.d[k] = fma(s, a.d[k], b.d[k]);
-    return r;
+// Four-argument minmod: the selected argument (0..3), or -1 for 0.
+__device__ __forceinline__ int minmod4_sel(const double (&x)[4], double& val) {
+    const int lo = argmin4(x), hi = argmax4(x);
+    if (x[lo] > 0.0) {
+        val = x[lo];
+        return lo;
+    }
+    if (x[hi] < 0.0) {
+        val = x[hi];
+        return hi;
+    }
+    val = 0.0;
+    return -1;
 }
 
-__device__ __forceinline__ const D9& dmin(const D9& a, const D9& b) { return b.v < a.v ? b : a; }
-__device__ __forceinline__ const D9& dmax(const D9& a, const D9& b) { return b.v > a.v ? b : a; }
+// d/d(w_k) of the curvatures C_{s-1}, C_s, C_{s+1} (w_4 = F_s).
+__device__ __forceinline__ double dcurv(int j, int k) {  // C at node j: w_{j-1} - 2 w_j + w_{j+1}
+    return (k == j - 1 ? 1.0 : 0.0) + (k == j ? -2.0 : 0.0) + (k == j + 1 ? 1.0 : 0.0);
+}
 
-// minmod4 with the derivative of the selected argument (0 when signs differ)
-__device__ __forceinline__ D9 dminmod4(const D9& a, const D9& b, const D9& c, const D9& e) {
-    const D9& mn = dmin(dmin(a, b), dmin(c, e));
-    const D9& mx = dmax(dmax(a, b), dmax(c, e));
-    D9 r;
-    if (mn.v > 0.0) return mn;
-    if (mx.v < 0.0) return mx;
-    r.v = 0.0;
-    for (int k = 0; k < 9; ++k) r.d[k] = 0.0;
-    return r;
+// Component k of the gradient of the selected argument of
+// minmod4(4 Ca - Cb, 4 Cb - Ca, Ca, Cb), curvatures at nodes ja, jb.
+__device__ __forceinline__ double dminmod_arg(int sel, int ja, int jb, int k) {
+    const double ga = dcurv(ja, k), gb = dcurv(jb, k);
+    switch (sel) {
+        case 0: return 4.0 * ga - gb;
+        case 1: return 4.0 * gb - ga;
+        case 2: return ga;
+        case 3: return gb;
+        default: return 0.0;
+    }
 }
 
 // Weights of F^L on the nine nodes F_{s-4} .. F_{s+4} (Sec. IV), times 2520.
@@ -108,7 +122,9 @@ __device__ __forceinline__ double linear_weight(int k) {
 
 // d(face)/d(w[k]) for the upwind-first window w[0..8] (w[4] = F_s): the same
 // decision as the forward (mp9_face_linear), the linear weights when the
-// face is not clipped, else the derivative of the clip.
+// face is not clipped, else the derivative of the clip's selected branch
+// (candidates F_s, F_{s+1}, MD, UL, LC; F^min / F^max by three-way min /
+// max as in the forward).
 __device__ double face_jacobian(const double (&w)[9], int k) {
     double dd[8];
 #pragma unroll
@@ -116,78 +132,94 @@ __device__ double face_jacobian(const double (&w)[9], int k) {
     double t, q;
     const double fl = mp9_face_linear<double>(dd, w[4], t, q);
     if (!(q > 0.0)) return linear_weight(k);
-    D9 W[9];
-    for (int i = 0; i < 9; ++i) {
-        W[i].v = w[i];
-        for (int j = 0; j < 9; ++j) W[i].d[j] = i == j ? 1.0 : 0.0;
-    }
-    D9 Dd[8];
-    for (int j = 0; j < 8; ++j) Dd[j] = dsub(W[j + 1], W[j]);
-    // F^L: value as the forward, gradient the linear weights
-    D9 FL;
-    FL.v = fl;
-    for (int j = 0; j < 9; ++j) FL.d[j] = linear_weight(j);
-    const D9 &f = W[4], &g = W[5];
-    D9 u;  // F^UL = F_s + 4 (F_s - F_{s-1})
-    u.v = f.v + t;
-    for (int j = 0; j < 9; ++j) u.d[j] = f.d[j] + 4.0 * Dd[3].d[j];
-    const D9 cm = dsub(Dd[3], Dd[2]), c0 = dsub(Dd[4], Dd[3]), cp = dsub(Dd[5], Dd[4]);
-    auto lin2 = [](double a, const D9& x, double b, const D9& y) {  // a x + b y, as fma(a, x, b*y)
-        D9 r;
-        r.v = fma(a, x.v, b * y.v);
-        for (int j = 0; j < 9; ++j) r.d[j] = a * x.d[j] + b * y.d[j];
-        return r;
+    const double f = w[4], g = w[5], ul = f + t;
+    const double cm = dd[3] - dd[2], c0 = dd[4] - dd[3], cp = dd[5] - dd[4];
+    double vm, v0;
+    const double am[4] = {fma(4.0, cm, -c0), fma(4.0, c0, -cm), cm, c0};
+    const double a0[4] = {fma(4.0, c0, -cp), fma(4.0, cp, -c0), c0, cp};
+    const int sm = minmod4_sel(am, vm);   // d^M4 at s - 1/2
+    const int s0 = minmod4_sel(a0, v0);   // d^M4 at s + 1/2
+    const double lc = fma(4.0 / 3.0, vm, fma(0.5, dd[3], f));
+    const double md = fma(0.5, dd[4] - v0, f);
+    // candidates: 0 f, 1 g, 2 md, 3 ul, 4 lc
+    const double cv[5] = {f, g, md, ul, lc};
+    auto pick_min3 = [&](int i, int j, int l) {  // fmin(fmin(x_i, x_j), x_l)
+        int r = cv[j] < cv[i] ? j : i;
+        return cv[l] < cv[r] ? l : r;
     };
-    const D9 mdm = dminmod4(lin2(4.0, cm, -1.0, c0), lin2(4.0, c0, -1.0, cm), cm, c0);
-    const D9 md0 = dminmod4(lin2(4.0, c0, -1.0, cp), lin2(4.0, cp, -1.0, c0), c0, cp);
-    const D9 lc = dfma(4.0 / 3.0, mdm, dfma(0.5, Dd[3], f));
-    const D9 md = dfma(0.5, dsub(Dd[4], md0), f);
-    const D9& lo = dmax(dmin(dmin(f, g), md), dmin(dmin(f, u), lc));
-    const D9& hi = dmin(dmax(dmax(f, g), md), dmax(dmax(f, u), lc));
-    if (FL.v < lo.v) return lo.d[k];
-    if (FL.v > hi.v) return hi.d[k];
-    return FL.d[k];
+    auto pick_max3 = [&](int i, int j, int l) {
+        int r = cv[j] > cv[i] ? j : i;
+        return cv[l] > cv[r] ? l : r;
+    };
+    const int a = pick_min3(0, 1, 2), b = pick_min3(0, 3, 4);
+    const int lo = cv[b] > cv[a] ? b : a;
+    const int c = pick_max3(0, 1, 2), e = pick_max3(0, 3, 4);
+    const int hi = cv[e] < cv[c] ? e : c;
+    int sel;
+    if (fl < cv[lo]) sel = lo;
+    else if (fl > cv[hi]) sel = hi;
+    else return linear_weight(k);
+    const double ek3 = k == 3 ? 1.0 : 0.0, ek4 = k == 4 ? 1.0 : 0.0, ek5 = k == 5 ? 1.0 : 0.0;
+    switch (sel) {
+        case 0: return ek4;                                               // F_s
+        case 1: return ek5;                                               // F_{s+1}
+        case 2: return 0.5 * ek4 + 0.5 * ek5 - 0.5 * dminmod_arg(s0, 4, 5, k);  // MD
+        case 3: return 5.0 * ek4 - 4.0 * ek3;                             // UL
+        default: return 1.5 * ek4 - 0.5 * ek3 + (4.0 / 3.0) * dminmod_arg(sm, 3, 4, k);  // LC
+    }
 }
 
 // Adjoint contribution along one axis to node t of a line of n nodes
 // (stride st): sum over the faces whose stencils read t (or a ghost node
 // that copies t) of d(face)/d(node) * d(face), where d(face s) =
 // p/ds (dA_s - dA_{s+1}) for the face between s and s+1 and dA is zero
-// outside the line (outflow) or wraps (periodic).
-__device__ double adj_axis(const double* F, const Lin4& dA, size_t base, long long st, int n, int bc, int t,
-                           double p, double inv_ds) {
-    if (p == 0.0) return 0.0;
-    const bool fwd = p > 0.0;
+// outside the line (outflow) or wraps (periodic).  FWD: p > 0 (window
+// F_{s-4} .. F_{s+4}), else the mirrored window F_{s+5} .. F_{s-3}.
+template <bool FWD>
+__device__ double adj_axis_dir(const double* F, const Lin4& dA, size_t base, long long st, int n, int bc, int t,
+                               double pinv) {
     int vlo = t, vhi = t;
     if (bc == 0) {
         if (t == 0) vlo = -5;
         if (t == n - 1) vhi = n + 4;
     }
-    auto dAat = [&](int i) -> double {
-        if (bc == 0) {
-            if (i < 0 || i >= n) return 0.0;
-        } else {
-            i = bc_map(i, n, 1);
-        }
-        return lin_at(dA, base + (size_t)i * st);
-    };
     double acc = 0.0;
     for (int tv = vlo; tv <= vhi; ++tv) {
         double w17[17];  // nodes tv-8 .. tv+8
+#pragma unroll
         for (int i = 0; i < 17; ++i) w17[i] = F[base + (size_t)bc_map(tv - 8 + i, n, bc) * st];
+        double a10[10];  // dA at faces' nodes: FWD s = tv-4 .. tv+5, else s = tv-5 .. tv+4
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            int j = (FWD ? tv - 4 : tv - 5) + i;
+            double v = 0.0;
+            if (bc == 0) {
+                if (j >= 0 && j < n) v = lin_at(dA, base + (size_t)j * st);
+            } else {
+                v = lin_at(dA, base + (size_t)bc_map(j, n, 1) * st);
+            }
+            a10[i] = v;
+        }
+#pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const int s = fwd ? tv + 4 - k : tv - 5 + k;  // face between s and s+1
+            const int s = FWD ? tv + 4 - k : tv - 5 + k;  // face between s and s+1
             if (bc == 0 && (s < -1 || s > n - 1)) continue;
             double fw[9];
-            for (int kk = 0; kk < 9; ++kk) {
-                const int pos = fwd ? s - 4 + kk : s + 5 - kk;
-                fw[kk] = w17[pos - tv + 8];
-            }
-            const double dface = p * inv_ds * (dAat(s) - dAat(s + 1));
+#pragma unroll
+            for (int kk = 0; kk < 9; ++kk) fw[kk] = w17[FWD ? 8 - k + kk : 8 + k - kk];
+            const int ia = FWD ? 8 - k : k;  // a10 index of s
+            const double dface = pinv * (a10[ia] - a10[ia + 1]);
             acc = fma(face_jacobian(fw, k), dface, acc);
         }
     }
     return acc;
+}
+
+__device__ __forceinline__ double adj_axis(const double* F, const Lin4& dA, size_t base, long long st, int n,
+                                           int bc, int t, double p, double inv_ds) {
+    if (p == 0.0) return 0.0;
+    return p > 0.0 ? adj_axis_dir<true>(F, dA, base, st, n, bc, t, p * inv_ds)
+                   : adj_axis_dir<false>(F, dA, base, st, n, bc, t, p * inv_ds);
 }
 
 // out[v][c] (=|+=) V^T dA at every node, both axes in 2D.
