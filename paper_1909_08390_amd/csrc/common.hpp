@@ -62,7 +62,8 @@ struct PlaneStep {
 
 // PlaneStep packed for the kernels (6 dwords, prefetched into SGPRs):
 // bits: set | first<<1 | new_group<<2 | yfirst<<3 | new_set<<4 | kx<<5 |
-// ky<<10 | hx<<15 | hy<<20 (node indices < 32).
+// ky<<10 | hx<<15 | hy<<20 | last<<25 (node indices < 32; last marks the
+// final plane of the order).
 struct PackedStep {
     double px, py;
     int v;
@@ -71,7 +72,7 @@ struct PackedStep {
 
 // Constant tables of one context, in device memory.
 struct DevTables {
-    PackedStep step[kMaxPlanes];
+    PackedStep step[kMaxPlanes + 2];  // two zero padding entries past the last plane
     // h[set][k][l] = w_k He_l(p_k) / l!  (zero for l >= Q_set), so that the
     // one-axis equilibrium factor of Eq. (gExpanded) is g_k = sum_l h[k][l] a_l
     // with the Hermite coefficients a_l(u, T) of the local Maxwellian.

@@ -252,7 +252,8 @@ hipError_t upload_tables(int d, const int Q[2], const double p[2][kQMax], const 
         ps.py = st.py;
         ps.v = st.v;
         ps.bits = st.set | (st.first << 1) | (st.new_group << 2) | (st.yfirst << 3) |
-                  (st.new_set << 4) | (st.kx << 5) | (st.ky << 10) | (st.hx << 15) | (st.hy << 20);
+                  (st.new_set << 4) | (st.kx << 5) | (st.ky << 10) | (st.hx << 15) | (st.hy << 20) |
+                  ((j == nplanes - 1) << 25);
     }
     hipError_t e = hipMalloc((void**)d_tab, sizeof(DevTables));
     if (e == hipSuccess) e = hipMemcpyAsync(*d_tab, t, sizeof(DevTables), hipMemcpyHostToDevice, stream);

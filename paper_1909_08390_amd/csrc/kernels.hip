@@ -237,6 +237,7 @@ struct Step {
     __device__ int ky() const { return (bits >> 10) & 31; }
     __device__ int hx() const { return (bits >> 15) & 31; }
     __device__ int hy() const { return (bits >> 20) & 31; }
+    __device__ bool last() const { return (bits >> 25) & 1; }
 };
 
 __device__ __forceinline__ Step load_pstep(CTab* t, int j) {
@@ -421,9 +422,13 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
 #pragma unroll
     for (int s = 0; s < NS; ++s) boff[s] = gcell[s] * (int)sizeof(S);
     const int own_off = (oy * nx + ox0) * (int)sizeof(S);
+    // element offset of plane v: one 32 x 32 -> 64-bit product (a plane
+    // holds fewer than 2^31 elements, checked on the host)
+    const unsigned ps32 = (unsigned)ps;
+    auto plane_off = [&](int v) -> size_t { return (size_t)((unsigned long long)(unsigned)v * ps32); };
     double pg[NS], pf[OWN];
     auto fetch = [&](int v) {
-        const Rsrc rs = plane_rsrc(static_cast<const S*>(a.src) + (size_t)v * ps, ps);
+        const Rsrc rs = plane_rsrc(static_cast<const S*>(a.src) + plane_off(v), ps);
         if constexpr (VEC) {
             bload2<S>(rs, boff[0], pg);
         } else {
@@ -433,7 +438,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
 #pragma unroll
         for (int jh = 0; jh < HS; ++jh) pg[OWN + jh] = bload1<S>(rs, boff[OWN + jh]);
         if constexpr (KIND == kStage4 || KIND == kStage5) {
-            const Rsrc rf = plane_rsrc(static_cast<const S*>(a.fbuf) + (size_t)v * ps, ps);
+            const Rsrc rf = plane_rsrc(static_cast<const S*>(a.fbuf) + plane_off(v), ps);
             if constexpr (VEC) {
                 bload2<S>(rf, boff[0], pf);
             } else {
@@ -444,15 +449,21 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     };
 
     constexpr int NC = HornerLayout<QM>::total();
-    const int np = tab->nplanes;
+    // the flux-difference buffers start at zero: a plane whose velocity
+    // component is zero skips that sweep and reads zeros (times a zero speed)
+    for (int i = tid; i < TY * VP; i += NT) {
+        vfx[i] = S(0);
+        vfy[i] = S(0);
+    }
+    // the step table carries two padding entries past the last plane, so the
+    // look-ahead load needs no bound test
     Step s0 = load_pstep(tab, 0);
-    Step s1 = load_pstep(tab, np > 1 ? 1 : 0);
+    Step s1 = load_pstep(tab, 1);
     fetch(s0.v);
-    for (int j = 0; j < np; ++j) {
+    for (int j = 0;; ++j) {  // ends at the plane flagged last
         const Step st = s0;
         s0 = s1;
-        if (j + 2 < np) s1 = load_pstep(tab, j + 2);
-        const int Q = tab->q[st.set()];
+        s1 = load_pstep(tab, j + 2);
         double g[NS], fb[OWN];
 #pragma unroll
         for (int s = 0; s < NS; ++s) g[s] = pg[s];
@@ -464,6 +475,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
         if constexpr (RELAX) {
             if constexpr (TAB) {
                 if (st.new_set()) {  // x factors of every node of this set
+                    const int Q = tab->q[st.set()];
                     for (int k = 0; k < (Q + 1) / 2; ++k) {
                         CDp hx = hrow<QM>(tab, st.set(), k);
                         double cf[NC];
@@ -602,13 +614,10 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
         const double sy = fabs(st.py) * a.inv_dy;
         double vf[OWN];
 #pragma unroll
-        for (int i = 0; i < OWN; ++i) {
-            vf[i] = 0.0;
-            if (st.px != 0.0) vf[i] = (double)vfx[orow * VP + ox + i] * sx;
-            if (st.py != 0.0) vf[i] = fma((double)vfy[orow * VP + ox + i], sy, vf[i]);
-        }
+        for (int i = 0; i < OWN; ++i)
+            vf[i] = fma((double)vfy[orow * VP + ox + i], sy, (double)vfx[orow * VP + ox + i] * sx);
 
-        const size_t own0 = (size_t)st.v * ps + (size_t)oy * nx + ox0;
+        const size_t own0 = plane_off(st.v) + (size_t)oy * nx + ox0;
         if constexpr (KIND == kAdvect) {
             double* o = static_cast<double*>(a.out) + own0;
 #pragma unroll
@@ -636,7 +645,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                     outv[i] = fbv[i];
                 }
             }
-            const Rsrc ro = plane_rsrc(static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + (size_t)st.v * ps, ps);
+            const Rsrc ro = plane_rsrc(static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + plane_off(st.v), ps);
             if constexpr (VEC) {
                 bstore2<S>(ro, own_off, outv);
             } else {
@@ -645,7 +654,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                     if (row_real && ox0 + i < nx) bstore1<S>(ro, own_off + i * (int)sizeof(S), outv[i]);
             }
             if constexpr (KIND == kStage4) {
-                const Rsrc rf = plane_rsrc(static_cast<S*>(a.fbuf) + (size_t)st.v * ps, ps);
+                const Rsrc rf = plane_rsrc(static_cast<S*>(a.fbuf) + plane_off(st.v), ps);
                 if constexpr (VEC) {
                     bstore2<S>(rf, own_off, fbv);
                 } else {
@@ -668,6 +677,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                 for (int i = 0; i < OWN; ++i) acc[i].se += (double)outv[i];
             }
         }
+        if (st.last()) break;
     }
 
     if constexpr (KIND != kAdvect) {
