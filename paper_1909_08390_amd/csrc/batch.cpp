@@ -216,7 +216,7 @@ imexlb_status imexlb_batch_create(const imexlb_tube* tubes, int count, int q_phi
         delete b;
         return bad("too many cells");
     }
-    hipError_t e = upload_tables(1, b->q, b->p, b->w, &b->d_tab, b->stream);
+    hipError_t e = upload_tables(1, b->q, b->p, b->w, 0, &b->d_tab, b->stream);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_args, 3 * (size_t)count * sizeof(StageArgs));
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_tiles, 2 * (size_t)mt * sizeof(int));
     if (e == hipSuccess) e = upload_tiles(b);

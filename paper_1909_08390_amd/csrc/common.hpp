@@ -57,13 +57,17 @@ struct PlaneStep {
     int hy;                   // node whose Horner row evaluates (ky, mirror)
     int new_group;            // 1: ky (or the set) changed -> y factor changes
     int yfirst;               // 1: evaluate the y pair now; 0: use the cached mirror
-    int new_set;              // 1: first step of a set (x-factor tables rebuilt)
+    int new_set;              // 1: first step of a set
+    int new_tab;              // 1: first step of an x-factor table group (tables rebuilt)
+    int tcount;               // mirror pairs in the table group (2D, orders up to 8)
+    int slot;                 // table slot of kx within its group
 };
 
 // PlaneStep packed for the kernels (6 dwords, prefetched into SGPRs):
-// bits: set | first<<1 | new_group<<2 | yfirst<<3 | new_set<<4 | kx<<5 |
-// ky<<10 | hx<<15 | hy<<20 | last<<25 (node indices < 32; last marks the
-// final plane of the order).
+// bits: set | first<<1 | new_group<<2 | yfirst<<3 | new_tab<<4 | last<<5 |
+// slot<<6 | tcount<<9 | hx<<12 | hy<<17 (node indices < 32; last marks the
+// final plane of the order; new_tab, slot and tcount describe the x-factor
+// table group, see upload_tables).
 struct PackedStep {
     double px, py;
     int v;
@@ -118,7 +122,7 @@ struct StageArgs {
 // Host helpers shared by the single-grid and batched contexts (imexlb.cpp).
 bool quadrature_rule(int Q, double* p, double* w);
 hipError_t upload_tables(int d, const int Q[2], const double p[2][kQMax], const double w[2][kQMax],
-                         DevTables** d_tab, hipStream_t stream);
+                         int tab_nodes, DevTables** d_tab, hipStream_t stream);
 void stage_coefficients(double dt, double tau, StageArgs& a);  // dt, omega, a1, a2, k[]
 void pass_args(const StageArgs& a, void* F, void* G3, void* G4, double* Mn, double* M3, double* M4,
                StageArgs out[3]);
@@ -176,5 +180,9 @@ constexpr int kBatchTiles[3] = {256, 512, 1024};
 // Tiles are visited in column bands of this many tiles (2D blocking of the
 // work that runs concurrently on one XCD, so halos hit that XCD's L2).
 constexpr int kBand = 2;
+// Nodes per x-factor table group of the 2D plane order (orders up to 8):
+// FP32 storage takes two mirror pairs per group (the kernels keep 4 tables
+// of one double per loaded cell in LDS), FP64 storage a whole set (8).
+constexpr int tab_nodes_2d(bool f32) { return f32 ? 4 : 8; }
 
 }  // namespace imexlb

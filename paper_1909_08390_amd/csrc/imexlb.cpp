@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -135,7 +136,7 @@ bool quadrature_rule(int Q, double* p, double* w) { return gauss_hermite(Q, p, w
 // Builds the constant tables of one quadrature (Sec. II) and copies them to
 // a new device allocation *d_tab (synchronous on s).
 hipError_t upload_tables(int d, const int Q[2], const double p[2][kQMax], const double w[2][kQMax],
-                         DevTables** d_tab, hipStream_t stream) {
+                         int tab_nodes, DevTables** d_tab, hipStream_t stream) {
     *d_tab = nullptr;
     DevTables* t = new (std::nothrow) DevTables();
     if (!t) return hipErrorOutOfMemory;
@@ -178,38 +179,52 @@ hipError_t upload_tables(int d, const int Q[2], const double p[2][kQMax], const 
         }
     t->nplanes = nplanes;
     t->nphi = nphi;
-    {   // processing order of the 2D passes: per set, ky-major; every node
-        // (in x and in y) followed by its mirror, so that one Horner
-        // evaluation gives the factors of both
+    {   // processing order of the passes: per set, ky-major; every node (in
+        // x and in y) followed by its mirror, so that one Horner evaluation
+        // gives the factors of both.  2D grids of orders up to 8 take the x
+        // nodes of a set in table groups of tab_nodes / 2 mirror pairs (all
+        // ky of one group before the next group), so that the kernels keep
+        // the x factors of one group in LDS tables.
+        const bool grouped = d == 2 && Q[0] <= 8 && Q[1] <= 8;
         int j = 0;
         for (int s = 0; s < 2; ++s) {
             const int base = s ? nphi : 0;
             const int nyg = d == 2 ? Q[s] : 1;
+            const int npairs = (Q[s] + 1) / 2;
+            const int gpairs = grouped ? std::max(1, tab_nodes / 2) : npairs;
             bool set_start = true;
-            for (int ly = 0; ly < (nyg + 1) / 2; ++ly) {
-                const int ypair[2] = {ly, nyg - 1 - ly};
-                const int ycnt = ypair[0] == ypair[1] ? 1 : 2;
-                for (int ey = 0; ey < ycnt; ++ey) {
-                    const int ky = ypair[ey];
-                    bool group_start = true;
-                    for (int k = 0; k < (Q[s] + 1) / 2; ++k) {
-                        const int pair[2] = {k, Q[s] - 1 - k};
-                        const int cnt = pair[0] == pair[1] ? 1 : 2;
-                        for (int e = 0; e < cnt; ++e, ++j) {
-                            PlaneStep& st = t->order[j];
-                            const int kx = pair[e];
-                            st.v = base + kx + Q[s] * ky;
-                            st.set = s;
-                            st.kx = kx;
-                            st.ky = ky;
-                            st.hx = k;
-                            st.first = e == 0;
-                            st.hy = ly;
-                            st.new_group = group_start;
-                            st.yfirst = group_start && ey == 0;
-                            st.new_set = set_start;
-                            group_start = false;
-                            set_start = false;
+            for (int k0 = 0; k0 < npairs; k0 += gpairs) {
+                const int kend = std::min(npairs, k0 + gpairs);
+                bool tab_start = true;
+                for (int ly = 0; ly < (nyg + 1) / 2; ++ly) {
+                    const int ypair[2] = {ly, nyg - 1 - ly};
+                    const int ycnt = ypair[0] == ypair[1] ? 1 : 2;
+                    for (int ey = 0; ey < ycnt; ++ey) {
+                        const int ky = ypair[ey];
+                        bool group_start = true;
+                        for (int k = k0; k < kend; ++k) {
+                            const int pair[2] = {k, Q[s] - 1 - k};
+                            const int cnt = pair[0] == pair[1] ? 1 : 2;
+                            for (int e = 0; e < cnt; ++e, ++j) {
+                                PlaneStep& st = t->order[j];
+                                const int kx = pair[e];
+                                st.v = base + kx + Q[s] * ky;
+                                st.set = s;
+                                st.kx = kx;
+                                st.ky = ky;
+                                st.hx = k;
+                                st.first = e == 0;
+                                st.hy = ly;
+                                st.new_group = group_start;
+                                st.yfirst = group_start && ey == 0;
+                                st.new_set = set_start;
+                                st.new_tab = tab_start;
+                                st.tcount = grouped ? kend - k0 : 0;
+                                st.slot = grouped ? 2 * (k - k0) + e : 0;
+                                group_start = false;
+                                set_start = false;
+                                tab_start = false;
+                            }
                         }
                     }
                 }
@@ -251,9 +266,9 @@ hipError_t upload_tables(int d, const int Q[2], const double p[2][kQMax], const 
         ps.px = st.px;
         ps.py = st.py;
         ps.v = st.v;
-        ps.bits = st.set | (st.first << 1) | (st.new_group << 2) | (st.yfirst << 3) |
-                  (st.new_set << 4) | (st.kx << 5) | (st.ky << 10) | (st.hx << 15) | (st.hy << 20) |
-                  ((j == nplanes - 1) << 25);
+        ps.bits = st.set | (st.first << 1) | (st.new_group << 2) | (st.yfirst << 3) | (st.new_tab << 4) |
+                  ((j == nplanes - 1) << 5) | (st.slot << 6) | (st.tcount << 9) | (st.hx << 12) |
+                  (st.hy << 17);
     }
     hipError_t e = hipMalloc((void**)d_tab, sizeof(DevTables));
     if (e == hipSuccess) e = hipMemcpyAsync(*d_tab, t, sizeof(DevTables), hipMemcpyHostToDevice, stream);
@@ -442,7 +457,7 @@ imexlb_status imexlb_create(const imexlb_config* cfg, void* hip_stream, imexlb_c
     c->cells = (long long)cfg->nx * c->cfg.ny;
     c->elem = cfg->storage == IMEXLB_F32 ? 4 : 8;
 
-    hipError_t e = upload_tables(d, Q, c->p, c->w, &c->d_tab, c->stream);
+    hipError_t e = upload_tables(d, Q, c->p, c->w, tab_nodes_2d(c->elem == 4), &c->d_tab, c->stream);
     if (e == hipErrorOutOfMemory) {
         delete c;
         return IMEXLB_ENOMEM;

@@ -232,12 +232,12 @@ struct Step {
     __device__ bool first() const { return (bits >> 1) & 1; }
     __device__ bool new_group() const { return (bits >> 2) & 1; }
     __device__ bool yfirst() const { return (bits >> 3) & 1; }
-    __device__ bool new_set() const { return (bits >> 4) & 1; }
-    __device__ int kx() const { return (bits >> 5) & 31; }
-    __device__ int ky() const { return (bits >> 10) & 31; }
-    __device__ int hx() const { return (bits >> 15) & 31; }
-    __device__ int hy() const { return (bits >> 20) & 31; }
-    __device__ bool last() const { return (bits >> 25) & 1; }
+    __device__ bool new_tab() const { return (bits >> 4) & 1; }
+    __device__ bool last() const { return (bits >> 5) & 1; }
+    __device__ int slot() const { return (bits >> 6) & 7; }
+    __device__ int tcount() const { return (bits >> 9) & 7; }
+    __device__ int hx() const { return (bits >> 12) & 31; }
+    __device__ int hy() const { return (bits >> 17) & 31; }
 };
 
 __device__ __forceinline__ Step load_pstep(CTab* t, int j) {
@@ -281,8 +281,12 @@ __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& 
 //  - sweeps: the first half of the threads slides the MP-9 window along x
 //    over L = 2 OWN cells of a row, the second half along y over L cells of
 //    a column;
-//  - per plane: fill LDS (next plane's global loads already in flight),
-//    barrier, sweeps, barrier, pointwise stage algebra + stores + moments.
+//  - x factors (orders up to 8) from LDS tables of one table group of the
+//    plane order (kTabNodes nodes: mirror pairs), built when a group starts;
+//  - software-pipelined planes: sweep plane j and relax plane j + 1 into
+//    the other of two LDS tiles (the global loads of plane j + 2 then in
+//    flight), one barrier, pointwise stage algebra + stores + moments of
+//    plane j (stage 4: relax, barrier, sweeps, barrier, pointwise).
 // LDS pitches are odd so the row-strided x windows and the column-strided
 // results spread over all banks.
 // ---------------------------------------------------------------------------
@@ -298,6 +302,16 @@ struct Stage2DShape {
     static constexpr bool RELAX = KIND != kAdvect;
     static constexpr bool TAB = RELAX && (QM == 8);
     static constexpr int NLOAD = TX * TY + NH;
+    // x-factor table nodes: the table groups of the plane order built by the
+    // host for this storage type
+    static constexpr int TABN = tab_nodes_2d(sizeof(S) == 4);
+    // software-pipelined plane loop (double-buffered LDS tile and flux
+    // buffers) for FP32 storage; stage 4, whose registers are already full
+    // with the E^n factors of its own cells, and FP64 storage, whose tiles
+    // would not leave room for two work-groups per compute unit next to the
+    // full x-factor tables, keep the two-barrier loop
+    static constexpr bool PIPE = KIND != kStage4 && sizeof(S) == 4;
+    static constexpr int NBUF = PIPE ? 2 : 1;
 };
 
 template <typename S, int KIND, int QM, int TY, int OWN, bool VEC>
@@ -357,8 +371,9 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
         }
     }
 
-    // x-factor tables in LDS (orders up to 8): gtab[k * NLOAD + cid] holds
-    // g_x of node k at loaded cell cid; rebuilt at the start of each set.
+    // x-factor tables in LDS (orders up to 8): gtab[t * NLOAD + cid] holds
+    // g_x of table slot t (node hx + t / 2 of the group's first pair, or its
+    // mirror for odd t) at loaded cell cid; rebuilt when a table group starts.
     constexpr bool TAB = Sh::TAB;
     constexpr int NLOAD = Sh::NLOAD;
     int cid[NS];
@@ -426,9 +441,14 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     // holds fewer than 2^31 elements, checked on the host)
     const unsigned ps32 = (unsigned)ps;
     auto plane_off = [&](int v) -> size_t { return (size_t)((unsigned long long)(unsigned)v * ps32); };
+    // Loads of plane v; with live == false (the padding entries past the
+    // last plane) the buffer resources have no records, so the loads return
+    // zeros without touching memory while every iteration still issues them
+    // (a conditional load would make the compiler wait for it right away).
     double pg[NS], pf[OWN];
-    auto fetch = [&](int v) {
-        const Rsrc rs = plane_rsrc(static_cast<const S*>(a.src) + plane_off(v), ps);
+    auto fetch = [&](int v, bool live) {
+        const long long recs = live ? ps : 0;
+        const Rsrc rs = plane_rsrc(static_cast<const S*>(a.src) + plane_off(v), recs);
         if constexpr (VEC) {
             bload2<S>(rs, boff[0], pg);
         } else {
@@ -438,7 +458,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
 #pragma unroll
         for (int jh = 0; jh < HS; ++jh) pg[OWN + jh] = bload1<S>(rs, boff[OWN + jh]);
         if constexpr (KIND == kStage4 || KIND == kStage5) {
-            const Rsrc rf = plane_rsrc(static_cast<const S*>(a.fbuf) + plane_off(v), ps);
+            const Rsrc rf = plane_rsrc(static_cast<const S*>(a.fbuf) + plane_off(v), recs);
             if constexpr (VEC) {
                 bload2<S>(rf, boff[0], pf);
             } else {
@@ -449,35 +469,27 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     };
 
     constexpr int NC = HornerLayout<QM>::total();
-    // the flux-difference buffers start at zero: a plane whose velocity
-    // component is zero skips that sweep and reads zeros (times a zero speed)
-    for (int i = tid; i < TY * VP; i += NT) {
-        vfx[i] = S(0);
-        vfy[i] = S(0);
-    }
-    // the step table carries two padding entries past the last plane, so the
-    // look-ahead load needs no bound test
-    Step s0 = load_pstep(tab, 0);
-    Step s1 = load_pstep(tab, 1);
-    fetch(s0.v);
-    for (int j = 0;; ++j) {  // ends at the plane flagged last
-        const Step st = s0;
-        s0 = s1;
-        s1 = load_pstep(tab, j + 2);
+    constexpr int TSZ = (TY + 10) * P, VSZ = TY * VP;
+    // relax-time part of the pointwise stage algebra at the own cells: the
+    // stage value without its flux term (stage 4: the stage value and R)
+    constexpr int NB = KIND == kStage4 ? 2 : 1;
+
+    // Relax on read of plane st (loads in pg / pf) into the LDS tile tl;
+    // updates the factor caches when a table group or a y group starts.
+    // x factors come from the LDS tables, or (orders above 8, and stage 4's
+    // own E^n) from one Horner evaluation per cell on the first plane of a
+    // mirror pair, the second plane using the cached mirror factor.
+    auto relax = [&](const Step& st, S* tl, double (&base)[NB][OWN]) {
         double g[NS], fb[OWN];
 #pragma unroll
         for (int s = 0; s < NS; ++s) g[s] = pg[s];
 #pragma unroll
         for (int i = 0; i < OWN; ++i) fb[i] = pf[i];
-        const bool ygroup = RELAX && st.new_group() && st.yfirst();
-        fetch(s0.v);  // unconditional (the last iteration refetches) keeps the load count fixed
-
         if constexpr (RELAX) {
             if constexpr (TAB) {
-                if (st.new_set()) {  // x factors of every node of this set
-                    const int Q = tab->q[st.set()];
-                    for (int k = 0; k < (Q + 1) / 2; ++k) {
-                        CDp hx = hrow<QM>(tab, st.set(), k);
+                if (st.new_tab()) {  // x factors of the mirror pairs of this table group
+                    for (int p = 0; p < st.tcount(); ++p) {
+                        CDp hx = hrow<QM>(tab, st.set(), st.hx() + p);
                         double cf[NC];
 #pragma unroll
                         for (int i = 0; i < NC; ++i) cf[i] = hx[i];
@@ -486,15 +498,18 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                             if (sval[s]) {
                                 double gp, gq;
                                 g_pair_r<QM>(cf, sux[s], sth[s], gp, gq);
-                                gtab[k * NLOAD + cid[s]] = gp;
-                                gtab[(Q - 1 - k) * NLOAD + cid[s]] = gq;
+                                gtab[(2 * p) * NLOAD + cid[s]] = gp;
+                                gtab[(2 * p + 1) * NLOAD + cid[s]] = gq;
                             }
                         }
                     }
                 }
             }
+            // (both branches of the factor updates assign the same arrays, so
+            // that they stay in registers)
             if (st.new_group()) {  // y factors of the group (and of its mirror)
-                if (ygroup) {
+                double tA[NS], tAm[NS], tnA[OWN], tnAm[OWN];
+                if (st.yfirst()) {
                     CDp hy = hrow<QM>(tab, st.set(), st.hy());
                     double cf[NC];
 #pragma unroll
@@ -505,121 +520,161 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                         const double pre = st.set() ? a.chi_fac * n * (sth[s] + 1.0) : n;
                         double gp, gq;
                         g_pair_r<QM>(cf, guy[s], sth[s], gp, gq);
-                        sA[s] = pre * gp;
-                        sAm[s] = pre * gq;
+                        tA[s] = pre * gp;
+                        tAm[s] = pre * gq;
                     }
-                    if constexpr (KIND == kStage4) {
 #pragma unroll
-                        for (int i = 0; i < OWN; ++i) {
+                    for (int i = 0; i < OWN; ++i) {
+                        tnA[i] = 0.0;
+                        tnAm[i] = 0.0;
+                        if constexpr (KIND == kStage4) {
                             const double n = gnn[i];
                             const double pre = st.set() ? a.chi_fac * n * (nth[i] + 1.0) : n;
                             double gp, gq;
                             g_pair_r<QM>(cf, gnuy[i], nth[i], gp, gq);
-                            nA[i] = pre * gp;
-                            nAm[i] = pre * gq;
+                            tnA[i] = pre * gp;
+                            tnAm[i] = pre * gq;
                         }
                     }
                 } else {
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) sA[s] = sAm[s];
+                    for (int s = 0; s < NS; ++s) {
+                        tA[s] = sAm[s];
+                        tAm[s] = sAm[s];
+                    }
 #pragma unroll
-                    for (int i = 0; i < OWN; ++i) nA[i] = nAm[i];
+                    for (int i = 0; i < OWN; ++i) {
+                        tnA[i] = nAm[i];
+                        tnAm[i] = nAm[i];
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    sA[s] = tA[s];
+                    sAm[s] = tAm[s];
+                }
+#pragma unroll
+                for (int i = 0; i < OWN; ++i) {
+                    nA[i] = tnA[i];
+                    nAm[i] = tnAm[i];
                 }
             }
         }
 
-        // relax on read into the LDS tile.  x factors come from the LDS
-        // tables, or (orders above 8, and stage 4's own E^n) from one Horner
-        // evaluation per cell on the first plane of a mirror pair, the
-        // second plane using the cached mirror factor.
-        double eown[OWN], enown[OWN];
-        {
-            double gxs[NS], gxn[OWN];
-            if constexpr (RELAX) {
-                if constexpr (TAB) {
+        double eown[OWN];
+        double gxs[NS], gxn[OWN];
+        if constexpr (RELAX) {
+            if constexpr (TAB) {
 #pragma unroll
-                    for (int s = 0; s < NS; ++s)
-                        gxs[s] = gtab[st.kx() * NLOAD + (sval[s] ? cid[s] : cid[0])];
+                for (int s = 0; s < NS; ++s)
+                    gxs[s] = gtab[st.slot() * NLOAD + (sval[s] ? cid[s] : cid[0])];
+            }
+            double tgx[NS], tgm[NS], tgn[OWN], tgnm[OWN];
+            if (st.first()) {
+                CDp hx = hrow<QM>(tab, st.set(), st.hx());
+                double cf[NC];
+#pragma unroll
+                for (int i = 0; i < NC; ++i) cf[i] = hx[i];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    tgx[s] = 0.0;
+                    tgm[s] = 0.0;
+                    if constexpr (!TAB) g_pair_r<QM>(cf, sux[s], sth[s], tgx[s], tgm[s]);
                 }
-                if (st.first()) {
-                    CDp hx = hrow<QM>(tab, st.set(), st.hx());
-                    double cf[NC];
 #pragma unroll
-                    for (int i = 0; i < NC; ++i) cf[i] = hx[i];
-                    if constexpr (!TAB) {
+                for (int i = 0; i < OWN; ++i) {
+                    tgn[i] = 0.0;
+                    tgnm[i] = 0.0;
+                    if constexpr (KIND == kStage4) g_pair_r<QM>(cf, nux[i], nth[i], tgn[i], tgnm[i]);
+                }
+            } else {
 #pragma unroll
-                        for (int s = 0; s < NS; ++s) {
-                            double gp = 0.0, gq = 0.0;
-                            g_pair_r<QM>(cf, sux[s], sth[s], gp, gq);
-                            gxs[s] = gp;
-                            sgm[s] = gq;
-                        }
-                    }
-                    if constexpr (KIND == kStage4) {
+                for (int s = 0; s < NS; ++s) {
+                    tgx[s] = sgm[s];
+                    tgm[s] = sgm[s];
+                }
 #pragma unroll
-                        for (int i = 0; i < OWN; ++i) {
-                            double gp, gq;
-                            g_pair_r<QM>(cf, nux[i], nth[i], gp, gq);
-                            gxn[i] = gp;
-                            ngm[i] = gq;
-                        }
-                    }
-                } else {
-                    if constexpr (!TAB) {
-#pragma unroll
-                        for (int s = 0; s < NS; ++s) gxs[s] = sgm[s];
-                    }
-#pragma unroll
-                    for (int i = 0; i < OWN; ++i) gxn[i] = ngm[i];
+                for (int i = 0; i < OWN; ++i) {
+                    tgn[i] = ngm[i];
+                    tgnm[i] = ngm[i];
                 }
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                double e = 0.0;
-                if constexpr (RELAX) e = sA[s] * gxs[s];
-                if (s < OWN) eown[s] = e;
-                if (sval[s]) {
-                    const double val = RELAX ? fma(a.a_rel, g[s], a.b_rel * e) : g[s];
-                    tile[lidx[s]] = (S)val;
-                }
+                if constexpr (!TAB) gxs[s] = tgx[s];
+                sgm[s] = tgm[s];
             }
-            if constexpr (KIND == kStage4) {
 #pragma unroll
-                for (int i = 0; i < OWN; ++i) enown[i] = nA[i] * gxn[i];
+            for (int i = 0; i < OWN; ++i) {
+                gxn[i] = tgn[i];
+                ngm[i] = tgnm[i];
             }
         }
-        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            double e = 0.0;
+            if constexpr (RELAX) e = sA[s] * gxs[s];
+            if (s < OWN) eown[s] = e;
+            if (sval[s]) {
+                const double val = RELAX ? fma(a.a_rel, g[s], a.b_rel * e) : g[s];
+                tl[lidx[s]] = (S)val;
+            }
+        }
+        // stage algebra with the host-combined coefficients k[] (see
+        // StageArgs), the flux term added in the pointwise step
+#pragma unroll
+        for (int i = 0; i < OWN; ++i) {
+            if constexpr (KIND == kStage3) {
+                base[0][i] = fma(-a.k[0], g[i] - eown[i], g[i]);
+            } else if constexpr (KIND == kStage4) {
+                const double fn = fb[i], g3 = g[i];
+                const double dn = fn - nA[i] * gxn[i], d3 = g3 - eown[i];
+                base[0][i] = fma(0.75, fn, fma(0.25, g3, fma(a.k[1], dn, -a.k[2] * d3)));
+                base[1][i] = fma(5.0 / 6.0, fn, fma(1.0 / 6.0, g3, fma(-a.k[3], dn, -a.k[4] * d3)));
+            } else if constexpr (KIND == kStage5) {
+                base[0][i] = fma(-a.k[5], g[i] - eown[i], fb[i]);
+            } else {
+                base[0][i] = 0.0;
+            }
+        }
+    };
 
-        if (tid < NT / 2) {  // x sweep: row tid % TY, cells L (tid / TY) .. +L-1
+    // MP-9 sweeps of one plane from the LDS tile tl into the flux buffers
+    // fx, fy: the first half of the threads along x (row tid % TY, cells
+    // L (tid / TY) .. +L-1), the second along y (column (tid - NT/2) % TX,
+    // cells L seg .. +L-1).
+    auto sweep = [&](const Step& st, const S* tl, R* fx, R* fy) {
+        if (tid < NT / 2) {
             if (st.px != 0.0) {
                 const int row = tid % TY, seg = tid / TY;
-                const S* lo = tile + (row + 5) * P + seg * L;
-                R* o = vfx + row * VP + seg * L;
+                const S* lo = tl + (row + 5) * P + seg * L;
+                R* o = fx + row * VP + seg * L;
                 if (st.px > 0.0) mp9_sweep<R, S, L, 1, 1, true>(lo, o);
                 else mp9_sweep<R, S, L, 1, 1, false>(lo + 1, o);
             }
-        } else {             // y sweep: column (tid - NT/2) % TX, cells L seg .. +L-1
+        } else {
             if (st.py != 0.0) {
                 const int i2 = tid - NT / 2;
                 const int col = i2 % TX, seg = i2 / TX;
-                const S* lo = tile + seg * L * P + col + 5;
-                R* o = vfy + seg * L * VP + col;
+                const S* lo = tl + seg * L * P + col + 5;
+                R* o = fy + seg * L * VP + col;
                 if (st.py > 0.0) mp9_sweep<R, S, L, P, VP, true>(lo, o);
                 else mp9_sweep<R, S, L, P, VP, false>(lo + P, o);
             }
         }
-        __syncthreads();
+    };
 
+    // Flux term, stores and moment accumulation of one plane.
+    auto pointwise = [&](const Step& st, const R* fx, const R* fy, const double (&base)[NB][OWN]) {
         const double sx = fabs(st.px) * a.inv_dx;
         const double sy = fabs(st.py) * a.inv_dy;
         double vf[OWN];
 #pragma unroll
         for (int i = 0; i < OWN; ++i)
-            vf[i] = fma((double)vfy[orow * VP + ox + i], sy, (double)vfx[orow * VP + ox + i] * sx);
+            vf[i] = fma((double)fy[orow * VP + ox + i], sy, (double)fx[orow * VP + ox + i] * sx);
 
-        const size_t own0 = plane_off(st.v) + (size_t)oy * nx + ox0;
         if constexpr (KIND == kAdvect) {
-            double* o = static_cast<double*>(a.out) + own0;
+            double* o = static_cast<double*>(a.out) + plane_off(st.v) + (size_t)oy * nx + ox0;
 #pragma unroll
             for (int i = 0; i < OWN; ++i)
                 if (row_real && ox0 + i < nx) o[i] = vf[i];
@@ -627,21 +682,14 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
             S outv[OWN], fbv[OWN];
 #pragma unroll
             for (int i = 0; i < OWN; ++i) {
-                // stage algebra with the host-combined coefficients k[] (see
-                // StageArgs): same terms as the header, regrouped
                 if constexpr (KIND == kStage3) {
-                    const double fn = g[i], en = eown[i];
-                    outv[i] = (S)fma(-a.k[0], fn - en, fma(-a.dt, vf[i], fn));
+                    outv[i] = (S)fma(-a.dt, vf[i], base[0][i]);
                     fbv[i] = outv[i];
                 } else if constexpr (KIND == kStage4) {
-                    const double fn = fb[i], g3 = g[i];
-                    const double dn = fn - enown[i], d3 = g3 - eown[i];
-                    const double s4 = fma(0.75, fn, fma(0.25, g3, fma(a.k[1], dn, fma(-a.k[2], d3, -0.25 * a.dt * vf[i]))));
-                    const double r = fma(5.0 / 6.0, fn, fma(1.0 / 6.0, g3, fma(-a.k[3], dn, fma(-a.k[4], d3, -(1.0 / 6.0) * a.dt * vf[i]))));
-                    outv[i] = (S)s4;
-                    fbv[i] = (S)r;
+                    outv[i] = (S)fma(-0.25 * a.dt, vf[i], base[0][i]);
+                    fbv[i] = (S)fma(-(1.0 / 6.0) * a.dt, vf[i], base[1][i]);
                 } else {  // kStage5
-                    fbv[i] = (S)fma(-a.k[5], g[i] - eown[i], fma(-(2.0 / 3.0) * a.dt, vf[i], fb[i]));
+                    fbv[i] = (S)fma(-(2.0 / 3.0) * a.dt, vf[i], base[0][i]);
                     outv[i] = fbv[i];
                 }
             }
@@ -677,7 +725,63 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                 for (int i = 0; i < OWN; ++i) acc[i].se += (double)outv[i];
             }
         }
-        if (st.last()) break;
+    };
+
+    // The flux buffers start at zero: a plane whose velocity component is
+    // zero skips that sweep and reads zeros (times a zero speed).  The step
+    // table carries two padding entries past the last plane, so the
+    // look-ahead loads need no bound test.
+    for (int i = tid; i < Sh::NBUF * VSZ; i += NT) {
+        vfx[i] = S(0);
+        vfy[i] = S(0);
+    }
+    Step st = load_pstep(tab, 0);  // plane swept in the current iteration
+    Step s1 = load_pstep(tab, 1);  // the plane after it
+    double bcur[NB][OWN], bnext[NB][OWN];
+    fetch(st.v, true);
+    if constexpr (Sh::PIPE) {
+        // Software pipeline over the planes, two LDS tiles and two pairs of
+        // flux buffers: iteration j sweeps plane j out of tile j % 2 and
+        // relaxes plane j + 1 into the other tile, one barrier, then the
+        // pointwise step of plane j.  A tile is rewritten two iterations
+        // after it was swept and a flux buffer two iterations after it was
+        // read, each time with a barrier in between, so one barrier per
+        // plane suffices.
+        relax(st, tile, bcur);
+        fetch(s1.v, !st.last());
+        __syncthreads();
+        int buf = 0;
+        for (int j = 0;; ++j) {  // ends at the plane flagged last
+            const Step sn = s1;
+            s1 = load_pstep(tab, j + 2);
+            sweep(st, tile + buf * TSZ, vfx + buf * VSZ, vfy + buf * VSZ);
+            if (!st.last()) relax(sn, tile + (buf ^ 1) * TSZ, bnext);
+            fetch(s1.v, !st.last() && !sn.last());
+            __syncthreads();
+            pointwise(st, vfx + buf * VSZ, vfy + buf * VSZ, bcur);
+            if (st.last()) break;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int i = 0; i < OWN; ++i) bcur[b][i] = bnext[b][i];
+            st = sn;
+            buf ^= 1;
+        }
+    } else {
+        // One tile and one pair of flux buffers: relax (the next plane's
+        // loads in flight), barrier, sweeps, barrier, pointwise step.
+        for (int j = 0;; ++j) {
+            const Step sn = s1;
+            s1 = load_pstep(tab, j + 2);
+            relax(st, tile, bcur);
+            fetch(sn.v, !st.last());
+            __syncthreads();
+            sweep(st, tile, vfx, vfy);
+            __syncthreads();
+            pointwise(st, vfx, vfy, bcur);
+            if (st.last()) break;
+            st = sn;
+        }
     }
 
     if constexpr (KIND != kAdvect) {
@@ -701,10 +805,10 @@ template <typename S, int KIND, int QM, int TY, int OWN>
 __global__ void __launch_bounds__(kTile2X * TY / OWN) __attribute__((amdgpu_waves_per_eu(2)))
 stage2d_kernel(StageArgs a) {
     using Sh = Stage2DShape<S, KIND, QM, TY, OWN>;
-    __shared__ S tile[(TY + 10) * Sh::P];
-    __shared__ S vfx[TY * Sh::VP];
-    __shared__ S vfy[TY * Sh::VP];
-    __shared__ double gtab[Sh::TAB ? 8 * Sh::NLOAD : 1];
+    __shared__ S tile[Sh::NBUF * (TY + 10) * Sh::P];
+    __shared__ S vfx[Sh::NBUF * TY * Sh::VP];
+    __shared__ S vfy[Sh::NBUF * TY * Sh::VP];
+    __shared__ double gtab[Sh::TAB ? Sh::TABN * Sh::NLOAD : 1];
     int txi, tyi;
     if (!tile_of_block(a, txi, tyi)) return;
     // interior tiles of a grid whose rows are multiples of OWN take the
@@ -851,7 +955,7 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
 
         double e[NS], en[L];
         if constexpr (RELAX) {
-            if (st.new_set() && st.set() == 1) {
+            if (st.new_tab() && st.set() == 1) {
 #pragma unroll
                 for (int s = 0; s < NS; ++s) sP[s] = a.chi_fac * sP[s] * (sth[s] + 1.0);
                 if constexpr (KIND == kStage4) {
