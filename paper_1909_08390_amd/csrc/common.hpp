@@ -76,7 +76,7 @@ struct PackedStep {
 
 // Constant tables of one context, in device memory.
 struct DevTables {
-    PackedStep step[kMaxPlanes + 2];  // two zero padding entries past the last plane
+    PackedStep step[kMaxPlanes + 3];  // zero padding entries past the last plane (look-ahead)
     // h[set][k][l] = w_k He_l(p_k) / l!  (zero for l >= Q_set), so that the
     // one-axis equilibrium factor of Eq. (gExpanded) is g_k = sum_l h[k][l] a_l
     // with the Hermite coefficients a_l(u, T) of the local Maxwellian.
@@ -103,6 +103,7 @@ struct StageArgs {
     const DevTables* tab;
     int nx, ny, bcx, bcy;
     int ntx, nty, tiles_per_xcd, qm;  // qm: padded Horner order (8 or 16)
+    int paired;              // 2D, both orders even: planes come in x-mirror pairs
     long long plane_stride;  // cells per plane
     long long mstride;       // elements per moment field (1D kernels)
     double inv_dx, inv_dy;

@@ -11,6 +11,8 @@ namespace {
 // Tables are read through the constant address space so that uniform
 // accesses become scalar loads.
 #define IMEXLB_CONST __attribute__((address_space(4)))
+// Lambdas of the kernel bodies are inlined even where they are called twice.
+#define IMEXLB_INLINE __attribute__((always_inline))
 typedef const DevTables IMEXLB_CONST CTab;
 typedef const double IMEXLB_CONST* CDp;
 

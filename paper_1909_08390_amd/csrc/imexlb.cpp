@@ -391,6 +391,7 @@ StageArgs base_args(const imexlb_ctx* c) {
     }
     a.tiles_per_xcd = (a.ntx * a.nty + 7) / 8;
     a.qm = (k.q_phi <= 8 && k.q_chi <= 8) ? 8 : 16;
+    a.paired = k.d == 2 && k.q_phi % 2 == 0 && k.q_chi % 2 == 0;
     a.plane_stride = c->cells;
     a.mstride = c->cells;
     a.inv_dx = k.nx / k.lx;

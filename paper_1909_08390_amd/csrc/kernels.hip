@@ -256,6 +256,19 @@ __device__ __forceinline__ CDp hrow(CTab* t, int set, int k) {
     else return t->hc16[set][k];
 }
 
+// The own cells of a thread (one or two) as one access.
+template <typename S, int OWN>
+__device__ __forceinline__ void bload_own(Rsrc r, int off, double* o) {
+    if constexpr (OWN == 2) bload2<S>(r, off, o);
+    else o[0] = bload1<S>(r, off);
+}
+
+template <typename S, int OWN>
+__device__ __forceinline__ void bstore_own(Rsrc r, int off, const S* v) {
+    if constexpr (OWN == 2) bstore2<S>(r, off, v);
+    else bstore1<S>(r, off, v[0]);
+}
+
 // Tile visiting order: column bands of kBand tiles, row-major inside a band;
 // consecutive logical indices go to one XCD (blockIdx % 8 selects the XCD).
 __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& ty) {
@@ -290,7 +303,7 @@ __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& 
 // LDS pitches are odd so the row-strided x windows and the column-strided
 // results spread over all banks.
 // ---------------------------------------------------------------------------
-template <typename S, int KIND, int QM, int TY, int OWN>
+template <typename S, int KIND, int QM, int TY, int OWN, bool PAIR>
 struct Stage2DShape {
     static constexpr int TX = kTile2X, NT = TX * TY / OWN, L = 2 * OWN;
     static constexpr int OPR = TX / OWN;          // threads per tile row
@@ -300,7 +313,7 @@ struct Stage2DShape {
     static constexpr int HS = (NH + NT - 1) / NT;
     static constexpr int NS = OWN + HS;
     static constexpr bool RELAX = KIND != kAdvect;
-    static constexpr bool TAB = RELAX && (QM == 8);
+    static constexpr bool TAB = RELAX && (QM == 8) && !PAIR;
     static constexpr int NLOAD = TX * TY + NH;
     // x-factor table nodes: the table groups of the plane order built by the
     // host for this storage type
@@ -310,14 +323,17 @@ struct Stage2DShape {
     // with the E^n factors of its own cells, and FP64 storage, whose tiles
     // would not leave room for two work-groups per compute unit next to the
     // full x-factor tables, keep the two-barrier loop
-    static constexpr bool PIPE = KIND != kStage4 && sizeof(S) == 4;
-    static constexpr int NBUF = PIPE ? 2 : 1;
+    static constexpr bool PIPE = KIND != kStage4 && sizeof(S) == 4 && !PAIR;
+    static constexpr int NBUF = (PIPE || PAIR) ? 2 : 1;
+    // waves per SIMD the register budget aims at: two work-groups per
+    // compute unit
+    static constexpr int WPE = 2 * NT / 256;
 };
 
-template <typename S, int KIND, int QM, int TY, int OWN, bool VEC>
+template <typename S, int KIND, int QM, int TY, int OWN, bool PAIR, bool VEC>
 __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int tyi, S* tile, S* vfx,
                                              S* vfy, double* gtab) {
-    using Sh = Stage2DShape<S, KIND, QM, TY, OWN>;
+    using Sh = Stage2DShape<S, KIND, QM, TY, OWN, PAIR>;
     constexpr int TX = Sh::TX, NT = Sh::NT, L = Sh::L, OPR = Sh::OPR, P = Sh::P, VP = Sh::VP;
     constexpr int NH = Sh::NH, HS = Sh::HS, NS = Sh::NS;
     constexpr bool RELAX = Sh::RELAX;
@@ -432,7 +448,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     // Global loads of one plane: the source plane at the loaded cells and,
     // for stages 4 and 5, the state buffer at the own cells (byte offsets
     // within the plane; own cells of interior tiles as one vector access).
-    static_assert(OWN == 2, "vector accesses assume two own cells");
+    static_assert(OWN == 1 || OWN == 2, "own-cell accesses take one or two cells");
     int boff[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) boff[s] = gcell[s] * (int)sizeof(S);
@@ -446,11 +462,11 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     // zeros without touching memory while every iteration still issues them
     // (a conditional load would make the compiler wait for it right away).
     double pg[NS], pf[OWN];
-    auto fetch = [&](int v, bool live) {
+    auto fetch_to = [&](double (&pg)[NS], double (&pf)[OWN], int v, bool live) IMEXLB_INLINE {
         const long long recs = live ? ps : 0;
         const Rsrc rs = plane_rsrc(static_cast<const S*>(a.src) + plane_off(v), recs);
         if constexpr (VEC) {
-            bload2<S>(rs, boff[0], pg);
+            bload_own<S, OWN>(rs, boff[0], pg);
         } else {
 #pragma unroll
             for (int i = 0; i < OWN; ++i) pg[i] = bload1<S>(rs, boff[i]);
@@ -460,13 +476,14 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
         if constexpr (KIND == kStage4 || KIND == kStage5) {
             const Rsrc rf = plane_rsrc(static_cast<const S*>(a.fbuf) + plane_off(v), recs);
             if constexpr (VEC) {
-                bload2<S>(rf, boff[0], pf);
+                bload_own<S, OWN>(rf, boff[0], pf);
             } else {
 #pragma unroll
                 for (int i = 0; i < OWN; ++i) pf[i] = bload1<S>(rf, boff[i]);
             }
         }
     };
+    auto fetch = [&](int v, bool live) { fetch_to(pg, pf, v, live); };
 
     constexpr int NC = HornerLayout<QM>::total();
     constexpr int TSZ = (TY + 10) * P, VSZ = TY * VP;
@@ -479,7 +496,8 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     // x factors come from the LDS tables, or (orders above 8, and stage 4's
     // own E^n) from one Horner evaluation per cell on the first plane of a
     // mirror pair, the second plane using the cached mirror factor.
-    auto relax = [&](const Step& st, S* tl, double (&base)[NB][OWN]) {
+    auto relax_from = [&](const double (&pg)[NS], const double (&pf)[OWN], const Step& st, S* tl,
+                          double (&base)[NB][OWN]) IMEXLB_INLINE {
         double g[NS], fb[OWN];
 #pragma unroll
         for (int s = 0; s < NS; ++s) g[s] = pg[s];
@@ -637,13 +655,22 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                 base[0][i] = 0.0;
             }
         }
+        // the bases are computed here, not sunk into the pointwise step: the
+        // loaded values then die here and the next loads reuse their
+        // registers (no copy, hence no early wait, at the loop latch)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int i = 0; i < OWN; ++i) opaque(base[b][i]);
     };
+
+    auto relax = [&](const Step& st, S* tl, double (&base)[NB][OWN]) { relax_from(pg, pf, st, tl, base); };
 
     // MP-9 sweeps of one plane from the LDS tile tl into the flux buffers
     // fx, fy: the first half of the threads along x (row tid % TY, cells
     // L (tid / TY) .. +L-1), the second along y (column (tid - NT/2) % TX,
     // cells L seg .. +L-1).
-    auto sweep = [&](const Step& st, const S* tl, R* fx, R* fy) {
+    auto sweep = [&](const Step& st, const S* tl, R* fx, R* fy) IMEXLB_INLINE {
         if (tid < NT / 2) {
             if (st.px != 0.0) {
                 const int row = tid % TY, seg = tid / TY;
@@ -665,7 +692,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     };
 
     // Flux term, stores and moment accumulation of one plane.
-    auto pointwise = [&](const Step& st, const R* fx, const R* fy, const double (&base)[NB][OWN]) {
+    auto pointwise = [&](const Step& st, const R* fx, const R* fy, const double (&base)[NB][OWN]) IMEXLB_INLINE {
         const double sx = fabs(st.px) * a.inv_dx;
         const double sy = fabs(st.py) * a.inv_dy;
         double vf[OWN];
@@ -695,7 +722,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
             }
             const Rsrc ro = plane_rsrc(static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + plane_off(st.v), ps);
             if constexpr (VEC) {
-                bstore2<S>(ro, own_off, outv);
+                bstore_own<S, OWN>(ro, own_off, outv);
             } else {
 #pragma unroll
                 for (int i = 0; i < OWN; ++i)
@@ -704,7 +731,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
             if constexpr (KIND == kStage4) {
                 const Rsrc rf = plane_rsrc(static_cast<S*>(a.fbuf) + plane_off(st.v), ps);
                 if constexpr (VEC) {
-                    bstore2<S>(rf, own_off, fbv);
+                    bstore_own<S, OWN>(rf, own_off, fbv);
                 } else {
 #pragma unroll
                     for (int i = 0; i < OWN; ++i)
@@ -739,7 +766,34 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     Step s1 = load_pstep(tab, 1);  // the plane after it
     double bcur[NB][OWN], bnext[NB][OWN];
     fetch(st.v, true);
-    if constexpr (Sh::PIPE) {
+    if constexpr (PAIR) {
+        // Planes in x-mirror pairs (kx, ky), (Q - 1 - kx, ky), consecutive in
+        // the plane order (even orders): both planes of a pair per iteration,
+        // their global loads issued together one iteration ahead (fixed
+        // register sets A and B), one Horner evaluation per loaded cell for
+        // the x factors of both (no LDS tables), relax both into two tiles,
+        // barrier, sweep both into two pairs of flux buffers, barrier,
+        // pointwise steps of both.
+        double pgB[NS], pfB[OWN], bB[NB][OWN];
+        fetch_to(pgB, pfB, s1.v, true);
+        for (int j = 0;; j += 2) {
+            const Step na = load_pstep(tab, j + 2), nb = load_pstep(tab, j + 3);
+            const bool more = !s1.last();
+            relax_from(pg, pf, st, tile, bcur);
+            relax_from(pgB, pfB, s1, tile + TSZ, bB);
+            fetch_to(pg, pf, na.v, more);
+            fetch_to(pgB, pfB, nb.v, more);
+            __syncthreads();
+            sweep(st, tile, vfx, vfy);
+            sweep(s1, tile + TSZ, vfx + VSZ, vfy + VSZ);
+            __syncthreads();
+            pointwise(st, vfx, vfy, bcur);
+            pointwise(s1, vfx + VSZ, vfy + VSZ, bB);
+            if (!more) break;
+            st = na;
+            s1 = nb;
+        }
+    } else if constexpr (Sh::PIPE) {
         // Software pipeline over the planes, two LDS tiles and two pairs of
         // flux buffers: iteration j sweeps plane j out of tile j % 2 and
         // relaxes plane j + 1 into the other tile, one barrier, then the
@@ -801,10 +855,11 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     }
 }
 
-template <typename S, int KIND, int QM, int TY, int OWN>
-__global__ void __launch_bounds__(kTile2X * TY / OWN) __attribute__((amdgpu_waves_per_eu(2)))
+template <typename S, int KIND, int QM, int TY, int OWN, bool PAIR>
+__global__ void __launch_bounds__(kTile2X * TY / OWN)
+__attribute__((amdgpu_waves_per_eu(Stage2DShape<S, KIND, QM, TY, OWN, PAIR>::WPE)))
 stage2d_kernel(StageArgs a) {
-    using Sh = Stage2DShape<S, KIND, QM, TY, OWN>;
+    using Sh = Stage2DShape<S, KIND, QM, TY, OWN, PAIR>;
     __shared__ S tile[Sh::NBUF * (TY + 10) * Sh::P];
     __shared__ S vfx[Sh::NBUF * TY * Sh::VP];
     __shared__ S vfy[Sh::NBUF * TY * Sh::VP];
@@ -814,8 +869,8 @@ stage2d_kernel(StageArgs a) {
     // interior tiles of a grid whose rows are multiples of OWN take the
     // vector-access path; tiles at a ragged edge the element-wise one
     const bool vec = ((txi + 1) * Sh::TX <= a.nx) && ((tyi + 1) * TY <= a.ny) && (a.nx % OWN == 0);
-    if (vec) stage2d_body<S, KIND, QM, TY, OWN, true>(a, txi, tyi, tile, vfx, vfy, gtab);
-    else stage2d_body<S, KIND, QM, TY, OWN, false>(a, txi, tyi, tile, vfx, vfy, gtab);
+    if (vec) stage2d_body<S, KIND, QM, TY, OWN, PAIR, true>(a, txi, tyi, tile, vfx, vfy, gtab);
+    else stage2d_body<S, KIND, QM, TY, OWN, PAIR, false>(a, txi, tyi, tile, vfx, vfy, gtab);
 }
 
 // ---------------------------------------------------------------------------
@@ -1227,10 +1282,22 @@ hipError_t launch_stage_t(int d, const StageArgs& a, hipStream_t s) {
     if (d == 2) {
         constexpr int TY = kTile2Y, OWN = kOwn2;
         constexpr int NT = kTile2X * TY / OWN;
+        // FP64 stage 3 of even orders takes the mirror-pair loop (stage 5,
+        // with twice its memory traffic, gains nothing from it)
+        constexpr bool CAN_PAIR = sizeof(S) == 8 && KIND == kStage3 && OWN == 2;
+        if constexpr (CAN_PAIR) {
+            if (a.paired) {
+                if (a.qm == 16)
+                    hipLaunchKernelGGL((stage2d_kernel<S, KIND, 16, TY, OWN, true>), dim3(grid), dim3(NT), 0, s, a);
+                else
+                    hipLaunchKernelGGL((stage2d_kernel<S, KIND, 8, TY, OWN, true>), dim3(grid), dim3(NT), 0, s, a);
+                return hipGetLastError();
+            }
+        }
         if (a.qm == 16)
-            hipLaunchKernelGGL((stage2d_kernel<S, KIND, 16, TY, OWN>), dim3(grid), dim3(NT), 0, s, a);
+            hipLaunchKernelGGL((stage2d_kernel<S, KIND, 16, TY, OWN, false>), dim3(grid), dim3(NT), 0, s, a);
         else
-            hipLaunchKernelGGL((stage2d_kernel<S, KIND, 8, TY, OWN>), dim3(grid), dim3(NT), 0, s, a);
+            hipLaunchKernelGGL((stage2d_kernel<S, KIND, 8, TY, OWN, false>), dim3(grid), dim3(NT), 0, s, a);
     } else {
         constexpr int TX = kTile1X;
         if (a.qm == 16)

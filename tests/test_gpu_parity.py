@@ -166,6 +166,28 @@ def test_imex_step_matches_oracle(case, data, steps):
     assert_moments_close(s.moments(), O.moments(oc, ref), c.d)
 
 
+# FP32 storage: the state is rounded to FP32 at every stage store (relative
+# 6e-8), a few steps stay well inside 1e-5 of the state's maximum.
+FP32_STEP_TOL = 1e-5
+
+
+@pytest.mark.parametrize("case,data,steps", STEP_CASES[1:])
+def test_fp32_storage_step_matches_oracle(case, data, steps):
+    """FP32 planes (their own plane order: x-factor table groups of two mirror
+    pairs in 2D, odd orders included) against the FP64 oracle."""
+    _torch()
+    c = I.Config(storage=I.F32, **case)
+    s = I.Solver(c)
+    n, ux, uy, T = fields_for(c, data, 2)
+    s.set_equilibrium(n, ux, uy, T)
+    oc = ocfg(c)
+    F0 = O.equilibrium(oc, n, ux, uy if c.d == 2 else None, T)
+    s.step(steps)
+    ref = O.step(oc, F0, steps)
+    assert_close_inf(s.state.cpu().numpy(), ref, tol=FP32_STEP_TOL, what="state")
+    assert_moments_close(s.moments(), O.moments(oc, ref), c.d, tol=FP32_STEP_TOL)
+
+
 @pytest.mark.slow
 def test_sod_full_run_matches_oracle():
     """The paper's Sod setup run to t = 0.1 (400 steps of 2.5e-4)."""
