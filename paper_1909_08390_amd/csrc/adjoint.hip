@@ -169,6 +169,58 @@ __device__ double face_jacobian(const double (&w)[9], int k) {
     }
 }
 
+// The whole row d(face)/d(w[0..8]) of one face: the limiter's decisions
+// are taken once (as in face_jacobian), then all nine entries follow.
+__device__ __forceinline__ void face_jacobian_row(const double (&w)[9], double (&J)[9]) {
+    double dd[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dd[j] = w[j + 1] - w[j];
+    double t, q;
+    const double fl = mp9_face_linear<double>(dd, w[4], t, q);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) J[k] = linear_weight(k);
+    if (!(q > 0.0)) return;
+    const double f = w[4], g = w[5], ul = f + t;
+    const double cm = dd[3] - dd[2], c0 = dd[4] - dd[3], cp = dd[5] - dd[4];
+    double vm, v0;
+    const double am[4] = {fma(4.0, cm, -c0), fma(4.0, c0, -cm), cm, c0};
+    const double a0[4] = {fma(4.0, c0, -cp), fma(4.0, cp, -c0), c0, cp};
+    const int sm = minmod4_sel(am, vm);
+    const int s0 = minmod4_sel(a0, v0);
+    const double lc = fma(4.0 / 3.0, vm, fma(0.5, dd[3], f));
+    const double md = fma(0.5, dd[4] - v0, f);
+    const double cv[5] = {f, g, md, ul, lc};
+    auto pick_min3 = [&](int i, int j, int l) {
+        int r = cv[j] < cv[i] ? j : i;
+        return cv[l] < cv[r] ? l : r;
+    };
+    auto pick_max3 = [&](int i, int j, int l) {
+        int r = cv[j] > cv[i] ? j : i;
+        return cv[l] > cv[r] ? l : r;
+    };
+    const int a = pick_min3(0, 1, 2), b = pick_min3(0, 3, 4);
+    const int lo = cv[b] > cv[a] ? b : a;
+    const int c = pick_max3(0, 1, 2), e = pick_max3(0, 3, 4);
+    const int hi = cv[e] < cv[c] ? e : c;
+    int sel;
+    if (fl < cv[lo]) sel = lo;
+    else if (fl > cv[hi]) sel = hi;
+    else return;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double ek3 = k == 3 ? 1.0 : 0.0, ek4 = k == 4 ? 1.0 : 0.0, ek5 = k == 5 ? 1.0 : 0.0;
+        double r;
+        switch (sel) {
+            case 0: r = ek4; break;
+            case 1: r = ek5; break;
+            case 2: r = 0.5 * ek4 + 0.5 * ek5 - 0.5 * dminmod_arg(s0, 4, 5, k); break;
+            case 3: r = 5.0 * ek4 - 4.0 * ek3; break;
+            default: r = 1.5 * ek4 - 0.5 * ek3 + (4.0 / 3.0) * dminmod_arg(sm, 3, 4, k); break;
+        }
+        J[k] = r;
+    }
+}
+
 // Adjoint contribution along one axis to node t of a line of n nodes
 // (stride st): sum over the faces whose stencils read t (or a ghost node
 // that copies t) of d(face)/d(node) * d(face), where d(face s) =
@@ -220,6 +272,128 @@ __device__ __forceinline__ double adj_axis(const double* F, const Lin4& dA, size
     if (p == 0.0) return 0.0;
     return p > 0.0 ? adj_axis_dir<true>(F, dA, base, st, n, bc, t, p * inv_ds)
                    : adj_axis_dir<false>(F, dA, base, st, n, bc, t, p * inv_ds);
+}
+
+// Face-major form along one axis: the thread owns the kAdjSeg nodes t0 ..
+// t0+kAdjSeg-1 of a line and streams over the kAdjSeg + 8 faces whose
+// stencils read them, each evaluated once with its whole Jacobian row (a
+// face is evaluated (kAdjSeg + 8) / kAdjSeg times per node instead of nine).
+// Positions p = 0 .. kAdjSeg+15 stand for node t0 - 8 + p; a rolling window
+// holds F at the nine positions of the current face and a rolling
+// accumulator their contributions, so the position leaving the window is
+// complete.  Positions left / right of the segment are the ghost nodes of an
+// outflow line (folded into its end nodes) or, on a periodic line, nodes of
+// other segments (dropped here, counted there).
+constexpr int kAdjSeg = 32;
+
+template <bool FWD>
+__device__ __forceinline__ void adj_stream(const double* F, const Lin4& dA, size_t base, long long st, int n,
+                                           int bc, int t0, double pinv, double* out, int accumulate) {
+    constexpr int L = kAdjSeg;
+    auto fat = [&](int p) { return F[base + (size_t)bc_map(t0 - 8 + p, n, bc) * st]; };
+    const int sa = t0 - (FWD ? 4 : 5);  // node s of face 0
+    auto dat = [&](int q) {             // dA at node sa + q, zero outside an outflow line
+        const int j = sa + q;
+        if (bc == 1) return lin_at(dA, base + (size_t)bc_map(j, n, 1) * st);
+        return (j >= 0 && j < n) ? lin_at(dA, base + (size_t)j * st) : 0.0;
+    };
+    auto emit = [&](int t, double val) {
+        const size_t o = base + (size_t)t * st;
+        out[o] = accumulate ? out[o] + val : val;
+    };
+    double w[9], r[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        w[k] = fat(k);
+        r[k] = 0.0;
+    }
+    double a0 = dat(0), a1 = dat(1);
+    double gl = 0.0, gend = 0.0;  // left ghosts; the last node of an outflow line and its ghosts
+    const bool outflow = bc == 0;
+#pragma unroll 1
+    for (int f = 0; f < L + 8; ++f) {
+        const double dface = pinv * (a0 - a1);
+        double fw[9];
+#pragma unroll
+        for (int kk = 0; kk < 9; ++kk) fw[kk] = w[FWD ? kk : 8 - kk];
+        double J[9];
+        face_jacobian_row(fw, J);
+#pragma unroll
+        for (int kk = 0; kk < 9; ++kk) r[FWD ? kk : 8 - kk] = fma(J[kk], dface, r[FWD ? kk : 8 - kk]);
+        // position f is complete
+        const double val = r[0];
+        if (f < 8) {
+            gl += val;
+        } else {
+            const int t = t0 + f - 8;
+            if (outflow && t >= n - 1) {
+                gend += val;
+            } else if (t < n) {
+                emit(t, (outflow && t == 0) ? val + gl : val);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            r[k] = r[k + 1];
+            w[k] = w[k + 1];
+        }
+        r[8] = 0.0;
+        if (f + 1 < L + 8) {
+            w[8] = fat(f + 9);
+            a0 = a1;
+            a1 = dat(f + 2);
+        }
+    }
+    if (outflow && n - 1 >= t0 && n - 1 < t0 + L) {  // this segment holds the last node
+        double g = gend;
+#pragma unroll
+        for (int k = 1; k < 9; ++k) g += r[k - 1];  // positions L+8 .. L+15, shifted once
+        emit(n - 1, (n - 1 == 0) ? g + gl : g);
+    }
+}
+
+// out[v][c] (=|+=) the contribution of one axis (AX 0: x lines, thread per
+// segment of a row; AX 1: y lines, thread per segment of a column, adjacent
+// lanes on adjacent columns).
+template <int AX>
+__global__ void __launch_bounds__(kAdjBlock) advect_adjoint_seg_kernel(const DevTables* __restrict__ tabp,
+                                                                       const double* __restrict__ F, Lin4 dA,
+                                                                       double* out, int nx, int ny, int bc,
+                                                                       double inv_ds, int accumulate) {
+    constexpr int L = kAdjSeg;
+    CTab* tab = (CTab*)tabp;
+    const long long cells = (long long)nx * ny;
+    const int v = blockIdx.y;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int n, t0;
+    size_t base;
+    long long st;
+    double p;
+    if (AX == 0) {
+        const int nseg = (nx + L - 1) / L;
+        if (i >= (long long)nseg * ny) return;
+        t0 = (int)(i % nseg) * L;
+        n = nx;
+        st = 1;
+        base = (size_t)v * cells + (size_t)(i / nseg) * nx;
+        p = tab->plane[v].px;
+    } else {
+        const int nseg = (ny + L - 1) / L;
+        if (i >= (long long)nseg * nx) return;
+        t0 = (int)(i / nx) * L;
+        n = ny;
+        st = nx;
+        base = (size_t)v * cells + (size_t)(i % nx);
+        p = tab->plane[v].py;
+    }
+    if (p > 0.0) {
+        adj_stream<true>(F, dA, base, st, n, bc, t0, p * inv_ds, out, accumulate);
+    } else if (p < 0.0) {
+        adj_stream<false>(F, dA, base, st, n, bc, t0, p * inv_ds, out, accumulate);
+    } else if (!accumulate) {
+#pragma unroll 1
+        for (int k = 0; k < L && t0 + k < n; ++k) out[base + (size_t)(t0 + k) * st] = 0.0;
+    }
 }
 
 // out[v][c] (=|+=) V^T dA at every node, both axes in 2D.
@@ -379,11 +553,27 @@ hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const
                                  hipStream_t s) {
     const Lin4 L = make_lin(ny_in, y, cf);
     const long long cells = (long long)nx * ny;
-    const dim3 grid((unsigned)((cells + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
-    if (d == 2)
-        hipLaunchKernelGGL((advect_adjoint_kernel<2>), grid, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, ny, bcx, bcy, inv_dx, inv_dy, (int)accumulate);
-    else
-        hipLaunchKernelGGL((advect_adjoint_kernel<1>), grid, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, 1, bcx, 0, inv_dx, 0.0, (int)accumulate);
+    // The face-major segments need periodic lines of at least kAdjSeg + 8
+    // nodes (a shorter ring would hold one face twice in a segment's range);
+    // shorter periodic lines take the gather form.
+    const bool short_ring = (bcx == 1 && nx < kAdjSeg + 8) || (d == 2 && bcy == 1 && ny < kAdjSeg + 8);
+    if (short_ring) {
+        const dim3 grid((unsigned)((cells + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
+        if (d == 2)
+            hipLaunchKernelGGL((advect_adjoint_kernel<2>), grid, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, ny, bcx, bcy, inv_dx, inv_dy, (int)accumulate);
+        else
+            hipLaunchKernelGGL((advect_adjoint_kernel<1>), grid, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, 1, bcx, 0, inv_dx, 0.0, (int)accumulate);
+        return hipGetLastError();
+    }
+    const int nyl = d == 2 ? ny : 1;
+    const long long segx = (long long)((nx + kAdjSeg - 1) / kAdjSeg) * nyl;
+    const dim3 gx((unsigned)((segx + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
+    hipLaunchKernelGGL((advect_adjoint_seg_kernel<0>), gx, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, nyl, bcx, inv_dx, (int)accumulate);
+    if (d == 2) {
+        const long long segy = (long long)((ny + kAdjSeg - 1) / kAdjSeg) * nx;
+        const dim3 gy((unsigned)((segy + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
+        hipLaunchKernelGGL((advect_adjoint_seg_kernel<1>), gy, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, ny, bcy, inv_dy, 1);
+    }
     return hipGetLastError();
 }
 

@@ -178,9 +178,19 @@ constexpr int kOwn2 = IMEXLB_OWN2;
 constexpr int kTile1X = 1024;
 // Tile widths (cells) the batched 1D passes can be launched with.
 constexpr int kBatchTiles[3] = {256, 512, 1024};
-// Tiles are visited in column bands of this many tiles (2D blocking of the
-// work that runs concurrently on one XCD, so halos hit that XCD's L2).
-constexpr int kBand = 2;
+// 2D tiles are visited in patches of kPatchW x kPatchH tiles (patch rows
+// top to bottom, patches left to right inside a patch row, tiles row-major
+// inside a patch), so that the tiles running at the same time on one XCD
+// (32 CUs x 2 work-groups) form a compact block whose halos hit that XCD's
+// L2.  The patch is wide in x: x-halo reads are 5-cell row segments that
+// use a fraction of each cache line, y-halo reads whole rows.
+#ifndef IMEXLB_PATCH_W
+#define IMEXLB_PATCH_W 12
+#endif
+#ifndef IMEXLB_PATCH_H
+#define IMEXLB_PATCH_H 6
+#endif
+constexpr int kPatchW = IMEXLB_PATCH_W, kPatchH = IMEXLB_PATCH_H;
 // Nodes per x-factor table group of the 2D plane order (orders up to 8):
 // FP32 storage takes two mirror pairs per group (the kernels keep 4 tables
 // of one double per loaded cell in LDS), FP64 storage a whole set (8).

@@ -269,17 +269,21 @@ __device__ __forceinline__ void bstore_own(Rsrc r, int off, const S* v) {
     else bstore1<S>(r, off, v[0]);
 }
 
-// Tile visiting order: column bands of kBand tiles, row-major inside a band;
-// consecutive logical indices go to one XCD (blockIdx % 8 selects the XCD).
+// Tile visiting order: patch rows of kPatchH tile rows (the last one may be
+// lower), patches of kPatchW tile columns inside a patch row (the last one
+// may be narrower), row-major inside a patch; consecutive logical indices go
+// to one XCD (blockIdx % 8 selects the XCD).
 __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& ty) {
     const int ntiles = a.ntx * a.nty;
     const int l = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
     if (l >= ntiles) return false;
-    const int per_band = kBand * a.nty;
-    const int band = l / per_band, rem = l % per_band;
-    const int wb = min(kBand, a.ntx - band * kBand);
-    tx = band * kBand + rem % wb;
-    ty = rem / wb;
+    const int ph = min(kPatchH, a.nty);
+    const int prow = l / (a.ntx * ph), rem = l - prow * a.ntx * ph;
+    const int h = min(ph, a.nty - prow * ph);
+    const int pcol = rem / (kPatchW * h), rem2 = rem - pcol * kPatchW * h;
+    const int w = min(kPatchW, a.ntx - pcol * kPatchW);
+    tx = pcol * kPatchW + rem2 % w;
+    ty = prow * ph + rem2 / w;
     return true;
 }
 
