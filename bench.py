@@ -30,7 +30,8 @@ PMAX8 = 4.144547186125894  # largest root of He_8
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E spec peak
 METRIC = "velocity-node updates/s per IMEX step, FP32 vs FP64, % of HBM roofline"
 # Kernel sources whose hash ties a committed counter summary to the code it measured.
-KERNEL_SOURCES = ("paper_1909_08390_amd/csrc/kernels.hip", "paper_1909_08390_amd/csrc/common.hpp")
+KERNEL_SOURCES = ("paper_1909_08390_amd/csrc/kernels.hip", "paper_1909_08390_amd/csrc/common.hpp",
+                  "paper_1909_08390_amd/csrc/device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_passes_riemann4096_hbm_traffic.txt")
 
 

@@ -274,8 +274,8 @@ __device__ __forceinline__ double adj_axis(const double* F, const Lin4& dA, size
                    : adj_axis_dir<false>(F, dA, base, st, n, bc, t, p * inv_ds);
 }
 
-// Face-major form along one axis: the thread owns the kAdjSeg nodes t0 ..
-// t0+kAdjSeg-1 of a line and streams over the kAdjSeg + 8 faces whose
+// Face-major form along a line (used for y columns): the thread owns the
+// kAdjSeg nodes t0 .. t0+kAdjSeg-1 and streams over the kAdjSeg + 8 faces whose
 // stencils read them, each evaluated once with its whole Jacobian row (a
 // face is evaluated (kAdjSeg + 8) / kAdjSeg times per node instead of nine).
 // Positions p = 0 .. kAdjSeg+15 stand for node t0 - 8 + p; a rolling window
@@ -352,48 +352,87 @@ __device__ __forceinline__ void adj_stream(const double* F, const Lin4& dA, size
     }
 }
 
-// out[v][c] (=|+=) the contribution of one axis (AX 0: x lines, thread per
-// segment of a row; AX 1: y lines, thread per segment of a column, adjacent
-// lanes on adjacent columns).
-template <int AX>
-__global__ void __launch_bounds__(kAdjBlock) advect_adjoint_seg_kernel(const DevTables* __restrict__ tabp,
-                                                                       const double* __restrict__ F, Lin4 dA,
-                                                                       double* out, int nx, int ny, int bc,
-                                                                       double inv_ds, int accumulate) {
+// x lines, wave-cooperative: one 64-lane work-group per chunk of kChunk
+// nodes of a row.  Lane l evaluates face s = c0 - 4 + l (flow to +x; else
+// c0 - 5 + l), the 64 faces whose stencils read the chunk's nodes, with
+// coalesced window loads, and writes its nine weighted Jacobian entries to
+// LDS; node c0 + i then gathers the nine entries addressed to it (from lanes
+// i + 8 - k, or i + k for flow to -x).  The end nodes of an outflow row also
+// collect the entries at ghost positions.
+constexpr int kChunk = 56;
+
+__device__ __forceinline__ int chunk_pos(bool fwd, int c0, int lane, int kk) {  // node index written by (lane, kk)
+    return fwd ? c0 - 8 + lane + kk : c0 + lane - kk;
+}
+
+__global__ void __launch_bounds__(64) advect_adjoint_xchunk_kernel(const DevTables* __restrict__ tabp,
+                                                                   const double* __restrict__ F, Lin4 dA,
+                                                                   double* out, int nx, int ny, int bc,
+                                                                   double inv_dx, int accumulate) {
+    __shared__ double contrib[9 * 64];
+    CTab* tab = (CTab*)tabp;
+    const long long cells = (long long)nx * ny;
+    const int v = blockIdx.y;
+    const int nch = (nx + kChunk - 1) / kChunk;
+    if ((long long)blockIdx.x >= (long long)nch * ny) return;
+    const int y = blockIdx.x / nch, c0 = (blockIdx.x % nch) * kChunk;
+    const int lane = threadIdx.x, n = nx;
+    const size_t base = (size_t)v * cells + (size_t)y * nx;
+    const double p = tab->plane[v].px;
+    const int t = c0 + lane;
+    if (p == 0.0) {
+        if (!accumulate && lane < kChunk && t < n) out[base + t] = 0.0;
+        return;
+    }
+    const bool fwd = p > 0.0;
+    const int s = c0 - (fwd ? 4 : 5) + lane;
+    double w[9];
+#pragma unroll
+    for (int kk = 0; kk < 9; ++kk) w[kk] = F[base + bc_map(fwd ? s - 4 + kk : s + 5 - kk, n, bc)];
+    auto dat = [&](int j) {
+        if (bc == 1) return lin_at(dA, base + (size_t)bc_map(j, n, 1));
+        return (j >= 0 && j < n) ? lin_at(dA, base + (size_t)j) : 0.0;
+    };
+    const double dface = p * inv_dx * (dat(s) - dat(s + 1));
+    double J[9];
+    face_jacobian_row(w, J);
+#pragma unroll
+    for (int kk = 0; kk < 9; ++kk) contrib[kk * 64 + lane] = J[kk] * dface;
+    __syncthreads();
+    if (lane < kChunk && t < n) {
+        double val = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < 9; ++kk) val += contrib[kk * 64 + (fwd ? lane + 8 - kk : lane + kk)];
+        if (bc == 0 && (t == 0 || t == n - 1)) {  // ghost positions copy the end nodes
+            for (int l = 0; l < 64; ++l)
+                for (int kk = 0; kk < 9; ++kk) {
+                    const int j = chunk_pos(fwd, c0, l, kk);
+                    if ((t == 0 && j < 0) || (t == n - 1 && j > n - 1)) val += contrib[kk * 64 + l];
+                }
+        }
+        const size_t o = base + (size_t)t;
+        out[o] = accumulate ? out[o] + val : val;
+    }
+}
+
+// y lines: thread per segment of a column, adjacent lanes on adjacent
+// columns (coalesced), out[v][c] += the y contribution.
+__global__ void __launch_bounds__(kAdjBlock) advect_adjoint_ycol_kernel(const DevTables* __restrict__ tabp,
+                                                                        const double* __restrict__ F, Lin4 dA,
+                                                                        double* out, int nx, int ny, int bc,
+                                                                        double inv_dy) {
     constexpr int L = kAdjSeg;
     CTab* tab = (CTab*)tabp;
     const long long cells = (long long)nx * ny;
     const int v = blockIdx.y;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int n, t0;
-    size_t base;
-    long long st;
-    double p;
-    if (AX == 0) {
-        const int nseg = (nx + L - 1) / L;
-        if (i >= (long long)nseg * ny) return;
-        t0 = (int)(i % nseg) * L;
-        n = nx;
-        st = 1;
-        base = (size_t)v * cells + (size_t)(i / nseg) * nx;
-        p = tab->plane[v].px;
-    } else {
-        const int nseg = (ny + L - 1) / L;
-        if (i >= (long long)nseg * nx) return;
-        t0 = (int)(i / nx) * L;
-        n = ny;
-        st = nx;
-        base = (size_t)v * cells + (size_t)(i % nx);
-        p = tab->plane[v].py;
-    }
-    if (p > 0.0) {
-        adj_stream<true>(F, dA, base, st, n, bc, t0, p * inv_ds, out, accumulate);
-    } else if (p < 0.0) {
-        adj_stream<false>(F, dA, base, st, n, bc, t0, p * inv_ds, out, accumulate);
-    } else if (!accumulate) {
-#pragma unroll 1
-        for (int k = 0; k < L && t0 + k < n; ++k) out[base + (size_t)(t0 + k) * st] = 0.0;
-    }
+    const int nseg = (ny + L - 1) / L;
+    if (i >= (long long)nseg * nx) return;
+    const int t0 = (int)(i / nx) * L;
+    const size_t base = (size_t)v * cells + (size_t)(i % nx);
+    const double p = tab->plane[v].py;
+    if (p > 0.0) adj_stream<true>(F, dA, base, nx, ny, bc, t0, p * inv_dy, out, 1);
+    else if (p < 0.0) adj_stream<false>(F, dA, base, nx, ny, bc, t0, p * inv_dy, out, 1);
 }
 
 // out[v][c] (=|+=) V^T dA at every node, both axes in 2D.
@@ -553,9 +592,10 @@ hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const
                                  hipStream_t s) {
     const Lin4 L = make_lin(ny_in, y, cf);
     const long long cells = (long long)nx * ny;
-    // The face-major segments need periodic lines of at least kAdjSeg + 8
-    // nodes (a shorter ring would hold one face twice in a segment's range);
-    // shorter periodic lines take the gather form.
+    // Face-major forms: x rows in 64-face chunks, y columns in streamed
+    // segments.  They need periodic lines of at least kAdjSeg + 8 nodes (on a
+    // shorter ring a segment's face range, or a face's window, would hold one
+    // node twice); shorter periodic lines take the gather form.
     const bool short_ring = (bcx == 1 && nx < kAdjSeg + 8) || (d == 2 && bcy == 1 && ny < kAdjSeg + 8);
     if (short_ring) {
         const dim3 grid((unsigned)((cells + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
@@ -566,13 +606,12 @@ hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const
         return hipGetLastError();
     }
     const int nyl = d == 2 ? ny : 1;
-    const long long segx = (long long)((nx + kAdjSeg - 1) / kAdjSeg) * nyl;
-    const dim3 gx((unsigned)((segx + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
-    hipLaunchKernelGGL((advect_adjoint_seg_kernel<0>), gx, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, nyl, bcx, inv_dx, (int)accumulate);
+    const long long chx = (long long)((nx + kChunk - 1) / kChunk) * nyl;
+    hipLaunchKernelGGL(advect_adjoint_xchunk_kernel, dim3((unsigned)chx, (unsigned)nplanes), dim3(64), 0, s, tab, F, L, out, nx, nyl, bcx, inv_dx, (int)accumulate);
     if (d == 2) {
         const long long segy = (long long)((ny + kAdjSeg - 1) / kAdjSeg) * nx;
         const dim3 gy((unsigned)((segy + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
-        hipLaunchKernelGGL((advect_adjoint_seg_kernel<1>), gy, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, ny, bcy, inv_dy, 1);
+        hipLaunchKernelGGL(advect_adjoint_ycol_kernel, gy, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, ny, bcy, inv_dy);
     }
     return hipGetLastError();
 }

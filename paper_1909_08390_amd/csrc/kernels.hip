@@ -299,11 +299,15 @@ __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& 
 //    over L = 2 OWN cells of a row, the second half along y over L cells of
 //    a column;
 //  - x factors (orders up to 8) from LDS tables of one table group of the
-//    plane order (kTabNodes nodes: mirror pairs), built when a group starts;
-//  - software-pipelined planes: sweep plane j and relax plane j + 1 into
-//    the other of two LDS tiles (the global loads of plane j + 2 then in
-//    flight), one barrier, pointwise stage algebra + stores + moments of
-//    plane j (stage 4: relax, barrier, sweeps, barrier, pointwise).
+//    plane order (tab_nodes_2d nodes: mirror pairs), built when a group
+//    starts, or, in the mirror-pair loop, from one Horner evaluation per
+//    loaded cell for both planes of a pair;
+//  - three plane loops (Stage2DShape): the software pipeline (FP32 passes 3
+//    and 5: sweep plane j and relax plane j + 1 into the other of two LDS
+//    tiles, the loads of plane j + 2 in flight, one barrier, pointwise step
+//    of plane j), the mirror-pair loop (FP64 pass 3 of even orders: both
+//    planes of an x-mirror pair per iteration) and the plain loop (relax,
+//    barrier, sweeps, barrier, pointwise).
 // LDS pitches are odd so the row-strided x windows and the column-strided
 // results spread over all banks.
 // ---------------------------------------------------------------------------
