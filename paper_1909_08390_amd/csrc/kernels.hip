@@ -922,7 +922,7 @@ __device__ __forceinline__ void bstore4(Rsrc r, int off, const S* v) {
     }
 }
 
-template <typename S, int KIND, int QM, int TX, typename A>
+template <typename S, int KIND, int QM, int TX, bool VEC, typename A>
 __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 10]) {
     constexpr int L = 4, NT = TX / L, NS = L + 1;
     constexpr bool RELAX = KIND != kAdvect;
@@ -934,7 +934,6 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
     const double* msrc = a.msrc;
     CTab* tab = (CTab*)a.tab;
     const int ox0 = x0 + tid * L;
-    const bool vec = (x0 + TX <= nx) && (nx % L == 0);
 
     // loaded slots: own cells 0..3, halo slot 4 (threads 0..9; the others
     // load cell gcell[0] again so that every thread issues the same loads)
@@ -978,10 +977,16 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
 #pragma unroll
     for (int i = 0; i < L; ++i) acc[i] = Acc{0.0, 0.0, 0.0, 0.0};
 
+    // element offset of plane v (a plane holds fewer than 2^31 elements)
+    const unsigned ps32 = (unsigned)ps;
+    auto plane_off = [&](int v) -> size_t { return (size_t)((unsigned long long)(unsigned)v * ps32); };
+    // Loads of plane v; past the last plane (live == false) the resources
+    // have no records, so every iteration issues the same loads.
     double pg[NS], pf[L];
-    auto fetch = [&](int v) {
-        const Rsrc rs = plane_rsrc(static_cast<const S*>(a.src) + (size_t)v * ps, ps);
-        if (vec) {
+    auto fetch = [&](int v, bool live) IMEXLB_INLINE {
+        const long long recs = live ? ps : 0;
+        const Rsrc rs = plane_rsrc(static_cast<const S*>(a.src) + plane_off(v), recs);
+        if constexpr (VEC) {
             bload4<S>(rs, boff[0], pg);
         } else {
 #pragma unroll
@@ -989,8 +994,8 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
         }
         pg[L] = bload1<S>(rs, boff[L]);
         if constexpr (KIND == kStage4 || KIND == kStage5) {
-            const Rsrc rf = plane_rsrc(static_cast<const S*>(a.fbuf) + (size_t)v * ps, ps);
-            if (vec) {
+            const Rsrc rf = plane_rsrc(static_cast<const S*>(a.fbuf) + plane_off(v), recs);
+            if constexpr (VEC) {
                 bload4<S>(rf, boff[0], pf);
             } else {
 #pragma unroll
@@ -1000,22 +1005,18 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
     };
 
     constexpr int NC = HornerLayout<QM>::total();
-    const int np = tab->nplanes;
-    Step s0 = load_pstep(tab, 0);
-    Step s1 = load_pstep(tab, np > 1 ? 1 : 0);
-    fetch(s0.v);
-    for (int j = 0; j < np; ++j) {
-        const Step st = s0;
-        s0 = s1;
-        if (j + 2 < np) s1 = load_pstep(tab, j + 2);
-        double g[NS], fb[L];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) g[s] = pg[s];
-#pragma unroll
-        for (int i = 0; i < L; ++i) fb[i] = pf[i];
-        fetch(s0.v);  // unconditional (the last iteration refetches)
+    // relax-time part of the stage algebra at the own cells (the stage value
+    // without its flux term; stage 4: the stage value and R)
+    constexpr int NB = KIND == kStage4 ? 2 : 1;
+    Step st = load_pstep(tab, 0);
+    Step s1 = load_pstep(tab, 1);
+    fetch(st.v, true);
+    for (int j = 0;; ++j) {  // ends at the plane flagged last
+        const Step sn = s1;
+        s1 = load_pstep(tab, j + 2);
         S* buf = tile[j & 1];
 
+        // relax on read of the loaded planes into the LDS tile
         double e[NS], en[L];
         if constexpr (RELAX) {
             if (st.new_tab() && st.set() == 1) {
@@ -1026,28 +1027,43 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
                     for (int i = 0; i < L; ++i) nP[i] = a.chi_fac * nP[i] * (nth[i] + 1.0);
                 }
             }
-            double gx[NS], gxn[L];
+            // (both branches assign the same arrays, so that they stay in registers)
+            double gx[NS], tgm[NS], gxn[L], tngm[L];
             if (st.first()) {
                 CDp hx = hrow<QM>(tab, st.set(), st.hx());
                 double cf[NC];
 #pragma unroll
                 for (int i = 0; i < NC; ++i) cf[i] = hx[i];
 #pragma unroll
-                for (int s = 0; s < NS; ++s) g_pair_r<QM>(cf, sux[s], sth[s], gx[s], sgm[s]);
-                if constexpr (KIND == kStage4) {
+                for (int s = 0; s < NS; ++s) g_pair_r<QM>(cf, sux[s], sth[s], gx[s], tgm[s]);
 #pragma unroll
-                    for (int i = 0; i < L; ++i) g_pair_r<QM>(cf, nux[i], nth[i], gxn[i], ngm[i]);
+                for (int i = 0; i < L; ++i) {
+                    gxn[i] = 0.0;
+                    tngm[i] = 0.0;
+                    if constexpr (KIND == kStage4) g_pair_r<QM>(cf, nux[i], nth[i], gxn[i], tngm[i]);
                 }
             } else {
 #pragma unroll
-                for (int s = 0; s < NS; ++s) gx[s] = sgm[s];
+                for (int s = 0; s < NS; ++s) {
+                    gx[s] = sgm[s];
+                    tgm[s] = sgm[s];
+                }
 #pragma unroll
-                for (int i = 0; i < L; ++i) gxn[i] = ngm[i];
+                for (int i = 0; i < L; ++i) {
+                    gxn[i] = ngm[i];
+                    tngm[i] = ngm[i];
+                }
             }
 #pragma unroll
-            for (int s = 0; s < NS; ++s) e[s] = sP[s] * gx[s];
+            for (int s = 0; s < NS; ++s) {
+                sgm[s] = tgm[s];
+                e[s] = sP[s] * gx[s];
+            }
 #pragma unroll
-            for (int i = 0; i < L; ++i) en[i] = KIND == kStage4 ? nP[i] * gxn[i] : 0.0;
+            for (int i = 0; i < L; ++i) {
+                ngm[i] = tngm[i];
+                en[i] = KIND == kStage4 ? nP[i] * gxn[i] : 0.0;
+            }
         } else {
 #pragma unroll
             for (int s = 0; s < NS; ++s) e[s] = 0.0;
@@ -1055,8 +1071,33 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
             for (int i = 0; i < L; ++i) en[i] = 0.0;
         }
 #pragma unroll
-        for (int s = 0; s < L; ++s) buf[lidx[s]] = (S)(RELAX ? fma(a.a_rel, g[s], a.b_rel * e[s]) : g[s]);
-        if (hval) buf[lidx[L]] = (S)(RELAX ? fma(a.a_rel, g[L], a.b_rel * e[L]) : g[L]);
+        for (int s = 0; s < L; ++s) buf[lidx[s]] = (S)(RELAX ? fma(a.a_rel, pg[s], a.b_rel * e[s]) : pg[s]);
+        if (hval) buf[lidx[L]] = (S)(RELAX ? fma(a.a_rel, pg[L], a.b_rel * e[L]) : pg[L]);
+        // stage algebra with the host-combined coefficients k[] (see
+        // StageArgs), the flux term added after the sweep
+        double base[NB][L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            if constexpr (KIND == kStage3) {
+                base[0][i] = fma(-a.k[0], pg[i] - e[i], pg[i]);
+            } else if constexpr (KIND == kStage4) {
+                const double fn = pf[i], g3 = pg[i];
+                const double dn = fn - en[i], d3 = g3 - e[i];
+                base[0][i] = fma(0.75, fn, fma(0.25, g3, fma(a.k[1], dn, -a.k[2] * d3)));
+                base[1][i] = fma(5.0 / 6.0, fn, fma(1.0 / 6.0, g3, fma(-a.k[3], dn, -a.k[4] * d3)));
+            } else if constexpr (KIND == kStage5) {
+                base[0][i] = fma(-a.k[5], pg[i] - e[i], pf[i]);
+            } else {
+                base[0][i] = 0.0;
+            }
+        }
+        // computed here, so that the loaded registers die and the next
+        // loads reuse them (no copy, hence no early wait)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int i = 0; i < L; ++i) opaque(base[b][i]);
+        fetch(sn.v, !st.last());
         __syncthreads();
 
         // MP-9 over the own cells: window of L + 9 values around them
@@ -1084,7 +1125,7 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
         }
 
         if constexpr (KIND == kAdvect) {
-            double* o = static_cast<double*>(a.out) + (size_t)st.v * ps + ox0;
+            double* o = static_cast<double*>(a.out) + plane_off(st.v) + ox0;
 #pragma unroll
             for (int i = 0; i < L; ++i)
                 if (ox0 + i < nx) o[i] = vf[i];
@@ -1093,23 +1134,18 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
 #pragma unroll
             for (int i = 0; i < L; ++i) {
                 if constexpr (KIND == kStage3) {
-                    const double fn = g[i];
-                    outv[i] = (S)fma(-a.k[0], fn - e[i], fma(-a.dt, vf[i], fn));
+                    outv[i] = (S)fma(-a.dt, vf[i], base[0][i]);
                     fbv[i] = outv[i];
                 } else if constexpr (KIND == kStage4) {
-                    const double fn = fb[i], g3 = g[i];
-                    const double dn = fn - en[i], d3 = g3 - e[i];
-                    const double s4 = fma(0.75, fn, fma(0.25, g3, fma(a.k[1], dn, fma(-a.k[2], d3, -0.25 * a.dt * vf[i]))));
-                    const double r = fma(5.0 / 6.0, fn, fma(1.0 / 6.0, g3, fma(-a.k[3], dn, fma(-a.k[4], d3, -(1.0 / 6.0) * a.dt * vf[i]))));
-                    outv[i] = (S)s4;
-                    fbv[i] = (S)r;
+                    outv[i] = (S)fma(-0.25 * a.dt, vf[i], base[0][i]);
+                    fbv[i] = (S)fma(-(1.0 / 6.0) * a.dt, vf[i], base[1][i]);
                 } else {  // kStage5
-                    fbv[i] = (S)fma(-a.k[5], g[i] - e[i], fma(-(2.0 / 3.0) * a.dt, vf[i], fb[i]));
+                    fbv[i] = (S)fma(-(2.0 / 3.0) * a.dt, vf[i], base[0][i]);
                     outv[i] = fbv[i];
                 }
             }
-            const Rsrc ro = plane_rsrc(static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + (size_t)st.v * ps, ps);
-            if (vec) {
+            const Rsrc ro = plane_rsrc(static_cast<S*>(KIND == kStage5 ? a.fbuf : a.out) + plane_off(st.v), ps);
+            if constexpr (VEC) {
                 bstore4<S>(ro, own_off, outv);
             } else {
 #pragma unroll
@@ -1117,8 +1153,8 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
                     if (ox0 + i < nx) bstore1<S>(ro, own_off + i * (int)sizeof(S), outv[i]);
             }
             if constexpr (KIND == kStage4) {
-                const Rsrc rf = plane_rsrc(static_cast<S*>(a.fbuf) + (size_t)st.v * ps, ps);
-                if (vec) {
+                const Rsrc rf = plane_rsrc(static_cast<S*>(a.fbuf) + plane_off(st.v), ps);
+                if constexpr (VEC) {
                     bstore4<S>(rf, own_off, fbv);
                 } else {
 #pragma unroll
@@ -1139,6 +1175,8 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
                 for (int i = 0; i < L; ++i) acc[i].se += (double)outv[i];
             }
         }
+        if (st.last()) break;
+        st = sn;
     }
 
     if constexpr (KIND != kAdvect) {
@@ -1157,13 +1195,21 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
     }
 }
 
+// interior tiles of a line whose length is a multiple of 4 take the
+// vector-access body, tiles at a ragged end the element-wise one
+template <typename S, int KIND, int QM, int TX, typename A>
+__device__ __forceinline__ void stage1d_tile(const A& a, int x0, S (*tile)[TX + 10]) {
+    if ((x0 + TX <= a.nx) && (a.nx % 4 == 0)) stage1d_body<S, KIND, QM, TX, true>(a, x0, tile);
+    else stage1d_body<S, KIND, QM, TX, false>(a, x0, tile);
+}
+
 template <typename S, int KIND, int QM, int TX>
 __global__ void __launch_bounds__(TX / 4) __attribute__((amdgpu_waves_per_eu(2)))
 stage1d_kernel(StageArgs a) {
     __shared__ S tile[2][TX + 10];
     const int logical = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
     if (logical >= a.ntx) return;
-    stage1d_body<S, KIND, QM, TX>(a, logical * TX, tile);
+    stage1d_tile<S, KIND, QM, TX>(a, logical * TX, tile);
 }
 
 // Batched form: block j runs tile tiles[j] = (tube, first cell) with that
@@ -1176,7 +1222,7 @@ stage1d_batch_kernel(const StageArgs* targs, const int2* tiles, int ntiles) {
     if ((int)blockIdx.x >= ntiles) return;
     const int IMEXLB_CONST* tp = (const int IMEXLB_CONST*)tiles + 2 * blockIdx.x;
     CArgs& a = ((CArgs*)targs)[tp[0]];
-    stage1d_body<S, KIND, QM, TX>(a, tp[1], tile);
+    stage1d_tile<S, KIND, QM, TX>(a, tp[1], tile);
 }
 
 // ---------------------------------------------------------------------------
