@@ -50,19 +50,20 @@ __device__ __forceinline__ void mp9_line(const R (&w)[L + 9], R (&dif)[L]) {
         for (int k = 0; k < 8; ++k) dd[k] = d[i + k];
         fl[i] = mp9_face_linear<R>(dd, w[i + 4], t[i], q[i]);
     }
-    // keep every linear part ahead of the first branch
+    // one branch for the whole line, skipped by every wavefront none of whose
+    // lanes needs a clip (the common case in smooth regions); inside it each
+    // face takes its clipped value where its test fails
+    bool any = false;
 #pragma unroll
-    for (int i = 0; i <= L; ++i) {
-        opaque(fl[i]);
-        opaque(q[i]);
-    }
+    for (int i = 0; i <= L; ++i) any |= q[i] > R(0);
+    if (any) {
 #pragma unroll
-    for (int i = 0; i <= L; ++i) {
-        if (q[i] > R(0)) {
+        for (int i = 0; i <= L; ++i) {
             R dd[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) dd[k] = d[i + k];
-            fl[i] = mp9_face_clip<R>(dd, w[i + 4], w[i + 5], t[i], fl[i]);
+            const R c = mp9_face_clip<R>(dd, w[i + 4], w[i + 5], t[i], fl[i]);
+            fl[i] = q[i] > R(0) ? c : fl[i];
         }
     }
 #pragma unroll
