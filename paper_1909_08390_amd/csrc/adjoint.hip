@@ -482,7 +482,9 @@ __global__ void __launch_bounds__(kAdjBlock) materialise_kernel(const DevTables*
 }
 
 // dM = (dE/dM)^T dE per cell, dE = sum_j c_j Y_j.  Moments (n, u, T) of M.
-template <int D>
+// The x factors (and their u and T derivatives) of the QM or fewer nodes of
+// a set are evaluated once per cell and set, then reused by every y group.
+template <int D, int QM>
 __global__ void __launch_bounds__(kAdjBlock) eq_adjoint_kernel(const DevTables* __restrict__ tabp,
                                                                const double* __restrict__ M, Lin4 dE,
                                                                double* dM, long long cells, double chi_fac) {
@@ -498,18 +500,28 @@ __global__ void __launch_bounds__(kAdjBlock) eq_adjoint_kernel(const DevTables* 
         const double pre = set ? chi_fac * nn * T : nn;       // P_phi = n, P_chi = (K+D-d) n T
         const double pre_n = set ? chi_fac * T : 1.0;
         const double pre_T = set ? chi_fac * nn : 0.0;
+        double gx[QM], gxu[QM], gxT[QM];
+#pragma unroll
+        for (int kx = 0; kx < QM; ++kx) {
+            gx[kx] = 0.0;
+            gxu[kx] = 0.0;
+            gxT[kx] = 0.0;
+            if (kx < Q) herm_factor_d(tab->h[set][kx], Q, u, th, gx[kx], gxu[kx], gxT[kx]);
+        }
         for (int ky = 0; ky < (D == 2 ? Q : 1); ++ky) {
             double gy = 1.0, gyu = 0.0, gyT = 0.0;
             if (D == 2) herm_factor_d(tab->h[set][ky], Q, w, th, gy, gyu, gyT);
-            for (int kx = 0; kx < Q; ++kx, ++v) {
-                double gx, gxu, gxT;
-                herm_factor_d(tab->h[set][kx], Q, u, th, gx, gxu, gxT);
-                const double e = lin_at(dE, (size_t)v * cells + c);
-                dn = fma(e, pre_n * gx * gy, dn);
-                dux = fma(e, pre * gxu * gy, dux);
-                if (D == 2) duy = fma(e, pre * gx * gyu, duy);
-                dT = fma(e, pre_T * gx * gy + pre * (gxT * gy + gx * gyT), dT);
+#pragma unroll
+            for (int kx = 0; kx < QM; ++kx) {
+                if (kx < Q) {
+                    const double e = lin_at(dE, (size_t)(v + kx) * cells + c);
+                    dn = fma(e, pre_n * gx[kx] * gy, dn);
+                    dux = fma(e, pre * gxu[kx] * gy, dux);
+                    if (D == 2) duy = fma(e, pre * gx[kx] * gyu, duy);
+                    dT = fma(e, pre_T * gx[kx] * gy + pre * (gxT[kx] * gy + gx[kx] * gyT), dT);
+                }
             }
+            v += Q;
         }
     }
     dM[c] = dn;
@@ -616,12 +628,18 @@ hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const
     return hipGetLastError();
 }
 
-hipError_t launch_eq_adjoint(int d, const DevTables* tab, const double* M, int ny_in, const double* const* y,
-                             const double* cf, double* dM, long long cells, double chi_fac, hipStream_t s) {
+hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, int ny_in,
+                             const double* const* y, const double* cf, double* dM, long long cells,
+                             double chi_fac, hipStream_t s) {
     const Lin4 L = make_lin(ny_in, y, cf);
     const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
-    if (d == 2) hipLaunchKernelGGL((eq_adjoint_kernel<2>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
-    else hipLaunchKernelGGL((eq_adjoint_kernel<1>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
+    if (d == 2) {
+        if (qm == 8) hipLaunchKernelGGL((eq_adjoint_kernel<2, 8>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
+        else hipLaunchKernelGGL((eq_adjoint_kernel<2, 16>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
+    } else {
+        if (qm == 8) hipLaunchKernelGGL((eq_adjoint_kernel<1, 8>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
+        else hipLaunchKernelGGL((eq_adjoint_kernel<1, 16>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
+    }
     return hipGetLastError();
 }
 

@@ -149,8 +149,9 @@ hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const
                                  const double* const* y, const double* cf, double* out, int nx, int ny,
                                  int bcx, int bcy, double inv_dx, double inv_dy, bool accumulate,
                                  hipStream_t s);
-hipError_t launch_eq_adjoint(int d, const DevTables* tab, const double* M, int ny_in, const double* const* y,
-                             const double* cf, double* dM, long long cells, double chi_fac, hipStream_t s);
+hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, int ny_in,
+                             const double* const* y, const double* cf, double* dM, long long cells,
+                             double chi_fac, hipStream_t s);
 hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, const double* dM, int ny_in,
                               const double* const* y, const double* cf, double* out, long long cells,
                               double dk, bool accumulate, hipStream_t s);

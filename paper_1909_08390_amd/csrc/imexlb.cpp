@@ -797,13 +797,14 @@ imexlb_status imexlb_adjoint_step(imexlb_ctx* c, const void* Fn, const double* l
     const double ka = 0.5 - be - et - kAlpha;
     const int np = c->nplanes, nx = c->cfg.nx, ny = d == 2 ? c->cfg.ny : 1;
     const double idx = a.inv_dx, idy = a.inv_dy;
+    const int qm = a.qm;
     auto adv = [&](const double* F, std::initializer_list<const double*> ys, std::initializer_list<double> cs,
                    double* out) {
         return launch_advect_adjoint(d, c->d_tab, np, F, (int)ys.size(), ys.begin(), cs.begin(), out, nx, ny,
                                      c->cfg.bc_x, c->cfg.bc_y, idx, idy, false, s);
     };
     auto eqt = [&](const double* M, std::initializer_list<const double*> ys, std::initializer_list<double> cs) {
-        return launch_eq_adjoint(d, c->d_tab, M, (int)ys.size(), ys.begin(), cs.begin(), dM, cells, chi, s);
+        return launch_eq_adjoint(d, qm, c->d_tab, M, (int)ys.size(), ys.begin(), cs.begin(), dM, cells, chi, s);
     };
     auto momt = [&](const double* M, std::initializer_list<const double*> ys, std::initializer_list<double> cs,
                     double* out) {
@@ -890,7 +891,7 @@ imexlb_status imexlb_equilibrium_adjoint(imexlb_ctx* c, const double* n, const d
     const double* ys[1] = {lam};
     const double cs[1] = {1.0};
     if (e == hipSuccess)
-        e = launch_eq_adjoint(d, c->d_tab, M, 1, ys, cs, dM, cells, (double)(c->cfg.K + kDTotal - d), s);
+        e = launch_eq_adjoint(d, base_args(c).qm, c->d_tab, M, 1, ys, cs, dM, cells, (double)(c->cfg.K + kDTotal - d), s);
     double* dst[4] = {dn, dux, d == 2 ? duy : dT, dT};
     for (int f = 0; f < c->nf && e == hipSuccess; ++f)
         e = hipMemcpyAsync(dst[f], dM + (size_t)f * cells, fb, hipMemcpyDeviceToDevice, s);
