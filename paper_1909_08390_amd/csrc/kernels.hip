@@ -126,22 +126,28 @@ __device__ __forceinline__ void bload2(Rsrc r, int off, double* o) {
     }
 }
 
-template <typename S>
+// Cache policy of a store (the buffer intrinsics' last operand): 0 is the
+// default; kStreamStore (sc1 | nt on gfx950) marks data that the pass does
+// not read again, so that it leaves the L2 early and the halo lines the
+// neighbouring tiles still read stay.
+constexpr int kStreamStore = 16 | 2;
+
+template <typename S, int POL = 0>
 __device__ __forceinline__ void bstore1(Rsrc r, int off, S v) {
     if constexpr (sizeof(S) == 8)
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, POL);
     else
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, POL);
 }
 
-template <typename S>
+template <typename S, int POL = 0>
 __device__ __forceinline__ void bstore2(Rsrc r, int off, const S* v) {
     if constexpr (sizeof(S) == 8) {
         const double2 x = {v[0], v[1]};
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), r, off, 0, POL);
     } else {
         const float2 x = {v[0], v[1]};
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, off, 0, POL);
     }
 }
 
@@ -266,8 +272,8 @@ __device__ __forceinline__ void bload_own(Rsrc r, int off, double* o) {
 
 template <typename S, int OWN>
 __device__ __forceinline__ void bstore_own(Rsrc r, int off, const S* v) {
-    if constexpr (OWN == 2) bstore2<S>(r, off, v);
-    else bstore1<S>(r, off, v[0]);
+    if constexpr (OWN == 2) bstore2<S, kStreamStore>(r, off, v);
+    else bstore1<S, kStreamStore>(r, off, v[0]);
 }
 
 // Tile visiting order: patch rows of kPatchH tile rows (the last one may be
@@ -735,7 +741,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
             } else {
 #pragma unroll
                 for (int i = 0; i < OWN; ++i)
-                    if (row_real && ox0 + i < nx) bstore1<S>(ro, own_off + i * (int)sizeof(S), outv[i]);
+                    if (row_real && ox0 + i < nx) bstore1<S, kStreamStore>(ro, own_off + i * (int)sizeof(S), outv[i]);
             }
             if constexpr (KIND == kStage4) {
                 const Rsrc rf = plane_rsrc(static_cast<S*>(a.fbuf) + plane_off(st.v), ps);
@@ -744,7 +750,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                 } else {
 #pragma unroll
                     for (int i = 0; i < OWN; ++i)
-                        if (row_real && ox0 + i < nx) bstore1<S>(rf, own_off + i * (int)sizeof(S), fbv[i]);
+                        if (row_real && ox0 + i < nx) bstore1<S, kStreamStore>(rf, own_off + i * (int)sizeof(S), fbv[i]);
                 }
             }
             if (st.set() == 0) {
