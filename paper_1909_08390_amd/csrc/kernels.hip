@@ -104,33 +104,36 @@ __device__ __forceinline__ Rsrc plane_rsrc(const S* p, long long cells) {
                                              kRawBufferWord3);
 }
 
-template <typename S>
+// Cache policy of a load or store (the buffer intrinsics' last operand): 0
+// is the default.  Data that the pass touches once and no neighbouring tile
+// reads (the own cells of the state buffer, the output planes) take the
+// streaming policies, so that it leaves the L2 early and the halo lines the
+// neighbouring tiles still read stay: kStreamLoad = nt, kStreamStore =
+// sc1 | nt (gfx950 encodings).
+constexpr int kStreamLoad = 2;
+constexpr int kStreamStore = 16 | 2;
+
+template <typename S, int POL = 0>
 __device__ __forceinline__ double bload1(Rsrc r, int off) {
     if constexpr (sizeof(S) == 8)
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, POL));
     else
-        return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+        return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, POL));
 }
 
 // Two consecutive elements as one access.
-template <typename S>
+template <typename S, int POL = 0>
 __device__ __forceinline__ void bload2(Rsrc r, int off, double* o) {
     if constexpr (sizeof(S) == 8) {
-        const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+        const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, POL));
         o[0] = v.x;
         o[1] = v.y;
     } else {
-        const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, POL));
         o[0] = v.x;
         o[1] = v.y;
     }
 }
-
-// Cache policy of a store (the buffer intrinsics' last operand): 0 is the
-// default; kStreamStore (sc1 | nt on gfx950) marks data that the pass does
-// not read again, so that it leaves the L2 early and the halo lines the
-// neighbouring tiles still read stay.
-constexpr int kStreamStore = 16 | 2;
 
 template <typename S, int POL = 0>
 __device__ __forceinline__ void bstore1(Rsrc r, int off, S v) {
@@ -264,10 +267,10 @@ __device__ __forceinline__ CDp hrow(CTab* t, int set, int k) {
 }
 
 // The own cells of a thread (one or two) as one access.
-template <typename S, int OWN>
+template <typename S, int OWN, int POL = 0>
 __device__ __forceinline__ void bload_own(Rsrc r, int off, double* o) {
-    if constexpr (OWN == 2) bload2<S>(r, off, o);
-    else o[0] = bload1<S>(r, off);
+    if constexpr (OWN == 2) bload2<S, POL>(r, off, o);
+    else o[0] = bload1<S, POL>(r, off);
 }
 
 template <typename S, int OWN>
@@ -491,10 +494,10 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
         if constexpr (KIND == kStage4 || KIND == kStage5) {
             const Rsrc rf = plane_rsrc(static_cast<const S*>(a.fbuf) + plane_off(v), recs);
             if constexpr (VEC) {
-                bload_own<S, OWN>(rf, boff[0], pf);
+                bload_own<S, OWN, kStreamLoad>(rf, boff[0], pf);
             } else {
 #pragma unroll
-                for (int i = 0; i < OWN; ++i) pf[i] = bload1<S>(rf, boff[i]);
+                for (int i = 0; i < OWN; ++i) pf[i] = bload1<S, kStreamLoad>(rf, boff[i]);
             }
         }
     };
