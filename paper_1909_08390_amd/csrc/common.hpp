@@ -43,9 +43,10 @@ struct HornerLayout {
     static constexpr int total() { return off(S + 1); }
 };
 
-// One entry of the plane processing order of the 2D stage passes: planes
-// run set by set, ky-major, with each x-node followed by its mirror so that
-// one Horner evaluation serves both.
+// One entry of the plane processing order of the stage passes: planes run
+// set by set, ky-major (in x-factor table groups for 2D FP32 storage), with
+// each x-node followed by its mirror so that one Horner evaluation serves
+// both.
 struct PlaneStep {
     double px, py;            // velocity of the plane
     double m0, mx, my, me;    // moment weights (as in PlaneDesc)
@@ -57,7 +58,6 @@ struct PlaneStep {
     int hy;                   // node whose Horner row evaluates (ky, mirror)
     int new_group;            // 1: ky (or the set) changed -> y factor changes
     int yfirst;               // 1: evaluate the y pair now; 0: use the cached mirror
-    int new_set;              // 1: first step of a set
     int new_tab;              // 1: first step of an x-factor table group (tables rebuilt)
     int tcount;               // mirror pairs in the table group (2D, orders up to 8)
     int slot;                 // table slot of kx within its group

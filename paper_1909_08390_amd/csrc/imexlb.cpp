@@ -192,7 +192,6 @@ hipError_t upload_tables(int d, const int Q[2], const double p[2][kQMax], const 
             const int nyg = d == 2 ? Q[s] : 1;
             const int npairs = (Q[s] + 1) / 2;
             const int gpairs = grouped ? std::max(1, tab_nodes / 2) : npairs;
-            bool set_start = true;
             for (int k0 = 0; k0 < npairs; k0 += gpairs) {
                 const int kend = std::min(npairs, k0 + gpairs);
                 bool tab_start = true;
@@ -217,12 +216,10 @@ hipError_t upload_tables(int d, const int Q[2], const double p[2][kQMax], const 
                                 st.hy = ly;
                                 st.new_group = group_start;
                                 st.yfirst = group_start && ey == 0;
-                                st.new_set = set_start;
                                 st.new_tab = tab_start;
                                 st.tcount = grouped ? kend - k0 : 0;
                                 st.slot = grouped ? 2 * (k - k0) + e : 0;
                                 group_start = false;
-                                set_start = false;
                                 tab_start = false;
                             }
                         }
