@@ -299,7 +299,7 @@ __device__ __forceinline__ void adj_stream(const double* F, const Lin4& dA, size
     };
     auto emit = [&](int t, double val) {
         const size_t o = base + (size_t)t * st;
-        out[o] = accumulate ? out[o] + val : val;
+        __builtin_nontemporal_store(accumulate ? out[o] + val : val, out + o);
     };
     double w[9], r[9];
 #pragma unroll
@@ -370,6 +370,7 @@ __global__ void __launch_bounds__(64) advect_adjoint_xchunk_kernel(const DevTabl
                                                                    double* out, int nx, int ny, int bc,
                                                                    double inv_dx, int accumulate) {
     __shared__ double contrib[9 * 64];
+    __shared__ double sF[72], sA[72];  // F at nodes c0-8 .. c0+63, dA at c0-5 .. c0+66
     CTab* tab = (CTab*)tabp;
     const long long cells = (long long)nx * ny;
     const int v = blockIdx.y;
@@ -385,15 +386,23 @@ __global__ void __launch_bounds__(64) advect_adjoint_xchunk_kernel(const DevTabl
         return;
     }
     const bool fwd = p > 0.0;
-    const int s = c0 - (fwd ? 4 : 5) + lane;
-    double w[9];
-#pragma unroll
-    for (int kk = 0; kk < 9; ++kk) w[kk] = F[base + bc_map(fwd ? s - 4 + kk : s + 5 - kk, n, bc)];
+    // the chunk's windows, read once into LDS (coalesced)
     auto dat = [&](int j) {
         if (bc == 1) return lin_at(dA, base + (size_t)bc_map(j, n, 1));
         return (j >= 0 && j < n) ? lin_at(dA, base + (size_t)j) : 0.0;
     };
-    const double dface = p * inv_dx * (dat(s) - dat(s + 1));
+    for (int i = lane; i < 72; i += 64) {
+        sF[i] = F[base + bc_map(c0 - 8 + i, n, bc)];
+        sA[i] = dat(c0 - 5 + i);
+    }
+    __syncthreads();
+    // face s = c0 - 4 + lane (flow to +x) or c0 - 5 + lane: window nodes
+    // s - 4 + kk = c0 - 8 + lane + kk, or s + 5 - kk = c0 + lane - kk
+    double w[9];
+#pragma unroll
+    for (int kk = 0; kk < 9; ++kk) w[kk] = sF[fwd ? lane + kk : lane + 8 - kk];
+    const int ia = lane + (fwd ? 1 : 0);  // sA index of node s
+    const double dface = p * inv_dx * (sA[ia] - sA[ia + 1]);
     double J[9];
     face_jacobian_row(w, J);
 #pragma unroll
@@ -411,7 +420,7 @@ __global__ void __launch_bounds__(64) advect_adjoint_xchunk_kernel(const DevTabl
                 }
         }
         const size_t o = base + (size_t)t;
-        out[o] = accumulate ? out[o] + val : val;
+        __builtin_nontemporal_store(accumulate ? out[o] + val : val, out + o);
     }
 }
 
