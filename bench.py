@@ -147,6 +147,22 @@ def run_precision(I, W, N, storage, steps, warmup, seed):
     return res, cfg, fields
 
 
+COPY_PROBE_BYTES = 4 << 30
+
+
+def hbm_copy_rate(I):
+    """Achievable HBM rate: best of 8 plain 4 GiB device copies (GB/s, read
+    plus written) by the library's copy probe."""
+    import torch
+
+    src = torch.empty(COPY_PROBE_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    gbs = I.copy_probe(src, dst, 8)
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def fp32_error(m32, m64):
     """Errors of the FP32-storage run against the FP64 run after the same
     steps: density and pressure relative (L1 over the grid and max), velocity
@@ -269,6 +285,53 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, size, cmds):
         alg = pass_bytes(128, cells, 4 if prec == "f32" else 8, 4)[stage]
         print(f"pass {prec} {stage}: fetch_kib={fetch[k]:.1f} write_kib={write[k]:.1f} "
               f"traffic_bytes={t:.4e} algorithmic_bytes={alg:.4e} ratio={t / alg:.3f}")
+
+
+INST_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_SMEM",
+                 "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_BRANCH", "GRBM_GUI_ACTIVE")
+
+
+def summarize_insts(d, size, cmds):
+    """Instruction mix of the stage passes from one --pmc run of
+    INST_COUNTERS: lane-instructions per velocity node (wave instructions x
+    64 / VN) and the VALU floor of each pass, one wave64 VALU instruction per
+    4 cycles per SIMD on 1024 SIMDs at 2.4 GHz, against the dispatch time."""
+    vals = {c: {} for c in INST_COUNTERS}
+    span = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                c = r["Counter_Name"]
+                if c not in vals:
+                    continue
+                key = (r["Kernel_Name"], r["Dispatch_Id"])
+                vals[c][key] = vals[c].get(key, 0.0) + float(r["Counter_Value"])
+                span[key] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+    vn = size * size * 128
+    print("# Instruction mix of the stage passes, 2D Riemann workload, "
+          f"{size}x{size} cells x 128 planes (one dispatch per pass and storage type)")
+    for c in cmds:
+        print(f"# command: {c}")
+    print(f"source_sha256: {kernel_source_hash()}")
+    print("# per_vn: wave instructions x 64 / velocity nodes; valu_floor_ms: SQ_INSTS_VALU x 4 cycles "
+          "/ (1024 SIMDs x 2.4 GHz); valu_frac = valu_floor_ms / dispatch_ms; gui_clock_ghz: "
+          "GRBM_GUI_ACTIVE (summed over the 8 XCDs) / 8 / dispatch time, the clock the pass ran at")
+    rows = {}
+    for (name, disp), v in vals["SQ_INSTS_VALU"].items():
+        key = _kernel_key(name)
+        if key is None:
+            continue
+        rows[key] = (name, disp)
+    for key in sorted(rows):
+        k = rows[key]
+        g = {c: vals[c].get(k, float("nan")) for c in INST_COUNTERS}
+        per = {c: g[c] * 64.0 / vn for c in INST_COUNTERS[1:-1]}
+        floor_ms = g["SQ_INSTS_VALU"] * 4.0 / (1024 * 2.4e9) * 1e3
+        print(f"pass {key[0]} {key[1]}: dispatch_ms={span[k]:.3f} waves={g['SQ_WAVES']:.0f} "
+              + " ".join(f"{c[9:].lower()}_per_vn={per[c]:.2f}" for c in per)
+              + f" gui_active_cycles={g['GRBM_GUI_ACTIVE']:.4e} "
+              f"gui_clock_ghz={g['GRBM_GUI_ACTIVE'] / 8 / (span[k] * 1e6):.2f} "
+              f"valu_floor_ms={floor_ms:.3f} valu_frac={floor_ms / span[k]:.3f}")
 
 
 def batch_pass_bytes(vn, elem):
@@ -417,6 +480,8 @@ def main():
                     help="print a summary of rocprofv3 --stats CSVs and exit")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the HBM traffic summary of two --pmc runs and exit")
+    ap.add_argument("--summarize-insts", metavar="DIR",
+                    help="print the instruction-mix summary of a --pmc run of INST_COUNTERS and exit")
     ap.add_argument("--cmd", action="append", default=[],
                     help="command line recorded in a summary")
     ap.add_argument("--workload", choices=["riemann2d", "batch", "adjoint"], default="riemann2d",
@@ -430,6 +495,9 @@ def main():
 
     if args.summarize_stats:
         summarize_stats(args.summarize_stats, " ; ".join(args.cmd))
+        return
+    if args.summarize_insts:
+        summarize_insts(args.summarize_insts, args.size, args.cmd)
         return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.copy_calib, args.size,
@@ -464,6 +532,8 @@ def main():
         log("bench: FP32 storage run")
         r32, _, _ = run_precision(I, W, args.size, I.F32, args.steps, args.warmup, args.seed)
         log(f"bench: FP32 {r32['value']:.3e} VN/s, {r32['ms_per_step']:.2f} ms/step, passes {r32['pass_ms']}")
+    copy_gbs = hbm_copy_rate(I)
+    log(f"bench: plain device copy {copy_gbs:.0f} GB/s")
     cpu = None
     if not args.no_cpu:
         import oracle as O
@@ -495,6 +565,11 @@ def main():
         "pass_ms": r64["pass_ms"],
         "bytes_per_vn_step": r64["bytes_per_vn_step"],
         "step_hbm_frac": r64["step_gbs"] / HBM_PEAK_GBS,
+        "hbm_copy": {"gbs": copy_gbs, "frac_of_peak": copy_gbs / HBM_PEAK_GBS,
+                     "bytes": COPY_PROBE_BYTES, "reps": 8,
+                     "kernel": "imexlb_copy_probe: one 16-byte load and store per thread",
+                     "stage4_frac_of_copy": r64["roofline"]["achieved"] / copy_gbs,
+                     "step_frac_of_copy": r64["step_gbs"] / copy_gbs},
         "cpu_baseline": cpu,
     }
     if r32 is not None:

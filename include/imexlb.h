@@ -274,6 +274,22 @@ imexlb_status imexlb_batch_tune(imexlb_batch* b, int nsteps, double* ms_out);
 
 const char* imexlb_batch_last_error(const imexlb_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Measurement helper (not a step of the method).
+ *
+ * Achievable HBM rate of a plain device copy: the practical ceiling that the
+ * bandwidth of the stage passes is set against, next to the spec-sheet peak.
+ * Copies `bytes` from d_src to d_dst (device memory owned by the caller,
+ * 16-byte aligned, not overlapping; bytes a positive multiple of 16, at most
+ * 2^40) once untimed and then `reps` times on hip_stream (NULL: the null
+ * stream), one 16-byte load and store per thread, each copy timed with HIP
+ * events, and writes the best rate in GB/s (bytes read plus bytes written,
+ * per second) to *gbs (host).  d_dst ends up equal to d_src.  Synchronises.
+ * IMEXLB_EINVAL for NULL or misaligned pointers, a bad size or reps < 1
+ * (checked before any HIP call); IMEXLB_EHIP for a HIP failure. */
+imexlb_status imexlb_copy_probe(const void* d_src, void* d_dst, size_t bytes, int reps,
+                                void* hip_stream, double* gbs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,8 +115,27 @@ def lib():
         L.imexlb_batch_tune.argtypes = [_vp, ctypes.c_int, _dp]
         L.imexlb_batch_last_error.argtypes = [_vp]
         L.imexlb_batch_last_error.restype = ctypes.c_char_p
+        L.imexlb_copy_probe.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp, _dp]
         _lib = L
     return _lib
+
+
+def copy_probe(src, dst, reps: int = 8) -> float:
+    """Best rate in GB/s (read + written) of ``reps`` plain device copies of
+    ``src`` into ``dst`` (contiguous CUDA tensors of one size in bytes, a
+    multiple of 16) on torch's current stream: the achievable HBM rate that
+    the stage passes are compared with.  ``imexlb_copy_probe``."""
+    import torch
+
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("copy_probe: src and dst must be contiguous and of the same size")
+    out = ctypes.c_double(0.0)
+    st = lib().imexlb_copy_probe(_vp(src.data_ptr()), _vp(dst.data_ptr()), nbytes, reps,
+                                 _vp(torch.cuda.current_stream().cuda_stream), ctypes.byref(out))
+    if st != OK:
+        raise ImexlbError(st, lib().imexlb_status_string(st).decode())
+    return out.value
 
 
 @dataclass

@@ -1,5 +1,6 @@
 """The C-ABI library loads, exports every declared entry point, and rejects
 invalid configurations before touching a device (runs without a GPU)."""
+import ctypes
 import os
 import re
 
@@ -70,6 +71,13 @@ def test_null_arguments():
     assert L.imexlb_create(None, None, None) == I.EINVAL
     assert L.imexlb_step(None, 1) == I.EINVAL
     assert L.imexlb_bind(None, None, None) == I.EINVAL
+
+
+def test_copy_probe_rejects_null_arguments():
+    L = I.lib()
+    out = ctypes.c_double(0.0)
+    assert L.imexlb_copy_probe(None, None, 64, 1, None, ctypes.byref(out)) == I.EINVAL
+    assert L.imexlb_copy_probe(None, None, 64, 1, None, None) == I.EINVAL
 
 
 BAD_TUBES = [
