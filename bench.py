@@ -257,7 +257,9 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, size, cmds):
     fetch_d = _pmc_dispatches(fetch_dir, "FETCH_SIZE")
     write_d = _pmc_dispatches(write_dir, "WRITE_SIZE")
     cb = copy_mib * (1 << 20)
-    copies = [k for k in fetch_d if "copy" in k.lower() and k in write_d]
+    # the runtime's copy kernel (torch copy_ of copy_mib MiB), not the
+    # library's copy probe, which the same run launches on 4 GiB
+    copies = [k for k in fetch_d if "copybuffer" in k.lower() and k in write_d]
     ck = max(copies, key=lambda k: max(fetch_d[k]))
     cf, nf = _calib(fetch_d[ck])
     cw, nw = _calib(write_d[ck])

@@ -193,8 +193,9 @@ constexpr int kBatchTiles[3] = {256, 512, 1024};
 #endif
 constexpr int kPatchW = IMEXLB_PATCH_W, kPatchH = IMEXLB_PATCH_H;
 // Nodes per x-factor table group of the 2D plane order (orders up to 8):
-// FP32 storage takes two mirror pairs per group (the kernels keep 4 tables
-// of one double per loaded cell in LDS), FP64 storage a whole set (8).
-constexpr int tab_nodes_2d(bool f32) { return f32 ? 4 : 8; }
+// two mirror pairs, i.e. 4 tables of one double per loaded cell in LDS
+// (31 KB), small enough to sit next to the two LDS tiles of the pipelined
+// and mirror-pair plane loops with two work-groups per compute unit.
+constexpr int kTabNodes2D = 4;
 
 }  // namespace imexlb

@@ -455,7 +455,7 @@ imexlb_status imexlb_create(const imexlb_config* cfg, void* hip_stream, imexlb_c
     c->cells = (long long)cfg->nx * c->cfg.ny;
     c->elem = cfg->storage == IMEXLB_F32 ? 4 : 8;
 
-    hipError_t e = upload_tables(d, Q, c->p, c->w, tab_nodes_2d(c->elem == 4), &c->d_tab, c->stream);
+    hipError_t e = upload_tables(d, Q, c->p, c->w, kTabNodes2D, &c->d_tab, c->stream);
     if (e == hipErrorOutOfMemory) {
         delete c;
         return IMEXLB_ENOMEM;

@@ -309,15 +309,15 @@ __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& 
 //    over L = 2 OWN cells of a row, the second half along y over L cells of
 //    a column;
 //  - x factors (orders up to 8) from LDS tables of one table group of the
-//    plane order (tab_nodes_2d nodes: mirror pairs), built when a group
-//    starts, or, in the mirror-pair loop, from one Horner evaluation per
-//    loaded cell for both planes of a pair;
+//    plane order (kTabNodes2D nodes: two mirror pairs), built when a group
+//    starts; above order 8 from one Horner evaluation per loaded cell for a
+//    node and its mirror;
 //  - three plane loops (Stage2DShape): the software pipeline (FP32 passes 3
-//    and 5: sweep plane j and relax plane j + 1 into the other of two LDS
-//    tiles, the loads of plane j + 2 in flight, one barrier, pointwise step
-//    of plane j), the mirror-pair loop (FP64 pass 3 of even orders: both
-//    planes of an x-mirror pair per iteration) and the plain loop (relax,
-//    barrier, sweeps, barrier, pointwise).
+//    and 5, FP64 pass 5: sweep plane j and relax plane j + 1 into the other
+//    of two LDS tiles, the loads of plane j + 2 in flight, one barrier,
+//    pointwise step of plane j), the mirror-pair loop (FP64 pass 3 of even
+//    orders: both planes of an x-mirror pair per iteration) and the plain
+//    loop (relax, barrier, sweeps, barrier, pointwise).
 // LDS pitches are odd so the row-strided x windows and the column-strided
 // results spread over all banks.
 // ---------------------------------------------------------------------------
@@ -331,17 +331,17 @@ struct Stage2DShape {
     static constexpr int HS = (NH + NT - 1) / NT;
     static constexpr int NS = OWN + HS;
     static constexpr bool RELAX = KIND != kAdvect;
-    static constexpr bool TAB = RELAX && (QM == 8) && !PAIR;
+    static constexpr bool TAB = RELAX && (QM == 8);
     static constexpr int NLOAD = TX * TY + NH;
     // x-factor table nodes: the table groups of the plane order built by the
-    // host for this storage type
-    static constexpr int TABN = tab_nodes_2d(sizeof(S) == 4);
+    // host
+    static constexpr int TABN = kTabNodes2D;
     // software-pipelined plane loop (double-buffered LDS tile and flux
-    // buffers) for FP32 storage; stage 4, whose registers are already full
-    // with the E^n factors of its own cells, and FP64 storage, whose tiles
-    // would not leave room for two work-groups per compute unit next to the
-    // full x-factor tables, keep the two-barrier loop
-    static constexpr bool PIPE = KIND != kStage4 && sizeof(S) == 4 && !PAIR;
+    // buffers) for passes 3 and 5 of FP32 storage and pass 5 of FP64 (FP64
+    // pass 3 takes the mirror-pair loop); stage 4, whose registers are
+    // already full with the E^n factors of its own cells, keeps the
+    // two-barrier loop
+    static constexpr bool PIPE = KIND != kStage4 && (sizeof(S) == 4 || KIND == kStage5) && !PAIR;
     static constexpr int NBUF = (PIPE || PAIR) ? 2 : 1;
     // waves per SIMD the register budget aims at: two work-groups per
     // compute unit
@@ -788,10 +788,10 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
         // Planes in x-mirror pairs (kx, ky), (Q - 1 - kx, ky), consecutive in
         // the plane order (even orders): both planes of a pair per iteration,
         // their global loads issued together one iteration ahead (fixed
-        // register sets A and B), one Horner evaluation per loaded cell for
-        // the x factors of both (no LDS tables), relax both into two tiles,
-        // barrier, sweep both into two pairs of flux buffers, barrier,
-        // pointwise steps of both.
+        // register sets A and B), x factors of both from the LDS tables (or,
+        // above order 8, from one Horner evaluation per loaded cell), relax
+        // both into two tiles, barrier, sweep both into two pairs of flux
+        // buffers, barrier, pointwise steps of both.
         double pgB[NS], pfB[OWN], bB[NB][OWN];
         fetch_to(pgB, pfB, s1.v, true);
         for (int j = 0;; j += 2) {
@@ -1346,8 +1346,8 @@ hipError_t launch_stage_t(int d, const StageArgs& a, hipStream_t s) {
     if (d == 2) {
         constexpr int TY = kTile2Y, OWN = kOwn2;
         constexpr int NT = kTile2X * TY / OWN;
-        // FP64 stage 3 of even orders takes the mirror-pair loop (stage 5,
-        // with twice its memory traffic, gains nothing from it)
+        // FP64 stage 3 of even orders takes the mirror-pair loop (stage 5 is
+        // as fast in the software pipeline, which needs no pairing)
         constexpr bool CAN_PAIR = sizeof(S) == 8 && KIND == kStage3 && OWN == 2;
         if constexpr (CAN_PAIR) {
             if (a.paired) {
