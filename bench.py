@@ -108,11 +108,17 @@ def run_precision(I, W, N, storage, steps, warmup, seed):
     s.set_equilibrium(*fields)
     if warmup:
         s.step(warmup)
+    # the timed steps in up to 5 repetitions of equal length (HIP-event
+    # time per step of each repetition reported beside the wall clock)
+    nrep = min(5, steps) if steps > 0 else 1
+    chunks = [steps // nrep + (1 if i < steps % nrep else 0) for i in range(nrep)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms = s.step_timed(steps)
+    reps = [s.step_timed(c) for c in chunks]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ms = sum(reps)
+    rep_ms = sorted(float(r.sum()) / c for r, c in zip(reps, chunks) if c > 0)
     ok = s.check_state()
     cells = N * N
     planes = cfg.planes
@@ -124,6 +130,8 @@ def run_precision(I, W, N, storage, steps, warmup, seed):
     res = {
         "value": vn,
         "ms_per_step": 1e3 * wall / steps,
+        "ms_per_step_reps": {"median": rep_ms[len(rep_ms) // 2], "min": rep_ms[0], "max": rep_ms[-1],
+                             "repetitions": len(rep_ms), "steps_each": chunks},
         "pass_ms": per,
         "pass_bytes": pb,
         "bytes_per_vn_step": step_bytes / (cells * planes),
@@ -148,14 +156,17 @@ def run_precision(I, W, N, storage, steps, warmup, seed):
 
 
 COPY_PROBE_BYTES = 4 << 30
+CACHE_PROBE_BYTES = 64 << 20
 
 
-def hbm_copy_rate(I):
-    """Achievable HBM rate: best of 8 plain 4 GiB device copies (GB/s, read
-    plus written) by the library's copy probe."""
+def hbm_copy_rate(I, nbytes=COPY_PROBE_BYTES):
+    """Achievable copy rate: best of 8 plain device copies of nbytes (GB/s,
+    read plus written) by the library's copy probe; 4 GiB measures HBM,
+    64 MiB (source and destination together inside the 256 MB last-level
+    cache) the cache."""
     import torch
 
-    src = torch.empty(COPY_PROBE_BYTES, dtype=torch.uint8, device="cuda")
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     gbs = I.copy_probe(src, dst, 8)
     del src, dst
@@ -376,6 +387,8 @@ def run_batch(args):
     per = {k: ms[i] / args.steps for i, k in enumerate(("stage3", "stage4", "stage5"))}
     gbs4 = pb["stage4"] / (per["stage4"] * 1e-3) / 1e9
     value = vn * args.steps / wall
+    cache_gbs = hbm_copy_rate(I, CACHE_PROBE_BYTES)
+    log(f"bench: 64 MiB device copy (cache-resident) {cache_gbs:.0f} GB/s")
     cpu = None
     if not args.no_cpu:
         import oracle as O
@@ -410,7 +423,8 @@ def run_batch(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs4 / HBM_PEAK_GBS,
                      "traffic": None, "algorithmic_bytes_per_launch": pb["stage4"],
                      "note": "working set (~%.0f MB) fits the 256 MB last-level cache"
-                             % ((b.state.numel() * elem * 3) / 1e6)},
+                             % ((b.state.numel() * elem * 3) / 1e6),
+                     "cache_copy_gbs": cache_gbs, "frac_of_cache_copy": gbs4 / cache_gbs},
         "pass_ms": per,
         "state_ok": ok,
         "cpu_baseline": cpu,
@@ -565,6 +579,7 @@ def main():
         },
         "roofline": r64["roofline"],
         "pass_ms": r64["pass_ms"],
+        "ms_per_step_reps": r64["ms_per_step_reps"],
         "bytes_per_vn_step": r64["bytes_per_vn_step"],
         "step_hbm_frac": r64["step_gbs"] / HBM_PEAK_GBS,
         "hbm_copy": {"gbs": copy_gbs, "frac_of_peak": copy_gbs / HBM_PEAK_GBS,
@@ -580,6 +595,7 @@ def main():
         out["fp32"] = {
             "value": r32["value"], "unit": "VN/s", "dtype": "f32 storage, f64 moments",
             "ms_per_step": r32["ms_per_step"], "pass_ms": r32["pass_ms"],
+            "ms_per_step_reps": r32["ms_per_step_reps"],
             "speedup_vs_fp64": r32["value"] / r64["value"],
             "bytes_per_vn_step": r32["bytes_per_vn_step"],
             "step_hbm_frac": r32["step_gbs"] / HBM_PEAK_GBS,
