@@ -118,7 +118,8 @@ def run_precision(I, W, N, storage, steps, warmup, seed):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = sum(reps)
-    rep_ms = sorted(float(r.sum()) / c for r, c in zip(reps, chunks) if c > 0)
+    rep_each = [float(r.sum()) / c for r, c in zip(reps, chunks) if c > 0]
+    rep_ms = sorted(rep_each)
     ok = s.check_state()
     cells = N * N
     planes = cfg.planes
@@ -131,7 +132,7 @@ def run_precision(I, W, N, storage, steps, warmup, seed):
         "value": vn,
         "ms_per_step": 1e3 * wall / steps,
         "ms_per_step_reps": {"median": rep_ms[len(rep_ms) // 2], "min": rep_ms[0], "max": rep_ms[-1],
-                             "repetitions": len(rep_ms), "steps_each": chunks},
+                             "each": rep_each, "steps_each": chunks},
         "pass_ms": per,
         "pass_bytes": pb,
         "bytes_per_vn_step": step_bytes / (cells * planes),
@@ -172,6 +173,24 @@ def hbm_copy_rate(I, nbytes=COPY_PROBE_BYTES):
     del src, dst
     torch.cuda.empty_cache()
     return gbs
+
+
+ALLOCATOR_WARMUP_BYTES = 64 << 30
+
+
+def allocator_warmup():
+    """Allocate and free one 64 GiB block before the workload's buffers.
+    On a freshly started GPU the first large allocation comes back with a
+    mapping under which the stage-4 pass runs about 7 % slower (14.6 instead
+    of 13.6 ms at 4096^2 in FP64, the same buffers staying slow for the life
+    of the process); every later allocation, in the same or another process,
+    runs at the steady-state speed.  The block is never touched."""
+    import torch
+
+    x = torch.empty(ALLOCATOR_WARMUP_BYTES, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    del x
+    torch.cuda.empty_cache()
 
 
 def fp32_error(m32, m64):
@@ -532,6 +551,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    allocator_warmup()
     if args.copy_calib:
         copy_calibration(args.copy_calib)
     if args.workload == "batch":
@@ -582,6 +602,7 @@ def main():
         "ms_per_step_reps": r64["ms_per_step_reps"],
         "bytes_per_vn_step": r64["bytes_per_vn_step"],
         "step_hbm_frac": r64["step_gbs"] / HBM_PEAK_GBS,
+        "allocator_warmup_bytes": ALLOCATOR_WARMUP_BYTES,
         "hbm_copy": {"gbs": copy_gbs, "frac_of_peak": copy_gbs / HBM_PEAK_GBS,
                      "bytes": COPY_PROBE_BYTES, "reps": 8,
                      "kernel": "imexlb_copy_probe: one 16-byte load and store per thread",
