@@ -312,12 +312,13 @@ __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& 
 //    plane order (kTabNodes2D nodes: two mirror pairs), built when a group
 //    starts; above order 8 from one Horner evaluation per loaded cell for a
 //    node and its mirror;
-//  - three plane loops (Stage2DShape): the software pipeline (FP32 passes 3
-//    and 5, FP64 pass 5: sweep plane j and relax plane j + 1 into the other
-//    of two LDS tiles, the loads of plane j + 2 in flight, one barrier,
-//    pointwise step of plane j), the mirror-pair loop (FP64 pass 3 of even
-//    orders: both planes of an x-mirror pair per iteration) and the plain
-//    loop (relax, barrier, sweeps, barrier, pointwise).
+//  - three plane loops (Stage2DShape): the mirror-pair loop (even orders:
+//    every FP32 pass and FP64 pass 3; both planes of an x-mirror pair per
+//    iteration), the software pipeline (FP64 pass 5, and FP32 passes 3 and
+//    5 of odd orders: sweep plane j and relax plane j + 1 into the other of
+//    two LDS tiles, the loads of plane j + 2 in flight, one barrier,
+//    pointwise step of plane j) and the plain loop (FP64 pass 4, FP32 pass
+//    4 of odd orders: relax, barrier, sweeps, barrier, pointwise).
 // LDS pitches are odd so the row-strided x windows and the column-strided
 // results spread over all banks.
 // ---------------------------------------------------------------------------
@@ -337,8 +338,8 @@ struct Stage2DShape {
     // host
     static constexpr int TABN = kTabNodes2D;
     // software-pipelined plane loop (double-buffered LDS tile and flux
-    // buffers) for passes 3 and 5 of FP32 storage and pass 5 of FP64 (FP64
-    // pass 3 takes the mirror-pair loop); stage 4, whose registers are
+    // buffers) for passes 3 and 5 of FP32 storage and pass 5 of FP64 where
+    // the mirror-pair loop is not taken; stage 4, whose registers are
     // already full with the E^n factors of its own cells, keeps the
     // two-barrier loop
     static constexpr bool PIPE = KIND != kStage4 && (sizeof(S) == 4 || KIND == kStage5) && !PAIR;
@@ -1346,9 +1347,11 @@ hipError_t launch_stage_t(int d, const StageArgs& a, hipStream_t s) {
     if (d == 2) {
         constexpr int TY = kTile2Y, OWN = kOwn2;
         constexpr int NT = kTile2X * TY / OWN;
-        // FP64 stage 3 of even orders takes the mirror-pair loop (stage 5 is
-        // as fast in the software pipeline, which needs no pairing)
-        constexpr bool CAN_PAIR = sizeof(S) == 8 && KIND == kStage3 && OWN == 2;
+        // Even orders take the mirror-pair loop for every FP32 pass and for
+        // FP64 stage 3 (FP64 stage 5 is as fast in the software pipeline,
+        // and FP64 stage 4 has no registers left for a second plane)
+        constexpr bool CAN_PAIR =
+            ((sizeof(S) == 8 && KIND == kStage3) || sizeof(S) == 4) && KIND != kAdvect && OWN == 2;
         if constexpr (CAN_PAIR) {
             if (a.paired) {
                 if (a.qm == 16)
