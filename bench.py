@@ -180,11 +180,10 @@ ALLOCATOR_WARMUP_BYTES = 64 << 30
 
 def allocator_warmup():
     """Allocate and free one 64 GiB block before the workload's buffers.
-    On a freshly started GPU the first large allocation comes back with a
-    mapping under which the stage-4 pass runs about 7 % slower (14.6 instead
-    of 13.6 ms at 4096^2 in FP64, the same buffers staying slow for the life
-    of the process); every later allocation, in the same or another process,
-    runs at the steady-state speed.  The block is never touched."""
+    The FP64 stage-4 pass at 4096^2 runs at 13.6 ms on some allocations of
+    its buffers and at 14.6 ms on others, for the life of the buffers; the
+    first large allocation on a freshly started GPU has always been a slow
+    one, and allocations after it mostly fast.  The block is never touched."""
     import torch
 
     x = torch.empty(ALLOCATOR_WARMUP_BYTES, dtype=torch.uint8, device="cuda")
