@@ -211,6 +211,20 @@ def fp32_error(m32, m64):
             "u": {"l1_abs": float(du.mean()), "max_abs": float(du.max())}}
 
 
+def host_cpu():
+    """CPU model and logical CPU count of the host that runs the oracle."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs on the host"
+
+
 def cpu_baseline(O, W, cfg, fields, side, steps):
     """The FP64 oracle on a side x side patch of the same workload (centre)."""
     N = cfg.nx
@@ -226,7 +240,8 @@ def cpu_baseline(O, W, cfg, fields, side, steps):
     vn = side * side * pc.planes * steps / dt
     return {"value": vn, "unit": "VN/s", "cores": 1, "kind": "oracle",
             "sample": f"{side}x{side} cells x 128 planes at the quadrant corner, {steps} "
-                      f"IMEX step(s), single-threaded C (-O2), {dt:.1f} s"}
+                      f"IMEX step(s), single-threaded C (-O2), {dt:.1f} s",
+            "host": host_cpu()}
 
 
 def _kernel_key(name):
@@ -426,7 +441,8 @@ def run_batch(args):
                 break
         cpu = {"value": vns / t_cpu, "unit": "VN/s", "cores": 1, "kind": "oracle",
                "sample": f"first {done} tubes of the batch (nx {used}), {args.cpu_steps} IMEX "
-                         f"steps each, single-threaded C (-O2), {t_cpu:.1f} s"}
+                         f"steps each, single-threaded C (-O2), {t_cpu:.1f} s",
+               "host": host_cpu()}
     out = {
         "metric": METRIC, "value": value, "unit": "VN/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
