@@ -338,10 +338,10 @@ struct Stage2DShape {
     // host
     static constexpr int TABN = kTabNodes2D;
     // software-pipelined plane loop (double-buffered LDS tile and flux
-    // buffers) for passes 3 and 5 of FP32 storage and pass 5 of FP64 where
-    // the mirror-pair loop is not taken; stage 4, whose registers are
-    // already full with the E^n factors of its own cells, keeps the
-    // two-barrier loop
+    // buffers) for FP64 pass 5 and for FP32 passes 3 and 5 without the
+    // mirror-pair loop (odd orders); stage 4, whose registers are already
+    // full with the E^n factors of its own cells, keeps the two-barrier loop
+    // when it does not pair
     static constexpr bool PIPE = KIND != kStage4 && (sizeof(S) == 4 || KIND == kStage5) && !PAIR;
     static constexpr int NBUF = (PIPE || PAIR) ? 2 : 1;
     // waves per SIMD the register budget aims at: two work-groups per
