@@ -148,6 +148,13 @@ STEP_CASES = [
           bc_y=I.PERIODIC), "smooth", 3),
     (dict(d=2, nx=70, ny=33, q_phi=4, q_chi=2, K=0, tau=1e-3, dt=1e-3, bc_x=I.OUTFLOW,
           bc_y=I.PERIODIC), "random", 3),
+    # orders above 8 (no x-factor tables): both even (mirror-pair loop) and
+    # both odd (the other plane loops), largest nodes 5.50 (Q = 12) and 5.19
+    # (Q = 11)
+    (dict(d=2, nx=67, ny=38, q_phi=12, q_chi=10, K=2, tau=1e-4, dt=0.5 / 67 / 5.5010),
+     "smooth", 2),
+    (dict(d=2, nx=53, ny=41, q_phi=9, q_chi=11, K=1, tau=1e-3, dt=0.5 / 53 / 5.1881,
+          bc_x=I.PERIODIC, bc_y=I.OUTFLOW), "riemann", 2),
 ]
 
 
@@ -173,8 +180,9 @@ FP32_STEP_TOL = 1e-5
 
 @pytest.mark.parametrize("case,data,steps", STEP_CASES[1:])
 def test_fp32_storage_step_matches_oracle(case, data, steps):
-    """FP32 planes (their own plane order: x-factor table groups of two mirror
-    pairs in 2D, odd orders included) against the FP64 oracle."""
+    """FP32 planes (x-factor table groups of two mirror pairs in 2D, the
+    mirror-pair loop for even orders, odd orders and orders above 8
+    included) against the FP64 oracle."""
     _torch()
     c = I.Config(storage=I.F32, **case)
     s = I.Solver(c)
