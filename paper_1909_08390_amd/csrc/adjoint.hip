@@ -1,8 +1,8 @@
 // Adjoint (reverse-mode) kernels of the IMEX-SSP3(4,3,3) step for gfx950.
 //
-// The reverse sweep through the stages of Table I (orchestrated in
-// adjoint.cpp) needs four operations, each the transpose of a forward
-// building block:
+// The reverse sweep through the stages of Table I (orchestrated by
+// imexlb_adjoint_step in imexlb.cpp) needs four operations, each the
+// transpose of a forward building block:
 //   * materialise a stage value  F_i = a S_i + b E(M_i)   (relax on read, Sec. III);
 //   * MP-9 advection transposed: dF = V^T dA, with V the flux difference of
 //     Sec. IV.  A face value is linear in its nine upwind-biased nodes with
