@@ -264,7 +264,7 @@ def _kernel_key(name):
     return prec, "stage" + args[1].strip()
 
 
-def summarize_stats(dirs, cmd):
+def summarize_stats(dirs, cmds):
     """Text summary of rocprofv3 --kernel-trace --stats CSVs."""
     rows = []
     for d in dirs:
@@ -272,7 +272,8 @@ def summarize_stats(dirs, cmd):
             with open(f) as fh:
                 rows += list(csv.DictReader(fh))
     print("# rocprofv3 kernel statistics (per-kernel launch durations)")
-    print(f"# command: {cmd}")
+    for c in cmds:
+        print(f"# command: {c}")
     print(f"# kernel sources: source_sha256: {kernel_source_hash()}")
     print(f"{'kernel':64s} {'calls':>6s} {'avg_ms':>10s} {'min_ms':>10s} {'max_ms':>10s} {'total_ms':>10s}")
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
@@ -555,7 +556,7 @@ def main():
     args = ap.parse_args()
 
     if args.summarize_stats:
-        summarize_stats(args.summarize_stats, " ; ".join(args.cmd))
+        summarize_stats(args.summarize_stats, args.cmd)
         return
     if args.summarize_insts:
         summarize_insts(args.summarize_insts, args.size, args.cmd)
