@@ -23,6 +23,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -244,15 +246,42 @@ def cpu_baseline(O, W, cfg, fields, side, steps):
     pc = O.Config(d=2, nx=side, ny=side, lx=side / N, ly=side / N, q_phi=8, q_chi=8, K=2,
                   tau=cfg.tau, dt=cfg.dt)
     n, ux, uy, T = fields
-    F = O.equilibrium(pc, n[sl], ux[sl], uy[sl], T[sl])
+    patch = tuple(np.ascontiguousarray(a[sl]) for a in (n, ux, uy, T))
+    F = O.equilibrium(pc, *patch)
     t0 = time.perf_counter()
-    O.step(pc, F, steps)
+    ref = O.step(pc, F, steps)
     dt = time.perf_counter() - t0
     vn = side * side * pc.planes * steps / dt
     return {"value": vn, "unit": "VN/s", "cores": 1, "kind": "oracle",
             "sample": f"{side}x{side} cells x 128 planes at the quadrant corner, {steps} "
                       f"IMEX step(s), single-threaded C (-O2), {dt:.1f} s",
-            "host": host_cpu()}
+            "host": host_cpu()}, (pc, patch, ref)
+
+
+def oracle_patch_errors(I, O, pc, patch, ref, steps):
+    """The oracle's patch problem run on the GPU in FP64 and with FP32
+    storage, against the oracle after the same steps: density and pressure
+    relative (L1 over the patch and max), velocity absolute."""
+    on, oux, ouy, oT = O.moments(pc, ref)
+    oP = on * oT
+
+    def rel(a, b):
+        d = np.abs(a - b)
+        return {"l1_rel": float(d.sum() / np.abs(b).sum()), "max_rel": float(d.max() / np.abs(b).max())}
+
+    out = {"sample": f"{pc.nx}x{pc.ny} patch of the workload (outflow edges), {steps} IMEX steps"}
+    for storage, tag in ((I.F64, "f64"), (I.F32, "f32_storage")):
+        c = I.Config(d=2, nx=pc.nx, ny=pc.ny, lx=pc.lx, ly=pc.ly, q_phi=pc.q_phi, q_chi=pc.q_chi, K=pc.K,
+                     tau=pc.tau, dt=pc.dt, storage=storage)
+        s = I.Solver(c)
+        s.set_equilibrium(*patch)
+        s.step(steps)
+        n, ux, uy, T = (t.cpu().numpy() for t in s.moments())
+        du = np.sqrt((ux - oux) ** 2 + (uy - ouy) ** 2)
+        out[tag] = {"rho": rel(n, on), "P": rel(n * T, oP),
+                    "u": {"l1_abs": float(du.mean()), "max_abs": float(du.max())}}
+        del s
+    return out
 
 
 def _kernel_key(name):
@@ -597,12 +626,14 @@ def main():
         log(f"bench: FP32 {r32['value']:.3e} VN/s, {r32['ms_per_step']:.2f} ms/step, passes {r32['pass_ms']}")
     copy_gbs = hbm_copy_rate(I)
     log(f"bench: plain device copy {copy_gbs:.0f} GB/s")
-    cpu = None
+    cpu = patch_err = None
     if not args.no_cpu:
         import oracle as O
         log("bench: CPU oracle baseline")
-        cpu = cpu_baseline(O, W, cfg, fields, args.cpu_side, args.cpu_steps)
+        cpu, (pc, patch, ref) = cpu_baseline(O, W, cfg, fields, args.cpu_side, args.cpu_steps)
         log(f"bench: oracle {cpu['value']:.3e} VN/s")
+        patch_err = oracle_patch_errors(I, O, pc, patch, ref, args.cpu_steps)
+        log(f"bench: GPU vs oracle on the patch: {patch_err}")
 
     out = {
         "metric": METRIC,
@@ -636,6 +667,7 @@ def main():
                      "stage4_frac_of_copy": r64["roofline"]["achieved"] / copy_gbs,
                      "step_frac_of_copy": r64["step_gbs"] / copy_gbs},
         "cpu_baseline": cpu,
+        "error_vs_oracle": patch_err,
     }
     if r32 is not None:
         err = fp32_error(r32["moments"], r64["moments"])
