@@ -199,10 +199,15 @@ def allocator_warmup():
     one, and allocations after it mostly fast.  The block is never touched."""
     import torch
 
-    x = torch.empty(ALLOCATOR_WARMUP_BYTES, dtype=torch.uint8, device="cuda")
+    try:
+        x = torch.empty(ALLOCATOR_WARMUP_BYTES, dtype=torch.uint8, device="cuda")
+    except RuntimeError as e:  # not enough free device memory: go on without it
+        log(f"bench: allocator warm-up skipped ({e})")
+        return 0
     torch.cuda.synchronize()
     del x
     torch.cuda.empty_cache()
+    return ALLOCATOR_WARMUP_BYTES
 
 
 def fp32_error(m32, m64):
@@ -607,7 +612,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    allocator_warmup()
+    warm = allocator_warmup()
     if args.copy_calib:
         copy_calibration(args.copy_calib)
     if args.workload == "batch":
@@ -660,7 +665,7 @@ def main():
         "ms_per_step_reps": r64["ms_per_step_reps"],
         "bytes_per_vn_step": r64["bytes_per_vn_step"],
         "step_hbm_frac": r64["step_gbs"] / HBM_PEAK_GBS,
-        "allocator_warmup_bytes": ALLOCATOR_WARMUP_BYTES,
+        "allocator_warmup_bytes": warm,
         "hbm_copy": {"gbs": copy_gbs, "frac_of_peak": copy_gbs / HBM_PEAK_GBS,
                      "bytes": COPY_PROBE_BYTES, "reps": 8,
                      "kernel": "imexlb_copy_probe: one 16-byte load and store per thread",
