@@ -154,14 +154,14 @@ def test_mp9_face_uniform_and_linear():
     assert O.mp9_face(f) == pytest.approx(1.0 + 0.25 * 4.5, rel=1e-15)
 
 
-def test_mp9_face_clips_to_monotone_bounds_at_a_jump():
-    """At a jump the face value stays between the two neighbours."""
-    f = np.array([0, 0, 0, 0, 0, 1, 1, 1, 1], dtype=float)
-    val = O.mp9_face(f)
-    assert 0.0 <= val <= 1.0
-    f = np.array([1, 1, 1, 1, 1, 0, 0, 0, 0], dtype=float)
-    val = O.mp9_face(f)
-    assert 0.0 <= val <= 1.0
+def test_mp9_face_at_a_jump_is_the_upwind_value():
+    """At a jump the limiter returns the upwind node's value exactly (both
+    limits collapse onto it; derivations in test_oracle_mp9_pins.py), and a
+    scaled and shifted jump gives the scaled and shifted value."""
+    assert O.mp9_face(np.array([0, 0, 0, 0, 0, 1, 1, 1, 1], dtype=float)) == 0.0
+    assert O.mp9_face(np.array([1, 1, 1, 1, 1, 0, 0, 0, 0], dtype=float)) == 1.0
+    assert O.mp9_face(np.array([3, 3, 3, 3, 3, 7, 7, 7, 7], dtype=float)) == 3.0
+    assert O.mp9_face(np.array([7, 7, 7, 7, 7, 3, 3, 3, 3], dtype=float)) == 7.0
 
 
 def test_2d_advection_is_sum_of_axis_operators():

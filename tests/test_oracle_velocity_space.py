@@ -49,6 +49,20 @@ def test_quadrature_q3_closed_form():
     np.testing.assert_allclose(w, [1 / 6, 2 / 3, 1 / 6], rtol=1e-14)
 
 
+def test_quadrature_q5_closed_form():
+    """He_5 = x^5 - 10 x^3 + 15 x, so the nodes are 0 and +-sqrt(5 -+ sqrt 10).
+    With a = x^2 at a nonzero node, a^2 = 10 a - 15 reduces
+    He_6 = x^6 - 15 x^4 + 45 x^2 - 15 to 60 - 20 a, hence
+    w = 5!/He_6^2 = 3/(10 (3 - a)^2): (7 + 2 sqrt 10)/60 at a = 5 - sqrt 10,
+    (7 - 2 sqrt 10)/60 at a = 5 + sqrt 10, and 120/225 = 8/15 at x = 0."""
+    r = math.sqrt(10.0)
+    inner, outer = math.sqrt(5 - r), math.sqrt(5 + r)
+    p, w = O.gauss_hermite(5)
+    np.testing.assert_allclose(p, [-outer, -inner, 0.0, inner, outer], rtol=0, atol=2e-15)
+    np.testing.assert_allclose(w, [(7 - 2 * r) / 60, (7 + 2 * r) / 60, 8 / 15,
+                                   (7 + 2 * r) / 60, (7 - 2 * r) / 60], rtol=1e-14)
+
+
 def gaussian_moment(m, u, T):
     """E[X^m] for X ~ N(u, T): sum_j C(m, j) u^(m-j) T^(j/2) (j-1)!! over even j."""
     return sum(math.comb(m, j) * u ** (m - j) * T ** (j // 2) * double_factorial(j - 1)
