@@ -110,11 +110,14 @@ def copy_calibration(mib):
     torch.cuda.empty_cache()
 
 
-def run_precision(I, W, N, storage, steps, warmup, seed):
+def run_precision(I, W, N, storage, steps, warmup, seed, horizon=0, tau=1e-7):
+    """Timed steps of the 2D workload in one storage type.  With horizon >
+    warmup + steps the run then continues untimed to `horizon` steps and the
+    moments at that horizon are returned as well."""
     import torch
 
     dt = 0.5 / N / PMAX8
-    cfg = I.Config(d=2, nx=N, ny=N, q_phi=8, q_chi=8, K=2, tau=1e-7, dt=dt, storage=storage)
+    cfg = I.Config(d=2, nx=N, ny=N, q_phi=8, q_chi=8, K=2, tau=tau, dt=dt, storage=storage)
     states, k = W.quadrant_states(seed)
     fields = W.riemann_2d(N, N, states)
     s = I.Solver(cfg)
@@ -164,6 +167,17 @@ def run_precision(I, W, N, storage, steps, warmup, seed):
                        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                        "copy-calibrated)"}
     res["moments"] = s.moments()  # (n, ux, uy, T) after warmup + timed steps
+    done = warmup + steps
+    if horizon > done:
+        t1 = time.perf_counter()
+        while done < horizon:
+            k = min(500, horizon - done)
+            s.step(k)
+            torch.cuda.synchronize()
+            done += k
+            log(f"bench: {N}^2 {'FP32' if elem == 4 else 'FP64'} at step {done} of {horizon}")
+        res["horizon"] = {"steps": horizon, "moments": s.moments(), "state_ok": s.check_state() == I.OK,
+                          "ms_per_step_after_timed": 1e3 * (time.perf_counter() - t1) / (horizon - warmup - steps)}
     del s
     torch.cuda.empty_cache()
     return res, cfg, fields
@@ -229,6 +243,21 @@ def fp32_error(m32, m64):
             "u": {"l1_abs": float(du.mean()), "max_abs": float(du.max())}}
 
 
+def horizon_1024(I, W, seed):
+    """Configuration of the 1024^2 four-quadrant problem (tau 1e-6, CFL 0.5):
+    FP64 and FP32 storage from the same seeded state to 500 steps; errors of
+    the FP32-storage moments against the FP64 run at the end."""
+    r64, _, _ = run_precision(I, W, 1024, I.F64, 10, 0, seed, horizon=500, tau=1e-6)
+    r32, _, _ = run_precision(I, W, 1024, I.F32, 10, 0, seed, horizon=500, tau=1e-6)
+    return {"workload": "1024x1024 four-quadrant problem, 8x8 velocities per f and g, tau 1e-6, "
+                        "CFL 0.5, outflow",
+            "steps": 500,
+            "f64_ms_per_step": r64["horizon"]["ms_per_step_after_timed"],
+            "f32_ms_per_step": r32["horizon"]["ms_per_step_after_timed"],
+            "state_ok": r64["horizon"]["state_ok"] and r32["horizon"]["state_ok"],
+            "error_vs_fp64": fp32_error(r32["horizon"]["moments"], r64["horizon"]["moments"])}
+
+
 def host_cpu():
     """CPU model and logical CPU count of the host that runs the oracle."""
     model = "unknown CPU"
@@ -243,23 +272,58 @@ def host_cpu():
     return f"{model}, {os.cpu_count()} logical CPUs on the host"
 
 
+MAX_ORACLE_THREADS = 16  # the host cores one GPU's share of the box provides
+
+
+def oracle_threads():
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(MAX_ORACLE_THREADS, avail))
+
+
 def cpu_baseline(O, W, cfg, fields, side, steps):
-    """The FP64 oracle on a side x side patch of the same workload (centre)."""
+    """The FP64 oracle on side x side patches of the same workload: one
+    patch at the quadrant corner on one core, then disjoint patches around it
+    on all host cores at once (one independent oracle run per thread; each
+    oracle call runs in C without the interpreter lock)."""
+    import concurrent.futures as cf
+
     N = cfg.nx
-    c0 = N // 2 - side // 2
-    sl = (slice(c0, c0 + side), slice(c0, c0 + side))
+    n, ux, uy, T = fields
+
+    def patch_at(r0, c0):
+        sl = (slice(r0, r0 + side), slice(c0, c0 + side))
+        return tuple(np.ascontiguousarray(a[sl]) for a in (n, ux, uy, T))
+
     pc = O.Config(d=2, nx=side, ny=side, lx=side / N, ly=side / N, q_phi=8, q_chi=8, K=2,
                   tau=cfg.tau, dt=cfg.dt)
-    n, ux, uy, T = fields
-    patch = tuple(np.ascontiguousarray(a[sl]) for a in (n, ux, uy, T))
+    c0 = N // 2 - side // 2
+    patch = patch_at(c0, c0)
     F = O.equilibrium(pc, *patch)
     t0 = time.perf_counter()
     ref = O.step(pc, F, steps)
-    dt = time.perf_counter() - t0
-    vn = side * side * pc.planes * steps / dt
-    return {"value": vn, "unit": "VN/s", "cores": 1, "kind": "oracle",
-            "sample": f"{side}x{side} cells x 128 planes at the quadrant corner, {steps} "
-                      f"IMEX step(s), single-threaded C (-O2), {dt:.1f} s",
+    dt1 = time.perf_counter() - t0
+    vn1 = side * side * pc.planes * steps / dt1
+
+    nthr = oracle_threads()
+    k = int(np.ceil(np.sqrt(nthr)))
+    base = N // 2 - (k * side) // 2
+    origins = [(base + (i // k) * side, base + (i % k) * side) for i in range(nthr)]
+    starts = [O.equilibrium(pc, *patch_at(r, c)) for r, c in origins]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=nthr) as pool:
+        list(pool.map(lambda F0: O.step(pc, F0, steps), starts))
+    dtn = time.perf_counter() - t0
+    vnn = nthr * side * side * pc.planes * steps / dtn
+    return {"value": vnn, "unit": "VN/s", "cores": nthr, "kind": "oracle",
+            "sample": f"{nthr} disjoint {side}x{side}-cell patches x 128 planes around the quadrant "
+                      f"corner, {steps} IMEX step(s) each, one single-threaded C (-O2) oracle run per "
+                      f"core at once, {dtn:.1f} s",
+            "single_core": {"value": vn1, "unit": "VN/s", "cores": 1,
+                            "sample": f"one {side}x{side} patch at the quadrant corner, {steps} IMEX "
+                                      f"step(s), {dt1:.1f} s"},
             "host": host_cpu()}, (pc, patch, ref)
 
 
@@ -567,6 +631,10 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--horizon", type=int, default=2000,
+                    help="after the timed steps, continue both storage types to this many steps "
+                         "and report the FP32-vs-FP64 errors there (and at 500 steps of the 1024^2 "
+                         "problem); 0 skips")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=10)
@@ -621,14 +689,21 @@ def main():
     if args.workload == "adjoint":
         run_adjoint(args)
         return
-    log(f"bench: {args.size}^2 cells x 128 planes, FP64, {args.warmup} warmup + {args.steps} steps")
-    r64, cfg, fields = run_precision(I, W, args.size, I.F64, args.steps, args.warmup, args.seed)
+    horizon = args.horizon if args.horizon > args.warmup + args.steps else 0
+    log(f"bench: {args.size}^2 cells x 128 planes, FP64, {args.warmup} warmup + {args.steps} steps"
+        + (f", then on to step {horizon}" if horizon else ""))
+    r64, cfg, fields = run_precision(I, W, args.size, I.F64, args.steps, args.warmup, args.seed, horizon)
     log(f"bench: FP64 {r64['value']:.3e} VN/s, {r64['ms_per_step']:.2f} ms/step, passes {r64['pass_ms']}")
     r32 = None
     if not args.no_fp32:
         log("bench: FP32 storage run")
-        r32, _, _ = run_precision(I, W, args.size, I.F32, args.steps, args.warmup, args.seed)
+        r32, _, _ = run_precision(I, W, args.size, I.F32, args.steps, args.warmup, args.seed, horizon)
         log(f"bench: FP32 {r32['value']:.3e} VN/s, {r32['ms_per_step']:.2f} ms/step, passes {r32['pass_ms']}")
+    h1024 = None
+    if not args.no_fp32 and args.horizon > 0 and args.size == 4096:
+        log("bench: 1024^2 FP32-vs-FP64 run to 500 steps")
+        h1024 = horizon_1024(I, W, args.seed)
+        log(f"bench: 1024^2 after 500 steps: {h1024['error_vs_fp64']}")
     copy_gbs = hbm_copy_rate(I)
     log(f"bench: plain device copy {copy_gbs:.0f} GB/s")
     cpu = patch_err = None
@@ -688,6 +763,17 @@ def main():
             "error_vs_fp64": err,
             "error_after_steps": args.warmup + args.steps,
         }
+        if horizon and "horizon" in r32 and "horizon" in r64:
+            herr = fp32_error(r32["horizon"]["moments"], r64["horizon"]["moments"])
+            log(f"bench: FP32 vs FP64 after {horizon} steps: {herr}")
+            out["fp32"]["horizons"] = [
+                {"workload": f"{args.size}x{args.size} (this bench's workload)", "steps": horizon,
+                 "f64_ms_per_step": r64["horizon"]["ms_per_step_after_timed"],
+                 "f32_ms_per_step": r32["horizon"]["ms_per_step_after_timed"],
+                 "state_ok": r64["horizon"]["state_ok"] and r32["horizon"]["state_ok"],
+                 "error_vs_fp64": herr}]
+            if h1024 is not None:
+                out["fp32"]["horizons"].append(h1024)
     print(json.dumps(out), flush=True)
 
 

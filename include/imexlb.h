@@ -66,6 +66,10 @@ typedef struct {
     int bc_x, bc_y;     /* imexlb_bc per axis: outflow (ghost nodes copy the
                            boundary node, Sec. IV) or periodic                 */
     int storage;        /* imexlb_storage of the plane-sets                    */
+    int check_physical; /* nonzero: imexlb_step checks the moments after every
+                           step and returns IMEXLB_ENONPHYS when some cell has
+                           n <= 0, T <= 0 or a non-finite moment (the step
+                           call then synchronises the stream)                  */
 } imexlb_config;
 
 typedef struct imexlb_ctx imexlb_ctx;
@@ -109,14 +113,19 @@ imexlb_status imexlb_set_state(imexlb_ctx* ctx, const void* d_F);
 imexlb_status imexlb_get_state(const imexlb_ctx* ctx, void* d_F);
 
 /* Advance the bound state by nsteps IMEX-SSP3(4,3,3) steps (Sec. III):
- * three fused stage passes per step, asynchronous on the stream. */
+ * three fused stage passes per step, asynchronous on the stream.  With
+ * cfg.check_physical set, the moments are checked on the device after every
+ * step and the call synchronises at the end: IMEXLB_ENONPHYS (the message
+ * names the first step that produced a non-physical cell) or IMEXLB_OK.  The
+ * steps are taken in either case. */
 imexlb_status imexlb_step(imexlb_ctx* ctx, int nsteps);
 
 /* imexlb_step with per-pass timing: adds to ms[0], ms[1], ms[2] the summed
  * durations (milliseconds, HIP events recorded on the context's stream
  * between the launches) of the stage-3, stage-4 and stage-5 passes of all
- * nsteps steps.  Same results as imexlb_step; synchronises the stream at the
- * end.  For measurement. */
+ * nsteps steps.  Same results and status as imexlb_step (with
+ * cfg.check_physical set, each step's check kernel falls in its stage-5
+ * interval); synchronises the stream at the end.  For measurement. */
 imexlb_status imexlb_step_timed(imexlb_ctx* ctx, int nsteps, double ms[3]);
 
 /* Device fields (n, ux, uy, T) of the current state (Sec. II, discrete
@@ -134,9 +143,23 @@ imexlb_status imexlb_compute_moments(const imexlb_ctx* ctx, const void* d_F, dou
 imexlb_status imexlb_advect(const imexlb_ctx* ctx, const void* d_F, double* d_VF);
 
 /* Host sums over all cells of the current state: out[0] = mass, out[1..2] =
- * momentum (x, y), out[3] = total energy (D+K)/2 n T + n |u|^2 / 2.
- * Synchronises the stream. */
+ * momentum (x, y; y is 0 when d = 1), out[3] = total energy
+ * (D+K)/2 n T + n |u|^2 / 2 (Sec. II, Eq. Moments), sums of cell values
+ * (multiply by the cell volume for integrals).  On periodic grids the step
+ * conserves all four (the MP-9 fluxes telescope, Sec. IV; the BGK terms
+ * carry no moments, Sec. III).  Deterministic: wavefront shuffle sums in a
+ * fixed order.  Synchronises the stream. */
 imexlb_status imexlb_domain_sums(const imexlb_ctx* ctx, double out[4]);
+
+/* Density loss L = 1/2 sum over cells of (n - n*)^2 and its gradient
+ * dL/dn = n - n*, for the adjoint workloads.  d_n: device FP64 density field
+ * (nx*ny values), or NULL for the density of the current state; d_target:
+ * device FP64 field n*; d_loss: device, one double (written); d_grad: device
+ * field (written) or NULL.  Deterministic, as imexlb_domain_sums.
+ * Asynchronous.  Errors: EINVAL for NULL d_target or d_loss, ESTATE for
+ * d_n = NULL without a state. */
+imexlb_status imexlb_density_loss(const imexlb_ctx* ctx, const double* d_n, const double* d_target,
+                                  double* d_loss, double* d_grad);
 
 /* Scan the current moments for n <= 0, T <= 0 or non-finite values:
  * IMEXLB_OK or IMEXLB_ENONPHYS.  Synchronises the stream. */

@@ -8,9 +8,10 @@ the gradients of the final moments (``imexlb_moments_adjoint``), then walks
 the segments backwards: each segment is recomputed forward from its
 checkpoint, storing its states, and the adjoint steps run through them in
 reverse; the equilibrium adjoint (``imexlb_equilibrium_adjoint``) finally
-maps the adjoint state to gradients of the initial fields.  Every step of
-this runs in the library's HIP kernels; this module only orders the calls
-and holds the checkpoints.
+maps the adjoint state to gradients of the initial fields.  The density loss
+and its gradient come from ``imexlb_density_loss``.  Every step of this runs
+in the library's HIP kernels; this module only orders the calls and holds
+the checkpoints.
 """
 from __future__ import annotations
 
@@ -65,6 +66,22 @@ class EquilibriumRollout(torch.autograd.Function):
         return dn, dux, duy, dT, None, None, None
 
 
+class DensityLoss(torch.autograd.Function):
+    """n -> 1/2 sum (n - target)^2 in the library (``imexlb_density_loss``),
+    with dL/dn = n - target from the same call."""
+
+    @staticmethod
+    def forward(ctx, n, target, solver):
+        loss, grad = solver.density_loss(target.detach(), n=n.detach(), grad=True)
+        ctx.save_for_backward(grad)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gloss):
+        (grad,) = ctx.saved_tensors
+        return gloss * grad, None, None
+
+
 def rollout(solver, n0, ux0, uy0, T0, nsteps: int, every: int = 20):
     """Differentiable final moments of an nsteps rollout (see
     EquilibriumRollout)."""
@@ -80,9 +97,9 @@ def density_loss_gradient(solver, n0, target, nsteps: int, every: int = 20, P: f
     zero = torch.zeros_like(n0)
     T0 = P / n0
     n, _, _, _ = rollout(solver, n0, zero, zero, T0, nsteps, every)
-    loss = 0.5 * ((n - target) ** 2).sum()
+    loss = DensityLoss.apply(n, target, solver)
     loss.backward()
     return float(loss.detach()), n0.grad.detach()
 
 
-__all__ = ["EquilibriumRollout", "rollout", "density_loss_gradient", "I"]
+__all__ = ["EquilibriumRollout", "DensityLoss", "rollout", "density_loss_gradient", "I"]

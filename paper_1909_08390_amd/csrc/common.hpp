@@ -137,9 +137,20 @@ hipError_t launch_init_equilibrium(int d, bool f32, const DevTables* tab, const 
 // moments of F (plane stride cells) into M with field stride ms
 hipError_t launch_moments(int d, bool f32, const DevTables* tab, const void* F, double* M,
                           long long cells, long long ms, double dk, hipStream_t s);
-hipError_t launch_domain_sums(int d, const double* M, long long cells, double dk,
+// Work-groups of the domain sums and the density loss (one partial each).
+constexpr int kSumBlocks = 1024;
+
+// Reductions (reduce.hip).  Moment fields M = (n, ux, [uy], T) with field
+// stride ms.  The sums use nblocks work-groups whose partials (4 resp. 1
+// values each) go to partial; the totals to out4 / out1 (device).
+hipError_t launch_domain_sums(int d, const double* M, long long ms, long long cells, double dk,
                               double* partial, int nblocks, double* out4, hipStream_t s);
-hipError_t launch_check(int d, const double* M, long long cells, int* flag, hipStream_t s);
+hipError_t launch_density_loss(const double* n, const double* target, long long cells, double* grad,
+                               double* partial, int nblocks, double* out1, hipStream_t s);
+// flag = INT_MAX; then flag = min(flag, code) when a cell is non-physical.
+hipError_t launch_check_reset(int* flag, hipStream_t s);
+hipError_t launch_check(int d, const double* M, long long ms, long long cells, int code, int* flag,
+                        hipStream_t s);
 // Adjoint building blocks (adjoint.hip).  y / cf: up to four FP64
 // plane-sets combined as sum_j cf[j] y[j].
 hipError_t launch_materialise(int d, bool f32, const DevTables* tab, const void* src, const double* M,

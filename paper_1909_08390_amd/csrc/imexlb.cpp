@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -39,7 +40,6 @@ struct imexlb_ctx {
 namespace {
 
 constexpr double kAlpha = 0.24169426078821;  // Table I
-constexpr int kRedBlocks = 1024;
 
 imexlb_status fail(imexlb_ctx* c, imexlb_status s, const std::string& msg) {
     if (c) c->err = msg;
@@ -461,7 +461,7 @@ imexlb_status imexlb_create(const imexlb_config* cfg, void* hip_stream, imexlb_c
         return IMEXLB_ENOMEM;
     }
     if (e == hipSuccess) e = hipGetDevice(&c->device);
-    c->nred = kRedBlocks;
+    c->nred = kSumBlocks;
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_small, sizeof(double) * (4 * c->nred + 4));
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_flag, sizeof(int) * 64);
     if (e != hipSuccess) {
@@ -583,17 +583,35 @@ imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev) {
     StageArgs pa[3];
     pass_args(a, F, G3, G4, Mn, M3, M4, pa);
     const StageArgs &a3 = pa[0], &a4 = pa[1], &a5 = pa[2];
+    const bool check = c->cfg.check_physical != 0;
     hipError_t e = hipSuccess;
-    if (ev) e = hipEventRecord(ev[0], c->stream);
+    if (check) e = launch_check_reset(c->d_flag, c->stream);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[0], c->stream);
     for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
         e = launch_stage(d, f32, kStage3, a3, c->stream);
         if (e == hipSuccess && ev) e = hipEventRecord(ev[3 * s + 1], c->stream);
         if (e == hipSuccess) e = launch_stage(d, f32, kStage4, a4, c->stream);
         if (e == hipSuccess && ev) e = hipEventRecord(ev[3 * s + 2], c->stream);
         if (e == hipSuccess) e = launch_stage(d, f32, kStage5, a5, c->stream);
+        // the moments of F^{n+1} (written by pass 5) against n > 0, T > 0, finite
+        if (e == hipSuccess && check) e = launch_check(d, Mn, c->cells, c->cells, s + 1, c->d_flag, c->stream);
         if (e == hipSuccess && ev) e = hipEventRecord(ev[3 * s + 3], c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "step");
+    return IMEXLB_OK;
+}
+
+// With check_physical set: wait for the steps and report the first step
+// that produced a non-physical cell.
+imexlb_status finish_check(imexlb_ctx* c) {
+    if (!c->cfg.check_physical) return IMEXLB_OK;
+    int h = 0;
+    hipError_t e = hipMemcpyAsync(&h, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "step: physical check");
+    if (h != INT_MAX)
+        return fail(c, IMEXLB_ENONPHYS, "step: non-physical moments (n <= 0, T <= 0 or non-finite) after step " +
+                                            std::to_string(h) + " of this call");
     return IMEXLB_OK;
 }
 
@@ -605,7 +623,8 @@ imexlb_status imexlb_step(imexlb_ctx* c, int nsteps) {
     if (!c) return IMEXLB_EINVAL;
     if (nsteps < 0) return fail(c, IMEXLB_EINVAL, "step: nsteps < 0");
     if (need_state(c) != IMEXLB_OK) return fail(c, IMEXLB_ESTATE, "step: no bound state");
-    return run_steps(c, nsteps, nullptr);
+    imexlb_status st = run_steps(c, nsteps, nullptr);
+    return st == IMEXLB_OK ? finish_check(c) : st;
 }
 
 imexlb_status imexlb_step_timed(imexlb_ctx* c, int nsteps, double ms[3]) {
@@ -633,6 +652,7 @@ imexlb_status imexlb_step_timed(imexlb_ctx* c, int nsteps, double ms[3]) {
                     ms[k] += t;
                 }
             if (e != hipSuccess) st = hip_fail(c, e, "step_timed: elapsed");
+            if (st == IMEXLB_OK) st = finish_check(c);
         }
     }
     for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
@@ -698,11 +718,25 @@ imexlb_status imexlb_domain_sums(const imexlb_ctx* c, double out[4]) {
     if (need_state(c) != IMEXLB_OK) return fail(m, IMEXLB_ESTATE, "domain_sums: no state");
     double* part = c->d_small;
     double* res = c->d_small + 4 * c->nred;
-    hipError_t e = launch_domain_sums(c->cfg.d, work_m(c, 0), c->cells, (double)(kDTotal + c->cfg.K), part,
-                                      c->nred, res, c->stream);
+    hipError_t e = launch_domain_sums(c->cfg.d, work_m(c, 0), c->cells, c->cells, (double)(kDTotal + c->cfg.K),
+                                      part, c->nred, res, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(m, e, "domain_sums");
+    return IMEXLB_OK;
+}
+
+imexlb_status imexlb_density_loss(const imexlb_ctx* c, const double* n, const double* target, double* loss,
+                                  double* grad) {
+    if (!c) return IMEXLB_EINVAL;
+    imexlb_ctx* m = const_cast<imexlb_ctx*>(c);
+    if (!target || !loss) return fail(m, IMEXLB_EINVAL, "density_loss: NULL target or loss");
+    if (!n) {
+        if (need_state(c) != IMEXLB_OK) return fail(m, IMEXLB_ESTATE, "density_loss: no state");
+        n = work_m(c, 0);  // field 0 of the state's moments
+    }
+    hipError_t e = launch_density_loss(n, target, c->cells, grad, c->d_small, c->nred, loss, c->stream);
+    if (e != hipSuccess) return hip_fail(m, e, "density_loss");
     return IMEXLB_OK;
 }
 
@@ -711,11 +745,12 @@ imexlb_status imexlb_check_state(const imexlb_ctx* c) {
     imexlb_ctx* m = const_cast<imexlb_ctx*>(c);
     if (need_state(c) != IMEXLB_OK) return fail(m, IMEXLB_ESTATE, "check_state: no state");
     int h = 0;
-    hipError_t e = launch_check(c->cfg.d, work_m(c, 0), c->cells, c->d_flag, c->stream);
+    hipError_t e = launch_check_reset(c->d_flag, c->stream);
+    if (e == hipSuccess) e = launch_check(c->cfg.d, work_m(c, 0), c->cells, c->cells, 1, c->d_flag, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&h, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(m, e, "check_state");
-    return h ? fail(m, IMEXLB_ENONPHYS, "check_state: non-physical moments") : IMEXLB_OK;
+    return h != INT_MAX ? fail(m, IMEXLB_ENONPHYS, "check_state: non-physical moments") : IMEXLB_OK;
 }
 
 }  // extern "C"

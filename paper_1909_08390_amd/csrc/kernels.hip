@@ -1287,59 +1287,6 @@ __global__ void __launch_bounds__(256) moments_kernel(const DevTables* __restric
     }
 }
 
-// Block-level sum of mass, momentum and total energy, fixed reduction order.
-template <int D>
-__global__ void __launch_bounds__(256) sums_kernel(const double* __restrict__ M, long long cells,
-                                                   double dk, double* partial) {
-    __shared__ double red[4][256];
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    const long long per = (cells + gridDim.x - 1) / gridDim.x;
-    const long long beg = (long long)blockIdx.x * per;
-    const long long end = beg + per < cells ? beg + per : cells;
-    for (long long c = beg + threadIdx.x; c < end; c += blockDim.x) {
-        const double n = M[c], ux = M[cells + c];
-        const double uy = D == 2 ? M[2 * cells + c] : 0.0;
-        const double T = M[(D + 1) * cells + c];
-        s[0] += n;
-        s[1] += n * ux;
-        s[2] += n * uy;
-        s[3] += 0.5 * dk * n * T + 0.5 * n * (ux * ux + uy * uy);
-    }
-    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = s[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
-}
-
-__global__ void __launch_bounds__(256) sums_final_kernel(const double* partial, int nblocks, double* out) {
-    __shared__ double red[4][256];
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-        for (int k = 0; k < 4; ++k) s[k] += partial[b * 4 + k];
-    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = s[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
-}
-
-template <int D>
-__global__ void __launch_bounds__(256) check_kernel(const double* __restrict__ M, long long cells, int* flag) {
-    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cells) return;
-    bool bad = false;
-    for (int f = 0; f < D + 2; ++f) bad |= !isfinite(M[f * cells + c]);
-    bad |= !(M[c] > 0.0) || !(M[(D + 1) * cells + c] > 0.0);
-    if (bad) atomicOr(flag, 1);
-}
-
 template <typename S, int KIND>
 hipError_t launch_stage_t(int d, const StageArgs& a, hipStream_t s) {
     const int ntiles = d == 2 ? a.ntx * a.nty : a.ntx;
@@ -1445,26 +1392,6 @@ hipError_t launch_moments(int d, bool f32, const DevTables* tab, const void* F, 
         if (f32) hipLaunchKernelGGL((moments_kernel<float, 1>), dim3(grid), dim3(256), 0, s, tab, (const float*)F, M, cells, ms, dk);
         else hipLaunchKernelGGL((moments_kernel<double, 1>), dim3(grid), dim3(256), 0, s, tab, (const double*)F, M, cells, ms, dk);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_domain_sums(int d, const double* M, long long cells, double dk,
-                              double* partial, int nblocks, double* out4, hipStream_t s) {
-    if (d == 2) hipLaunchKernelGGL((sums_kernel<2>), dim3(nblocks), dim3(256), 0, s, M, cells, dk, partial);
-    else hipLaunchKernelGGL((sums_kernel<1>), dim3(nblocks), dim3(256), 0, s, M, cells, dk, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sums_final_kernel, dim3(1), dim3(256), 0, s, partial, nblocks, out4);
-    return hipGetLastError();
-}
-
-__global__ void zero_int_kernel(int* p) { *p = 0; }
-
-hipError_t launch_check(int d, const double* M, long long cells, int* flag, hipStream_t s) {
-    const int grid = (int)((cells + 255) / 256);
-    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, flag);
-    if (d == 2) hipLaunchKernelGGL((check_kernel<2>), dim3(grid), dim3(256), 0, s, M, cells, flag);
-    else hipLaunchKernelGGL((check_kernel<1>), dim3(grid), dim3(256), 0, s, M, cells, flag);
     return hipGetLastError();
 }
 

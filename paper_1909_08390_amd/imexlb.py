@@ -27,7 +27,8 @@ class CConfig(ctypes.Structure):
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double),
                 ("q_phi", ctypes.c_int), ("q_chi", ctypes.c_int), ("K", ctypes.c_int),
                 ("tau", ctypes.c_double), ("dt", ctypes.c_double),
-                ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("storage", ctypes.c_int)]
+                ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("storage", ctypes.c_int),
+                ("check_physical", ctypes.c_int)]
 
 
 class CTube(ctypes.Structure):
@@ -78,6 +79,7 @@ def lib():
         L.imexlb_compute_moments.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.imexlb_advect.argtypes = [_vp, _vp, _vp]
         L.imexlb_domain_sums.argtypes = [_vp, _dp]
+        L.imexlb_density_loss.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.imexlb_check_state.argtypes = [_vp]
         L.imexlb_status_string.argtypes = [ctypes.c_int]
         L.imexlb_status_string.restype = ctypes.c_char_p
@@ -154,11 +156,12 @@ class Config:
     bc_x: int = OUTFLOW
     bc_y: int = OUTFLOW
     storage: int = F64
+    check_physical: int = 0
 
     def c(self) -> CConfig:
         return CConfig(self.d, self.nx, self.ny, self.lx, self.ly,
                        self.q_phi, self.q_chi, self.K, self.tau, self.dt, self.bc_x,
-                       self.bc_y, self.storage)
+                       self.bc_y, self.storage, self.check_physical)
 
     @property
     def planes(self) -> int:
@@ -309,6 +312,21 @@ class Solver:
         out = np.zeros(4)
         self._check(self.L.imexlb_domain_sums(self._h, out.ctypes.data_as(_dp)), "domain_sums")
         return out
+
+    def density_loss(self, target, n=None, grad: bool = False):
+        """(loss, grad): 1/2 sum (n - target)^2 as a 0-d FP64 device tensor
+        and, when ``grad``, the field n - target; n defaults to the density
+        of the current state.  ``imexlb_density_loss``."""
+        torch = self.torch
+        target = self._dev64(target)
+        n = self._dev64(n) if n is not None else None
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        g = torch.empty(self.cfg.field_shape, dtype=torch.float64, device=self.device) if grad else None
+        self._keep = (n, target)
+        self._check(self.L.imexlb_density_loss(
+            self._h, _vp(n.data_ptr()) if n is not None else None, _vp(target.data_ptr()),
+            _vp(loss.data_ptr()), _vp(g.data_ptr()) if g is not None else None), "density_loss")
+        return loss, g
 
     def check_state(self) -> int:
         return self.L.imexlb_check_state(self._h)

@@ -3,6 +3,7 @@ invalid configurations before touching a device (runs without a GPU)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -24,7 +25,7 @@ def test_header_declares_the_boundary():
                      "imexlb_set_equilibrium", "imexlb_set_state", "imexlb_get_state",
                      "imexlb_step", "imexlb_moments", "imexlb_advect",
                      "imexlb_compute_moments", "imexlb_domain_sums", "imexlb_check_state",
-                     "imexlb_status_string", "imexlb_last_error"]:
+                     "imexlb_density_loss", "imexlb_status_string", "imexlb_last_error"]:
         assert required in names
 
 
@@ -71,6 +72,30 @@ def test_null_arguments():
     assert L.imexlb_create(None, None, None) == I.EINVAL
     assert L.imexlb_step(None, 1) == I.EINVAL
     assert L.imexlb_bind(None, None, None) == I.EINVAL
+    assert L.imexlb_density_loss(None, None, None, None, None) == I.EINVAL
+
+
+def test_config_mirror_matches_header_layout(tmp_path):
+    """The ctypes mirrors of imexlb_config and imexlb_tube have the C
+    layout: sizes and field offsets printed by a program compiled against
+    the header."""
+    fields = [f for f, _ in I.CConfig._fields_]
+    tfields = [f for f, _ in I.CTube._fields_]
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "imexlb.h"', 'int main(void) {',
+             '  printf("%zu\\n", sizeof(imexlb_config));',
+             '  printf("%zu\\n", sizeof(imexlb_tube));']
+    lines += [f'  printf("%zu\\n", offsetof(imexlb_config, {f}));' for f in fields]
+    lines += [f'  printf("%zu\\n", offsetof(imexlb_tube, {f}));' for f in tfields]
+    lines += ['  return 0;', '}']
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(I.CConfig), ctypes.sizeof(I.CTube)]
+    want += [getattr(I.CConfig, f).offset for f in fields]
+    want += [getattr(I.CTube, f).offset for f in tfields]
+    assert got == want
 
 
 def test_copy_probe_rejects_null_arguments():
