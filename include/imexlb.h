@@ -161,6 +161,23 @@ imexlb_status imexlb_domain_sums(const imexlb_ctx* ctx, double out[4]);
 imexlb_status imexlb_density_loss(const imexlb_ctx* ctx, const double* d_n, const double* d_target,
                                   double* d_loss, double* d_grad);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sums
+ * of imexlb_domain_sums, same kernels and bitwise the same results, of
+ * caller-given moment fields, with no context, no allocation and no memset.
+ * d_M: device FP64 fields (n, ux, [uy], T) of `cells` values each, field
+ * after field (d + 2 fields); d_out: device, 4 doubles (written): mass,
+ * momentum x, y (0 when d = 1), energy with D + K = 3 + K.  Asynchronous on
+ * hip_stream (NULL: the null stream).  The per-work-group partials live in
+ * a 32 KiB static device array that each GPU holds for the life of the
+ * process; calls that overlap in time on one GPU (other streams, other
+ * threads) share it and race, so issue them in one stream order.
+ * Errors (checked before any device work): IMEXLB_EINVAL for d not 1 or 2,
+ * K < 0, NULL buffers, or cells outside [1, 2^31 - 1]; IMEXLB_EHIP for a HIP
+ * failure.  Messages go to stderr. */
+imexlb_status imexlb_domain_sums_noalloc(int d, int K, const double* d_M, long long cells,
+                                         double* d_out, void* hip_stream);
+
 /* Scan the current moments for n <= 0, T <= 0 or non-finite values:
  * IMEXLB_OK or IMEXLB_ENONPHYS.  Synchronises the stream. */
 imexlb_status imexlb_check_state(const imexlb_ctx* ctx);

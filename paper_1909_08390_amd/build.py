@@ -17,7 +17,8 @@ LIB = os.path.join(PKG, "libimexlb.so")
 
 SOURCES = [os.path.join(CSRC, "imexlb.cpp"), os.path.join(CSRC, "batch.cpp"),
            os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "adjoint.hip"),
-           os.path.join(CSRC, "probe.hip"), os.path.join(CSRC, "reduce.hip")]
+           os.path.join(CSRC, "probe.hip"), os.path.join(CSRC, "reduce.hip"),
+           os.path.join(CSRC, "noalloc.hip")]
 
 # Packed FP32 instructions are disabled for all device code (the compiler
 # would otherwise form v_pk_* ops from float code).

@@ -118,8 +118,29 @@ def lib():
         L.imexlb_batch_last_error.argtypes = [_vp]
         L.imexlb_batch_last_error.restype = ctypes.c_char_p
         L.imexlb_copy_probe.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp, _dp]
+        L.imexlb_domain_sums_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _ll, _vp, _vp]
         _lib = L
     return _lib
+
+
+def domain_sums_noalloc(d: int, K: int, M, stream=None):
+    """Mass, momentum (x, y) and energy totals of the moment fields M, a
+    contiguous FP64 device tensor (n, ux, [uy], T) of cells values each, as
+    a device tensor of 4 values, by ``imexlb_domain_sums_noalloc`` (no
+    allocation in the library; the output tensor is allocated here).
+    Asynchronous on ``stream`` (default: torch's current stream)."""
+    import torch
+
+    nf = d + 2
+    if not (M.is_cuda and M.dtype == torch.float64 and M.is_contiguous()) or M.numel() % nf:
+        raise ValueError("domain_sums_noalloc: M must be a contiguous FP64 device tensor of d + 2 fields")
+    out = torch.empty(4, dtype=torch.float64, device=M.device)
+    st = stream if stream is not None else torch.cuda.current_stream(M.device)
+    rc = lib().imexlb_domain_sums_noalloc(int(d), int(K), _vp(M.data_ptr()), M.numel() // nf,
+                                          _vp(out.data_ptr()), _vp(st.cuda_stream))
+    if rc != OK:
+        raise ImexlbError(rc, "domain_sums_noalloc: " + lib().imexlb_status_string(rc).decode())
+    return out
 
 
 def copy_probe(src, dst, reps: int = 8) -> float:
