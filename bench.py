@@ -506,14 +506,15 @@ def run_batch(args):
     from paper_1909_08390_amd import imexlb as I
     from paper_1909_08390_amd import workloads as W
 
-    tubes = W.batch_tubes(args.tubes, seed=args.seed)
+    tubes = W.batch_tubes(args.tubes, seed=args.seed, nx_range=tuple(args.tube_nx))
     specs = [I.TubeSpec(nx=t.nx, K=t.K, lx=1.0, tau=t.tau, dt=W.tube_dt(t.nx)) for t in tubes]
     storage = I.F64 if args.batch_f64 else I.F32
     b = I.Batch(specs, 8, 8, storage)
     f = [W.tube_fields(t) for t in tubes]
     b.set_equilibrium([x[0] for x in f], [x[1] for x in f], [x[2] for x in f])
-    tune = b.tune(5)
-    log(f"bench: batch tuner ms/step {tune}, chosen {b.tiling()}")
+    tune = b.tune(args.tune_steps)
+    plan = b.plan()
+    log(f"bench: batch tuner ms/step {tune}, chosen {plan}")
     if args.warmup:
         b.step(args.warmup)
     torch.cuda.synchronize()
@@ -527,9 +528,21 @@ def run_batch(args):
     vn = cells * 16
     elem = 4 if storage == I.F32 else 8
     pb = batch_pass_bytes(vn, elem)
-    per = {k: ms[i] / args.steps for i, k in enumerate(("stage3", "stage4", "stage5"))}
-    gbs4 = pb["stage4"] / (per["stage4"] * 1e-3) / 1e9
+    step_ms = float(ms.sum()) / args.steps
+    step_bytes = sum(pb.values())
+    if plan.mode == 0:
+        per = {k: ms[i] / args.steps for i, k in enumerate(("stage3", "stage4", "stage5"))}
+        gbs4 = pb["stage4"] / (per["stage4"] * 1e-3) / 1e9
+        rkernel, rbytes = "stage4 (stage1d_batch_kernel)", pb["stage4"]
+    else:
+        # one launch covers whole steps: the roofline of the persistent
+        # kernel over a launch is the step's bytes over the step's time
+        per = {"persistent_step": step_ms}
+        gbs4 = step_bytes / (step_ms * 1e-3) / 1e9
+        rkernel, rbytes = f"stage1d_persist_kernel ({plan.steps} steps per launch)", step_bytes * plan.steps
     value = vn * args.steps / wall
+    best0 = min(v for k, v in tune.items() if k.mode == 0)
+    best1 = min(v for k, v in tune.items() if k.mode == 1)
     cache_gbs = hbm_copy_rate(I, CACHE_PROBE_BYTES)
     log(f"bench: 64 MiB device copy (cache-resident) {cache_gbs:.0f} GB/s")
     cpu = None
@@ -558,14 +571,19 @@ def run_batch(args):
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 storage, f64 moments" if elem == 4 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{len(tubes)} batched 1D shock tubes, Nx 256..4096 (sum {cells}), "
+        "config": {"workload": f"{len(tubes)} batched 1D shock tubes, Nx {args.tube_nx[0]}..{args.tube_nx[1]} "
+                               f"(sum {cells}), "
                                "K in {0,2}, tau 1e-6..1e-2, 8+8 velocities, CFL 0.5, outflow",
                    "cells": cells, "planes": 16, "seed": args.seed,
-                   "tiling": {"tile": b.tiling()[0], "order": b.tiling()[1]},
-                   "tuner_ms_per_step": {f"{k[0]},{k[1]}": v for k, v in tune.items()}},
-        "roofline": {"bound": "hbm", "kernel": "stage4 (stage1d_batch_kernel)", "achieved": gbs4,
+                   "plan": {"mode": "persistent" if plan.mode else "per-pass launches", "tile": plan.tile,
+                            "order": plan.order, "chunk": plan.chunk, "steps_per_launch": plan.steps,
+                            "bins": plan.bins},
+                   "tuner_ms_per_step": {f"mode{k.mode} tile{k.tile} order{k.order} chunk{k.chunk} "
+                                         f"steps{k.steps} bins{k.bins}": v for k, v in tune.items()},
+                   "tuner_best_ms_per_step": {"per_pass_launches": best0, "persistent": best1}},
+        "roofline": {"bound": "hbm", "kernel": rkernel, "achieved": gbs4,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs4 / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": pb["stage4"],
+                     "traffic": None, "algorithmic_bytes_per_launch": rbytes,
                      "note": "working set (~%.0f MB) fits the 256 MB last-level cache"
                              % ((b.state.numel() * elem * 3) / 1e6),
                      "cache_copy_gbs": cache_gbs, "frac_of_cache_copy": gbs4 / cache_gbs},
@@ -655,6 +673,10 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--tubes", type=int, default=256)
     ap.add_argument("--batch-f64", action="store_true")
+    ap.add_argument("--tube-nx", type=int, nargs=2, default=[256, 4096], metavar=("LO", "HI"),
+                    help="range of the batched tubes' cell counts")
+    ap.add_argument("--tune-steps", type=int, default=8,
+                    help="steps per plan timed by the batch autotuner")
     args = ap.parse_args()
 
     if args.summarize_stats:

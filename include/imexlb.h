@@ -239,10 +239,19 @@ const char* imexlb_last_error(const imexlb_ctx* ctx);
  *
  * Every tube is a d = 1 problem of the model above with its own cell count,
  * length, K (so its own adiabatic index, Sec. II), tau, dt and boundary
- * rule; all tubes share one velocity quadrature and one storage type.  One
- * IMEX step of the whole batch is three launches (one per fused pass), each
- * covering every tile of every tube; the tile width is chosen by
- * imexlb_batch_tune() or set directly.
+ * rule; all tubes share one velocity quadrature and one storage type.  The
+ * batch runs under one of imexlb_batch_plan_count() execution plans, chosen
+ * by imexlb_batch_tune() or set directly:
+ *  - per-pass launches (mode 0): one IMEX step is three launches, one per
+ *    fused pass, each covering every tile of every tube;
+ *  - persistent launches (mode 1): one launch covers up to `steps` whole
+ *    steps.  Each work-group owns a bin of items, a tube or a chunk of an
+ *    outflow tube longer than `chunk` cells, and separates the passes with
+ *    work-group barriers only; a chunk is stepped over its cells extended
+ *    by 15 cells per step on each side (three passes of the 5-cell MP-9
+ *    reach, Sec. IV), at most `chunk` cells in all, so the results are
+ *    those of the whole tube.
+ * Every plan gives bitwise the same results.
  *
  * Layout.  Tube i's plane-set starts at element state_offset[i] of the
  * state buffer (multiples of 64 elements) and holds Q planes of nx_i cells,
@@ -270,9 +279,10 @@ imexlb_status imexlb_batch_create(const imexlb_tube* tubes, int count, int q_phi
 void imexlb_batch_destroy(imexlb_batch* b);
 imexlb_status imexlb_batch_set_stream(imexlb_batch* b, void* hip_stream);
 
-/* Sizes in bytes of the state and workspace buffers, the total cell count
- * and the per-tube offsets (host arrays of count elements, either may be
- * NULL). */
+/* Sizes in bytes of the state and workspace buffers (the workspace holds the
+ * stage and moment buffers and the private areas of the persistent plans),
+ * the total cell count and the per-tube offsets (host arrays of count
+ * elements, either may be NULL). */
 size_t imexlb_batch_state_bytes(const imexlb_batch* b);
 size_t imexlb_batch_workspace_bytes(const imexlb_batch* b);
 long long imexlb_batch_cells(const imexlb_batch* b);
@@ -290,7 +300,8 @@ imexlb_status imexlb_batch_state_changed(imexlb_batch* b);
 
 /* nsteps IMEX steps of every tube (each with its own dt).  Asynchronous.
  * The timed form synchronises and adds the milliseconds of passes 3, 4, 5
- * (HIP events around each batched launch) to ms[0..2]. */
+ * (HIP events around each batched launch) to ms[0..2]; under a persistent
+ * plan the passes share launches, and the whole time goes to ms[0]. */
 imexlb_status imexlb_batch_step(imexlb_batch* b, int nsteps);
 imexlb_status imexlb_batch_step_timed(imexlb_batch* b, int nsteps, double ms[3]);
 
@@ -298,18 +309,31 @@ imexlb_status imexlb_batch_step_timed(imexlb_batch* b, int nsteps, double ms[3])
  * imexlb_batch_cells() doubles. */
 imexlb_status imexlb_batch_moments(const imexlb_batch* b, double* d_n, double* d_u, double* d_T);
 
-/* Tile width (cells per work-group: 256, 512 or 1024) and tile order
- * (0: tube by tube, 1: longest tubes first) of the batched launches. */
+/* Execution plans.  imexlb_batch_plan_info writes info[0..5] = mode (0
+ * per-pass launches, 1 persistent), tile (cells per tile: 256, 512 or 1024;
+ * work-groups of tile/4 threads), order (mode 0: 0 tube by tube, 1 longest
+ * tubes first; mode 1: 1), chunk (mode 1: outflow tubes longer than this
+ * are split into chunks whose extended regions hold at most this many
+ * cells), steps (mode 1: steps per launch) and bins (mode 1: at most
+ * this many work-groups, items assigned longest first to the least-loaded
+ * one); EINVAL for a plan outside [0, imexlb_batch_plan_count()). */
+int imexlb_batch_plan_count(void);
+imexlb_status imexlb_batch_plan_info(int plan, int info[6]);
+imexlb_status imexlb_batch_set_plan(imexlb_batch* b, int plan);
+int imexlb_batch_get_plan(const imexlb_batch* b);
+
+/* The per-pass plan with this tile width (cells per work-group: 256, 512 or
+ * 1024) and tile order (0: tube by tube, 1: longest tubes first); the tile
+ * width and order of the current plan. */
 imexlb_status imexlb_batch_set_tiling(imexlb_batch* b, int tile, int order);
 imexlb_status imexlb_batch_get_tiling(const imexlb_batch* b, int* tile, int* order);
 
-/* Autotuner: time every (tile, order) candidate over nsteps steps (after one
- * untimed step) on the current state and keep the fastest.  The state and
- * its moments are saved first and restored after each candidate, so the
- * call leaves them unchanged; it allocates and frees a device copy of them.
- * ms_out (optional, host, 6 values) receives the time per step of each
- * candidate in the order (256,0) (256,1) (512,0) (512,1) (1024,0) (1024,1).
- * Requires a bound state.  Synchronises. */
+/* Autotuner: time every plan over nsteps steps (after one untimed step) on
+ * the current state and keep the fastest.  The state and its moments are
+ * saved first and restored after each plan, so the call leaves them
+ * unchanged; it allocates and frees a device copy of them.  ms_out
+ * (optional, host, imexlb_batch_plan_count() values) receives the time per
+ * step of each plan in plan order.  Requires a bound state.  Synchronises. */
 imexlb_status imexlb_batch_tune(imexlb_batch* b, int nsteps, double* ms_out);
 
 const char* imexlb_batch_last_error(const imexlb_batch* b);

@@ -172,6 +172,35 @@ hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, cons
 hipError_t launch_stage1d_batch(bool f32, int kind, int qm, int tile, const StageArgs* targs,
                                 const int2* tiles, int ntiles, hipStream_t s);
 
+// Persistent batched steps (temporal blocking).  An item is a tube, or a
+// chunk [own0, own1) of an outflow tube, stepped over the region
+// [r0, r0 + len) of tube cells in a private area; its pass arguments
+// (iargs[3 item + 0..2], passes 3, 4, 5) point into that area, with the
+// region as the line (nx = len) and the private plane and moment strides.
+struct PersistItem {
+    long long soff;   // tube's first state element in the global buffers
+    long long coff;   // tube's first cell in the global moment fields
+    int nx;           // tube length (plane stride of the global state)
+    int r0, len;      // region, in tube cells
+    int own0, own1;   // cells this item writes back, in tube cells
+    int pad;
+};
+// Global buffers of one launch: the state and moments are read from *_in
+// and the items' own cells written to *_out (distinct buffers).
+struct PersistIO {
+    const void* f_in;
+    void* f_out;
+    const double* m_in;
+    double* m_out;
+    long long ctot;   // field stride of the global moments
+    int nplanes;
+};
+// One launch of nsteps whole steps: block b owns the items
+// bin_items[bin_start[b] .. bin_start[b + 1]).
+hipError_t launch_stage1d_persist(bool f32, int qm, int tile, const StageArgs* iargs, const PersistItem* items,
+                                  const int* bin_start, const int* bin_items, int nbins, const PersistIO& io,
+                                  int nsteps, hipStream_t s);
+
 // Tile shapes (cells) used by the stage kernels: 2D tiles of kTile2X x
 // kTile2Y cells, kOwn2 consecutive cells per thread (kTile2X kTile2Y / kOwn2
 // threads).  32 x 16 keeps one FP64 work-group under 80 KB of LDS, so two

@@ -1206,11 +1206,11 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
     }
 }
 
-// interior tiles of a line whose length is a multiple of 4 take the
-// vector-access body, tiles at a ragged end the element-wise one
+// interior tiles of a line whose planes start at multiples of 4 elements
+// take the vector-access body, tiles at a ragged end the element-wise one
 template <typename S, int KIND, int QM, int TX, typename A>
 __device__ __forceinline__ void stage1d_tile(const A& a, int x0, S (*tile)[TX + 10]) {
-    if ((x0 + TX <= a.nx) && (a.nx % 4 == 0)) stage1d_body<S, KIND, QM, TX, true>(a, x0, tile);
+    if ((x0 + TX <= a.nx) && (a.plane_stride % 4 == 0)) stage1d_body<S, KIND, QM, TX, true>(a, x0, tile);
     else stage1d_body<S, KIND, QM, TX, false>(a, x0, tile);
 }
 
@@ -1234,6 +1234,74 @@ stage1d_batch_kernel(const StageArgs* targs, const int2* tiles, int ntiles) {
     const int IMEXLB_CONST* tp = (const int IMEXLB_CONST*)tiles + 2 * blockIdx.x;
     CArgs& a = ((CArgs*)targs)[tp[0]];
     stage1d_tile<S, KIND, QM, TX>(a, tp[1], tile);
+}
+
+// Persistent batched form (temporal blocking).  Block b owns a bin of
+// items (tubes, or chunks of outflow tubes) for nsteps whole steps.  An
+// item's region extends its own cells by 15 cells per step on each side
+// (clamped to the tube): a pass's stencil reaches 5 cells, so the values
+// that the clamped ghost nodes at an artificial region end make wrong
+// spread 5 cells per pass and stay outside the own cells for the whole
+// launch; at a true tube end the clamp is the outflow rule.  Each item's
+// state and moments are copied into its private area, stepped there (the
+// passes of all items of the bin, with a work-group barrier after every
+// tile, which also separates the passes), and the own cells copied out to
+// buffers distinct from the inputs, so that no block overwrites cells
+// another block still reads.  No block waits for another.
+template <typename S, int KIND, int QM, int TX>
+__device__ __forceinline__ void persist_pass(const StageArgs* iargs, const int* bin_items, int j0, int j1,
+                                             int k, S (*tile)[TX + 10]) {
+    for (int j = j0; j < j1; ++j) {
+        CArgs& a = ((CArgs*)iargs)[3 * bin_items[j] + k];
+        const int len = a.nx;
+        for (int x0 = 0; x0 < len; x0 += TX) {
+            stage1d_tile<S, KIND, QM, TX>(a, x0, tile);
+            __syncthreads();
+        }
+    }
+}
+
+template <typename S, int QM, int TX>
+__global__ void __launch_bounds__(TX / 4) __attribute__((amdgpu_waves_per_eu(2)))
+stage1d_persist_kernel(const StageArgs* iargs, const PersistItem* items, const int* bin_start,
+                       const int* bin_items, PersistIO io, int nsteps) {
+    __shared__ S tile[2][TX + 10];
+    constexpr int NT = TX / 4;
+    const int j0 = bin_start[blockIdx.x], j1 = bin_start[blockIdx.x + 1];
+    const int P = io.nplanes;
+    for (int j = j0; j < j1; ++j) {
+        const int it = bin_items[j];
+        const PersistItem m = items[it];
+        S* Fp = static_cast<S*>(iargs[3 * it + 1].fbuf);
+        double* Mp = iargs[3 * it + 2].mout;
+        const long long ps = iargs[3 * it].plane_stride, ms = iargs[3 * it].mstride;
+        const S* fi = static_cast<const S*>(io.f_in) + m.soff + m.r0;
+        for (int v = 0; v < P; ++v)
+            for (int x = threadIdx.x; x < m.len; x += NT) Fp[v * ps + x] = fi[(long long)v * m.nx + x];
+        const double* mi = io.m_in + m.coff + m.r0;
+        for (int f = 0; f < 3; ++f)
+            for (int x = threadIdx.x; x < m.len; x += NT) Mp[f * ms + x] = mi[f * io.ctot + x];
+    }
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+        persist_pass<S, kStage3, QM, TX>(iargs, bin_items, j0, j1, 0, tile);
+        persist_pass<S, kStage4, QM, TX>(iargs, bin_items, j0, j1, 1, tile);
+        persist_pass<S, kStage5, QM, TX>(iargs, bin_items, j0, j1, 2, tile);
+    }
+    for (int j = j0; j < j1; ++j) {
+        const int it = bin_items[j];
+        const PersistItem m = items[it];
+        const S* Fp = static_cast<const S*>(iargs[3 * it + 1].fbuf);
+        const double* Mp = iargs[3 * it + 2].mout;
+        const long long ps = iargs[3 * it].plane_stride, ms = iargs[3 * it].mstride;
+        S* fo = static_cast<S*>(io.f_out) + m.soff;
+        const int b = m.own0 - m.r0, n = m.own1 - m.own0;
+        for (int v = 0; v < P; ++v)
+            for (int x = threadIdx.x; x < n; x += NT) fo[(long long)v * m.nx + m.own0 + x] = Fp[v * ps + b + x];
+        double* mo = io.m_out + m.coff + m.own0;
+        for (int f = 0; f < 3; ++f)
+            for (int x = threadIdx.x; x < n; x += NT) mo[f * io.ctot + x] = Mp[f * ms + b + x];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1364,6 +1432,33 @@ hipError_t launch_stage1d_batch(bool f32, int kind, int qm, int tile, const Stag
         case kStage5: return f32 ? launch_batch_q<float, kStage5>(qm, tile, targs, tiles, ntiles, s) : launch_batch_q<double, kStage5>(qm, tile, targs, tiles, ntiles, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+namespace {
+
+template <typename S, int QM>
+hipError_t launch_persist_t(int tile, const StageArgs* iargs, const PersistItem* items, const int* bin_start,
+                            const int* bin_items, int nbins, const PersistIO& io, int nsteps, hipStream_t s) {
+    switch (tile) {
+        case 256: hipLaunchKernelGGL((stage1d_persist_kernel<S, QM, 256>), dim3(nbins), dim3(64), 0, s, iargs, items, bin_start, bin_items, io, nsteps); break;
+        case 512: hipLaunchKernelGGL((stage1d_persist_kernel<S, QM, 512>), dim3(nbins), dim3(128), 0, s, iargs, items, bin_start, bin_items, io, nsteps); break;
+        case 1024: hipLaunchKernelGGL((stage1d_persist_kernel<S, QM, 1024>), dim3(nbins), dim3(256), 0, s, iargs, items, bin_start, bin_items, io, nsteps); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stage1d_persist(bool f32, int qm, int tile, const StageArgs* iargs, const PersistItem* items,
+                                  const int* bin_start, const int* bin_items, int nbins, const PersistIO& io,
+                                  int nsteps, hipStream_t s) {
+    if (nbins <= 0 || nsteps <= 0) return hipSuccess;
+    if (f32)
+        return qm == 16 ? launch_persist_t<float, 16>(tile, iargs, items, bin_start, bin_items, nbins, io, nsteps, s)
+                        : launch_persist_t<float, 8>(tile, iargs, items, bin_start, bin_items, nbins, io, nsteps, s);
+    return qm == 16 ? launch_persist_t<double, 16>(tile, iargs, items, bin_start, bin_items, nbins, io, nsteps, s)
+                    : launch_persist_t<double, 8>(tile, iargs, items, bin_start, bin_items, nbins, io, nsteps, s);
 }
 
 hipError_t launch_init_equilibrium(int d, bool f32, const DevTables* tab, const double* n,

@@ -40,6 +40,30 @@ class CTube(ctypes.Structure):
 BATCH_TILINGS = [(256, 0), (256, 1), (512, 0), (512, 1), (1024, 0), (1024, 1)]
 
 
+@dataclass(frozen=True)
+class BatchPlan:
+    """One execution plan of a batch (``imexlb_batch_plan_info``)."""
+    index: int
+    mode: int    # 0: per-pass launches, 1: persistent launches
+    tile: int
+    order: int
+    chunk: int
+    steps: int
+    bins: int
+
+
+def batch_plans():
+    """Every execution plan the library offers, in plan order."""
+    L = lib()
+    out = []
+    for i in range(L.imexlb_batch_plan_count()):
+        info = (ctypes.c_int * 6)()
+        if L.imexlb_batch_plan_info(i, info) != OK:
+            raise ImexlbError(EINVAL, f"plan {i}")
+        out.append(BatchPlan(i, *list(info)))
+    return out
+
+
 class ImexlbError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"imexlb status {status}: {msg}")
@@ -115,6 +139,10 @@ def lib():
         L.imexlb_batch_get_tiling.argtypes = [_vp, ctypes.POINTER(ctypes.c_int),
                                               ctypes.POINTER(ctypes.c_int)]
         L.imexlb_batch_tune.argtypes = [_vp, ctypes.c_int, _dp]
+        L.imexlb_batch_plan_count.argtypes = []
+        L.imexlb_batch_plan_info.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.imexlb_batch_set_plan.argtypes = [_vp, ctypes.c_int]
+        L.imexlb_batch_get_plan.argtypes = [_vp]
         L.imexlb_batch_last_error.argtypes = [_vp]
         L.imexlb_batch_last_error.restype = ctypes.c_char_p
         L.imexlb_copy_probe.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp, _dp]
@@ -542,9 +570,19 @@ class Batch:
                     "batch_get_tiling")
         return t.value, o.value
 
+    def set_plan(self, plan):
+        """Execution plan by index or BatchPlan."""
+        idx = plan.index if isinstance(plan, BatchPlan) else int(plan)
+        self._check(self.L.imexlb_batch_set_plan(self._h, idx), "batch_set_plan")
+
+    def plan(self) -> BatchPlan:
+        return batch_plans()[self.L.imexlb_batch_get_plan(self._h)]
+
     def tune(self, nsteps: int = 5):
-        """Autotune the tiling; returns {(tile, order): ms per step}."""
-        ms = np.zeros(len(BATCH_TILINGS))
+        """Autotune over every plan; returns {BatchPlan: ms per step} and
+        leaves the fastest plan set."""
+        plans = batch_plans()
+        ms = np.zeros(len(plans))
         self._check(self.L.imexlb_batch_tune(self._h, int(nsteps), ms.ctypes.data_as(_dp)),
                     "batch_tune")
-        return dict(zip(BATCH_TILINGS, ms.tolist()))
+        return dict(zip(plans, ms.tolist()))

@@ -1,12 +1,16 @@
-"""Batched 1D passes: many shock tubes of uneven size, K, tau and dt in one
-launch per pass, through the C ABI.
+"""Batched 1D tubes: many shock tubes of uneven size, K, tau and dt,
+through the C ABI, under every execution plan (per-pass launches, and
+persistent launches of several steps with long outflow tubes split into
+chunks stepped over extended regions).
 
  * every tube matches the FP64 oracle stepping that tube alone (1e-12 of the
    reference's infinity norm), for uneven and ragged sizes, K = 0 and 2,
    outflow and periodic ends;
- * every tiling (tile width and order) gives results bitwise equal to the
-   single-grid 1D path, in FP64 and FP32 storage;
- * the autotuner times all tilings and leaves state and moments unchanged;
+ * every plan gives results bitwise equal to the single-grid 1D path, in
+   FP64 and FP32 storage, over 11 steps (odd and even launch counts, a
+   shorter last launch, a 4096-cell outflow tube split into 2 or 4 chunks, a
+   3001-cell periodic tube kept whole);
+ * the autotuner times all plans and leaves state and moments unchanged;
  * the full 256-tube workload (seeded, FP32 storage) stays physical and, on
    sampled tubes, agrees with the FP64 run and with the oracle.
 """
@@ -35,7 +39,7 @@ def spec_of(t: W.Tube, bc=I.OUTFLOW) -> I.TubeSpec:
 def mixed_tubes():
     """Uneven sizes (ragged, below one tile, several tiles), K 0/2, both ends."""
     rng = np.random.Generator(np.random.PCG64(7))
-    sizes = [37, 256, 300, 1030, 2049, 613, 4, 1024]
+    sizes = [37, 256, 300, 1030, 2049, 613, 4, 1024, 3001, 4096]
     out = []
     for i, nx in enumerate(sizes):
         K = [0, 2][i % 2]
@@ -46,7 +50,7 @@ def mixed_tubes():
     return out
 
 
-def run_batch(tubes_bc, storage, steps, tiling=None):
+def run_batch(tubes_bc, storage, steps, tiling=None, plan=None):
     torch = _torch()
     specs = [spec_of(t, bc) for t, bc in tubes_bc]
     b = I.Batch(specs, 8, 8, storage)
@@ -54,6 +58,8 @@ def run_batch(tubes_bc, storage, steps, tiling=None):
     b.set_equilibrium([x[0] for x in f], [x[1] for x in f], [x[2] for x in f])
     if tiling is not None:
         b.set_tiling(*tiling)
+    if plan is not None:
+        b.set_plan(plan)
     b.step(steps)
     torch.cuda.synchronize()
     return b
@@ -79,10 +85,11 @@ def test_every_tube_matches_the_oracle():
 
 
 @pytest.mark.parametrize("storage", [I.F64, I.F32])
-def test_every_tiling_equals_the_single_grid_path(storage):
+def test_every_plan_equals_the_single_grid_path(storage):
     torch = _torch()
     tubes = mixed_tubes()
-    ref = []
+    steps = 11
+    ref, mref = [], []
     for t, bc in tubes:
         s = spec_of(t, bc)
         c = I.Config(d=1, nx=t.nx, q_phi=8, q_chi=8, K=t.K, tau=s.tau, dt=s.dt, bc_x=bc,
@@ -90,17 +97,28 @@ def test_every_tiling_equals_the_single_grid_path(storage):
         sol = I.Solver(c)
         fn, fu, fT = W.tube_fields(t)
         sol.set_equilibrium(fn, fu, None, fT)
-        sol.step(4)
+        sol.step(steps)
         torch.cuda.synchronize()
         ref.append(sol.state.cpu().numpy())
-    for tiling in I.BATCH_TILINGS:
-        b = run_batch(tubes, storage, 4, tiling)
+        n, u, _, T = sol.moments()
+        mref.append((n.cpu().numpy(), u.cpu().numpy(), T.cpu().numpy()))
+    plans = I.batch_plans()
+    assert any(p.mode == 1 and p.chunk < 4096 for p in plans)
+    for plan in plans:
+        print(f"plan {plan}", flush=True)
+        b = run_batch(tubes, storage, steps, plan=plan)
+        assert b.plan() == plan
+        n, u, T = [x.cpu().numpy() for x in b.moments()]
         for i in range(len(tubes)):
             got = b.tube_state(i).cpu().numpy()
-            assert np.array_equal(got, ref[i]), f"tiling {tiling}, tube {i}"
+            assert np.array_equal(got, ref[i]), f"plan {plan}, tube {i}"
+            sl = slice(b.cell_offset[i], b.cell_offset[i] + tubes[i][0].nx)
+            for a, r in zip((n[sl], u[sl], T[sl]), mref[i]):
+                assert np.array_equal(a, r), f"plan {plan}, tube {i} moments"
+        del b
 
 
-def test_tuner_times_every_tiling_and_keeps_the_state():
+def test_tuner_times_every_plan_and_keeps_the_state():
     torch = _torch()
     tubes = [(t, I.OUTFLOW) for t in W.batch_tubes(32, seed=3)]
     b = run_batch(tubes, I.F32, 2)
@@ -108,8 +126,8 @@ def test_tuner_times_every_tiling_and_keeps_the_state():
     m0 = [x.clone() for x in b.moments()]
     times = b.tune(3)
     torch.cuda.synchronize()
-    assert set(times) == set(I.BATCH_TILINGS) and all(v > 0 for v in times.values())
-    assert b.tiling() == min(times, key=times.get)
+    assert set(times) == set(I.batch_plans()) and all(v > 0 for v in times.values())
+    assert b.plan() == min(times, key=times.get)
     bits = torch.int32 if b.state_dtype == torch.float32 else torch.int64
     for i in range(len(tubes)):
         assert torch.equal(b.tube_state(i).view(bits), before[i].view(bits)), f"tube {i}"
