@@ -99,9 +99,9 @@ __device__ __forceinline__ R minmod4(R a, R b, R c, R d) {
 // F_{s+1} - F_s, 4 (F_s - F_{s-1})), so the monotonicity test
 // (F^L - F_s)(F^L - F^MP) <= 0 needs no median.  When it fails the face is
 // F^L clipped to [F^min, F^max] built from the M4 curvatures.  The clipping
-// work is kept inside its branch (opaque copies of its inputs stop the
-// compiler from hoisting the shared curvatures of neighbouring faces), so a
-// wavefront none of whose lanes needs it skips it.
+// work is kept inside its branch (the caller passes opaque copies of its
+// inputs, so the compiler cannot hoist it), and a wavefront none of whose
+// lanes needs it skips it.
 template <typename R>
 __device__ __forceinline__ void opaque(R& x) {
     asm volatile("" : "+v"(x));
@@ -127,27 +127,27 @@ __device__ __forceinline__ R mp9_face_linear(const R (&dd)[8], R fs, R& t, R& q)
     return fma(s, inv, fs);
 }
 
-// The clipped face value: F^L limited to [F^min, F^max].
+// M4 limit between two curvatures: minmod4(4 a - b, 4 b - a, a, b), the
+// d^M4 of the F^LC and F^MD bounds (a = C_{s-1}, b = C_s gives the limit at
+// s - 1/2; a = C_s, b = C_{s+1} the one at s + 1/2).
 template <typename R>
-__device__ __forceinline__ R mp9_face_clip(const R (&dd)[8], R fs, R fp, R t, R fl) {
-    R dm2 = dd[2], dm1 = dd[3], d0 = dd[4], dp1 = dd[5], f = fs, g = fp, u = t;
-    opaque(dm2);
-    opaque(dm1);
-    opaque(d0);
-    opaque(dp1);
-    opaque(f);
-    opaque(g);
-    opaque(u);
-    const R cm = dm1 - dm2, c0 = d0 - dm1, cp = dp1 - d0;    // curvatures at s-1, s, s+1
-    const R mdm = minmod4(fma(R(4), cm, -c0), fma(R(4), c0, -cm), cm, c0);  // d^M4 at s-1/2
-    const R md0 = minmod4(fma(R(4), c0, -cp), fma(R(4), cp, -c0), c0, cp);  // d^M4 at s+1/2
+__device__ __forceinline__ R mp9_m4(R a, R b) {
+    return minmod4(fma(R(4), a, -b), fma(R(4), b, -a), a, b);
+}
+
+// F^L limited to [F^min, F^max] from the face's nodes F_s, F_{s+1}, t =
+// F^UL - F_s, the differences dm1 = F_s - F_{s-1} and d0 = F_{s+1} - F_s,
+// and the M4 limits at s - 1/2 (mlo) and s + 1/2 (mhi).
+template <typename R>
+__device__ __forceinline__ R mp9_face_bound(R f, R g, R u, R dm1, R d0, R mlo, R mhi, R fl) {
     const R ul = f + u;
-    const R lc = fma(R(4.0 / 3.0), mdm, fma(R(0.5), dm1, f));
-    const R md = fma(R(0.5), d0 - md0, f);
+    const R lc = fma(R(4.0 / 3.0), mlo, fma(R(0.5), dm1, f));
+    const R md = fma(R(0.5), d0 - mhi, f);
     const R lo = fmax(min3(f, g, md), min3(f, ul, lc));   // F^min <= F_s
     const R hi = fmin(max3(f, g, md), max3(f, ul, lc));   // F^max >= F_s
     return clamp(fl, lo, hi);
 }
+
 
 }  // namespace
 }  // namespace imexlb

@@ -52,18 +52,37 @@ __device__ __forceinline__ void mp9_line(const R (&w)[L + 9], R (&dif)[L]) {
     }
     // one branch for the whole line, skipped by every wavefront none of whose
     // lanes needs a clip (the common case in smooth regions); inside it each
-    // face takes its clipped value where its test fails
+    // face takes its clipped value where its test fails.  Neighbouring faces
+    // share curvatures and M4 limits (the limit at s + 1/2 of face i is the
+    // one at s - 1/2 of face i + 1), so the line evaluates L + 3 curvatures
+    // and L + 2 limits instead of three and two per face.
     bool any = false;
 #pragma unroll
     for (int i = 0; i <= L; ++i) any |= q[i] > R(0);
     if (any) {
+        // opaque copies keep this work inside the branch
+        R e[L + 4], f[L + 2];
+#pragma unroll
+        for (int j = 0; j < L + 4; ++j) {
+            e[j] = d[j + 2];
+            opaque(e[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < L + 2; ++j) {
+            f[j] = w[j + 4];
+            opaque(f[j]);
+        }
+        // e[j] = d[j + 2]: face i reads d[i + 2 .. i + 5] = e[i .. i + 3]
+        R c0 = e[2] - e[1];                          // curvature at s of face 0
+        R mlo = mp9_m4<R>(e[1] - e[0], c0);          // M4 limit at s - 1/2 of face 0
 #pragma unroll
         for (int i = 0; i <= L; ++i) {
-            R dd[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) dd[k] = d[i + k];
-            const R c = mp9_face_clip<R>(dd, w[i + 4], w[i + 5], t[i], fl[i]);
+            const R cp = e[i + 3] - e[i + 2];        // curvature at s + 1
+            const R mhi = mp9_m4<R>(c0, cp);         // M4 limit at s + 1/2
+            const R c = mp9_face_bound<R>(f[i], f[i + 1], t[i], e[i + 1], e[i + 2], mlo, mhi, fl[i]);
             fl[i] = q[i] > R(0) ? c : fl[i];
+            c0 = cp;
+            mlo = mhi;
         }
     }
 #pragma unroll
