@@ -352,37 +352,49 @@ __device__ __forceinline__ void adj_stream(const double* F, const Lin4& dA, size
     }
 }
 
-// x lines, wave-cooperative: one 64-lane work-group per chunk of kChunk
-// nodes of a row.  Lane l evaluates face s = c0 - 4 + l (flow to +x; else
-// c0 - 5 + l), the 64 faces whose stencils read the chunk's nodes, with
-// coalesced window loads, and writes its nine weighted Jacobian entries to
-// LDS; node c0 + i then gathers the nine entries addressed to it (from lanes
-// i + 8 - k, or i + k for flow to -x).  The end nodes of an outflow row also
-// collect the entries at ghost positions.
+// x lines, wave-cooperative: one wavefront per chunk of kChunk nodes of a
+// row, kChunkWaves chunks per work-group.  Lane l evaluates face
+// s = c0 - 4 + l (flow to +x; else c0 - 5 + l), the 64 faces whose stencils
+// read the chunk's nodes, with coalesced window loads, and writes its nine
+// weighted Jacobian entries to LDS; node c0 + i then gathers the nine
+// entries addressed to it (from lanes i + 8 - k, or i + k for flow to -x).
+// The end nodes of an outflow row also collect the entries at ghost
+// positions.
 constexpr int kChunk = 56;
 
 __device__ __forceinline__ int chunk_pos(bool fwd, int c0, int lane, int kk) {  // node index written by (lane, kk)
     return fwd ? c0 - 8 + lane + kk : c0 + lane - kk;
 }
 
-__global__ void __launch_bounds__(64) advect_adjoint_xchunk_kernel(const DevTables* __restrict__ tabp,
-                                                                   const double* __restrict__ F, Lin4 dA,
-                                                                   double* out, int nx, int ny, int bc,
-                                                                   double inv_dx, int accumulate) {
-    __shared__ double contrib[9 * 64];
-    __shared__ double sF[72], sA[72];  // F at nodes c0-8 .. c0+63, dA at c0-5 .. c0+66
+// Chunks per work-group of the x-row kernel: one per wavefront.
+constexpr int kChunkWaves = 4;
+
+__global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel(const DevTables* __restrict__ tabp,
+                                                                                 const double* __restrict__ F,
+                                                                                 Lin4 dA, double* out, int nx, int ny,
+                                                                                 int bc, double inv_dx,
+                                                                                 int accumulate) {
+    // per wavefront: F at nodes c0-8 .. c0+63, dA at c0-5 .. c0+66, and the
+    // 9 x 64 weighted Jacobian entries of its faces
+    __shared__ double contrib_all[kChunkWaves][9 * 64];
+    __shared__ double sF_all[kChunkWaves][72], sA_all[kChunkWaves][72];
     CTab* tab = (CTab*)tabp;
     const long long cells = (long long)nx * ny;
     const int v = blockIdx.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, n = nx;
+    double* contrib = contrib_all[wave];
+    double* sF = sF_all[wave];
+    double* sA = sA_all[wave];
     const int nch = (nx + kChunk - 1) / kChunk;
-    if ((long long)blockIdx.x >= (long long)nch * ny) return;
-    const int y = blockIdx.x / nch, c0 = (blockIdx.x % nch) * kChunk;
-    const int lane = threadIdx.x, n = nx;
+    const long long chunk = (long long)blockIdx.x * kChunkWaves + wave;
+    // a wavefront past the last chunk still takes part in the barriers
+    const bool live = chunk < (long long)nch * ny;
+    const int y = live ? (int)(chunk / nch) : 0, c0 = live ? (int)(chunk % nch) * kChunk : 0;
     const size_t base = (size_t)v * cells + (size_t)y * nx;
-    const double p = tab->plane[v].px;
+    const double p = tab->plane[v].px;  // one plane per work-group
     const int t = c0 + lane;
     if (p == 0.0) {
-        if (!accumulate && lane < kChunk && t < n) out[base + t] = 0.0;
+        if (live && !accumulate && lane < kChunk && t < n) out[base + t] = 0.0;
         return;
     }
     const bool fwd = p > 0.0;
@@ -391,24 +403,28 @@ __global__ void __launch_bounds__(64) advect_adjoint_xchunk_kernel(const DevTabl
         if (bc == 1) return lin_at(dA, base + (size_t)bc_map(j, n, 1));
         return (j >= 0 && j < n) ? lin_at(dA, base + (size_t)j) : 0.0;
     };
-    for (int i = lane; i < 72; i += 64) {
-        sF[i] = F[base + bc_map(c0 - 8 + i, n, bc)];
-        sA[i] = dat(c0 - 5 + i);
+    if (live) {
+        for (int i = lane; i < 72; i += 64) {
+            sF[i] = F[base + bc_map(c0 - 8 + i, n, bc)];
+            sA[i] = dat(c0 - 5 + i);
+        }
     }
     __syncthreads();
     // face s = c0 - 4 + lane (flow to +x) or c0 - 5 + lane: window nodes
     // s - 4 + kk = c0 - 8 + lane + kk, or s + 5 - kk = c0 + lane - kk
-    double w[9];
+    if (live) {
+        double w[9];
 #pragma unroll
-    for (int kk = 0; kk < 9; ++kk) w[kk] = sF[fwd ? lane + kk : lane + 8 - kk];
-    const int ia = lane + (fwd ? 1 : 0);  // sA index of node s
-    const double dface = p * inv_dx * (sA[ia] - sA[ia + 1]);
-    double J[9];
-    face_jacobian_row(w, J);
+        for (int kk = 0; kk < 9; ++kk) w[kk] = sF[fwd ? lane + kk : lane + 8 - kk];
+        const int ia = lane + (fwd ? 1 : 0);  // sA index of node s
+        const double dface = p * inv_dx * (sA[ia] - sA[ia + 1]);
+        double J[9];
+        face_jacobian_row(w, J);
 #pragma unroll
-    for (int kk = 0; kk < 9; ++kk) contrib[kk * 64 + lane] = J[kk] * dface;
+        for (int kk = 0; kk < 9; ++kk) contrib[kk * 64 + lane] = J[kk] * dface;
+    }
     __syncthreads();
-    if (lane < kChunk && t < n) {
+    if (live && lane < kChunk && t < n) {
         double val = 0.0;
 #pragma unroll
         for (int kk = 0; kk < 9; ++kk) val += contrib[kk * 64 + (fwd ? lane + 8 - kk : lane + kk)];
@@ -628,7 +644,9 @@ hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const
     }
     const int nyl = d == 2 ? ny : 1;
     const long long chx = (long long)((nx + kChunk - 1) / kChunk) * nyl;
-    hipLaunchKernelGGL(advect_adjoint_xchunk_kernel, dim3((unsigned)chx, (unsigned)nplanes), dim3(64), 0, s, tab, F, L, out, nx, nyl, bcx, inv_dx, (int)accumulate);
+    const long long gx = (chx + kChunkWaves - 1) / kChunkWaves;
+    hipLaunchKernelGGL(advect_adjoint_xchunk_kernel, dim3((unsigned)gx, (unsigned)nplanes), dim3(64 * kChunkWaves), 0, s,
+                       tab, F, L, out, nx, nyl, bcx, inv_dx, (int)accumulate);
     if (d == 2) {
         const long long segy = (long long)((ny + kAdjSeg - 1) / kAdjSeg) * nx;
         const dim3 gy((unsigned)((segy + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);

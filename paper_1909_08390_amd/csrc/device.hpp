@@ -143,8 +143,17 @@ __device__ __forceinline__ R mp9_face_bound(R f, R g, R u, R dm1, R d0, R mlo, R
     const R ul = f + u;
     const R lc = fma(R(4.0 / 3.0), mlo, fma(R(0.5), dm1, f));
     const R md = fma(R(0.5), d0 - mhi, f);
-    const R lo = fmax(min3(f, g, md), min3(f, ul, lc));   // F^min <= F_s
-    const R hi = fmin(max3(f, g, md), max3(f, ul, lc));   // F^max >= F_s
+    R lo, hi;  // F^min <= F_s <= F^max
+    if constexpr (sizeof(R) == 4) {
+        lo = fmax(min3(f, g, md), min3(f, ul, lc));
+        hi = fmin(max3(f, g, md), max3(f, ul, lc));
+    } else {
+        // without three-way FP64 min / max: max(min(F_s, A, B), min(F_s, C, D))
+        // = min(F_s, max(min(A, B), min(C, D))), min(F_s, .) being monotone
+        // (exact; four operations instead of five), and F^max likewise
+        lo = fmin(f, fmax(fmin(g, md), fmin(ul, lc)));
+        hi = fmax(f, fmin(fmax(g, md), fmax(ul, lc)));
+    }
     return clamp(fl, lo, hi);
 }
 
