@@ -72,19 +72,22 @@ __device__ __forceinline__ R clamp(R x, R lo, R hi) {
 }
 
 // Two-argument minmod: the signed smaller magnitude when both share a sign,
-// else 0; equal to the median of (0, a, b).
+// else 0; equal to the median of (0, a, b), i.e. 0 clamped to
+// [min(a, b), max(a, b)].
 template <typename R>
 __device__ __forceinline__ R minmod2(R a, R b) {
     if constexpr (sizeof(R) == 4) return __builtin_amdgcn_fmed3f(R(0), a, b);
-    else return fmax(fmin(a, b), R(0)) + fmin(fmax(a, b), R(0));
+    else return fmin(fmax(fmin(a, b), R(0)), fmax(a, b));
 }
 
-// Four-argument minmod: signed smallest magnitude when all share a sign.
+// Four-argument minmod: signed smallest magnitude when all share a sign,
+// else 0; equal to 0 clamped to [min, max] of the four arguments.
 template <typename R>
 __device__ __forceinline__ R minmod4(R a, R b, R c, R d) {
     const R mn = min3(a, b, fmin(c, d));
     const R mx = max3(a, b, fmax(c, d));
-    return fmax(mn, R(0)) + fmin(mx, R(0));
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_fmed3f(R(0), mn, mx);
+    else return fmin(fmax(mn, R(0)), mx);
 }
 
 // MP-9 interface value (Sec. IV) of the face between F_s and F_{s+1} for
