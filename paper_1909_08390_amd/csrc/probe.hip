@@ -35,7 +35,7 @@ extern "C" imexlb_status imexlb_copy_probe(const void* d_src, void* d_dst, size_
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess) return IMEXLB_EHIP;
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return IMEXLB_EHIP;
     }
     imexlb_status st = IMEXLB_OK;
@@ -52,8 +52,8 @@ extern "C" imexlb_status imexlb_copy_probe(const void* d_src, void* d_dst, size_
         if (st == IMEXLB_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = IMEXLB_EHIP;
         if (st == IMEXLB_OK && r > 0 && (best == 0.0f || ms < best)) best = ms;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != IMEXLB_OK) return st;
     *gbs = best > 0.0f ? 2.0 * (double)bytes / ((double)best * 1e-3) / 1e9 : 0.0;
     return IMEXLB_OK;
