@@ -213,7 +213,8 @@ imexlb_status imexlb_adjoint_step(imexlb_ctx* ctx, const void* d_Fn, const doubl
 
 /* dF = V^T dA: the transpose of the MP-9 advection operator of
  * imexlb_advect at the FP64 plane-set d_F (Sec. IV), for an FP64 plane-set
- * dA; the linearisation follows the limiter decisions at d_F. */
+ * dA; the linearisation follows the limiter decisions at d_F.  d_dF must not
+ * alias d_F or d_dA (EINVAL). */
 imexlb_status imexlb_advect_adjoint(const imexlb_ctx* ctx, const double* d_F, const double* d_dA,
                                     double* d_dF);
 

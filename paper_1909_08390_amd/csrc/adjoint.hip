@@ -64,172 +64,141 @@ __device__ __forceinline__ void herm_factor_d(CDp h, int Q, double u, double th,
 }
 
 // ---------------------------------------------------- clipped-face derivative
-// Index of the smallest / largest of four values, the first on ties (the
-// order the forward's nested min / max resolves them).
-__device__ __forceinline__ int argmin4(const double (&x)[4]) {
-    int i = 0;
-    if (x[1] < x[i]) i = 1;
-    if (x[2] < x[i]) i = 2;
-    if (x[3] < x[i]) i = 3;
-    return i;
-}
-__device__ __forceinline__ int argmax4(const double (&x)[4]) {
-    int i = 0;
-    if (x[1] > x[i]) i = 1;
-    if (x[2] > x[i]) i = 2;
-    if (x[3] > x[i]) i = 3;
-    return i;
-}
-
-// Four-argument minmod: the selected argument (0..3), or -1 for 0.
-__device__ __forceinline__ int minmod4_sel(const double (&x)[4], double& val) {
-    const int lo = argmin4(x), hi = argmax4(x);
-    if (x[lo] > 0.0) {
-        val = x[lo];
-        return lo;
-    }
-    if (x[hi] < 0.0) {
-        val = x[hi];
-        return hi;
-    }
-    val = 0.0;
-    return -1;
+// Selected argument of the four-argument minmod, as the weights (al, be) of
+// the two curvatures a, b in it: 4a - b -> (4, -1), 4b - a -> (-1, 4),
+// a -> (1, 0), b -> (0, 1), 0 -> (0, 0).  The smallest / largest argument is
+// the first one on ties, the order the forward's nested min / max resolves
+// them.
+__device__ __forceinline__ void minmod4_weights(double a, double b, double& al, double& be) {
+    const double x0 = fma(4.0, a, -b), x1 = fma(4.0, b, -a);
+    // argmin and argmax over (x0, x1, a, b), first on ties
+    double vmin = x0, vmax = x0, amin = 4.0, bmin = -1.0, amax = 4.0, bmax = -1.0;
+    if (x1 < vmin) { vmin = x1; amin = -1.0; bmin = 4.0; }
+    if (a < vmin) { vmin = a; amin = 1.0; bmin = 0.0; }
+    if (b < vmin) { vmin = b; amin = 0.0; bmin = 1.0; }
+    if (x1 > vmax) { vmax = x1; amax = -1.0; bmax = 4.0; }
+    if (a > vmax) { vmax = a; amax = 1.0; bmax = 0.0; }
+    if (b > vmax) { vmax = b; amax = 0.0; bmax = 1.0; }
+    const bool pos = vmin > 0.0, neg = vmax < 0.0;
+    al = pos ? amin : (neg ? amax : 0.0);
+    be = pos ? bmin : (neg ? bmax : 0.0);
 }
 
-// d/d(w_k) of the curvatures C_{s-1}, C_s, C_{s+1} (w_4 = F_s).
-__device__ __forceinline__ double dcurv(int j, int k) {  // C at node j: w_{j-1} - 2 w_j + w_{j+1}
-    return (k == j - 1 ? 1.0 : 0.0) + (k == j ? -2.0 : 0.0) + (k == j + 1 ? 1.0 : 0.0);
-}
-
-// Component k of the gradient of the selected argument of
-// minmod4(4 Ca - Cb, 4 Cb - Ca, Ca, Cb), curvatures at nodes ja, jb.
-__device__ __forceinline__ double dminmod_arg(int sel, int ja, int jb, int k) {
-    const double ga = dcurv(ja, k), gb = dcurv(jb, k);
-    switch (sel) {
-        case 0: return 4.0 * ga - gb;
-        case 1: return 4.0 * gb - ga;
-        case 2: return ga;
-        case 3: return gb;
-        default: return 0.0;
-    }
-}
-
-// Weights of F^L on the nine nodes F_{s-4} .. F_{s+4} (Sec. IV), times 2520.
-__device__ __forceinline__ double linear_weight(int k) {
-    constexpr double c[9] = {4.0, -41.0, 199.0, -641.0, 1879.0, 1375.0, -305.0, 55.0, -5.0};
-    return c[k] * (1.0 / 2520.0);
-}
-
-// d(face)/d(w[k]) for the upwind-first window w[0..8] (w[4] = F_s): the same
-// decision as the forward (mp9_face_linear), the linear weights when the
-// face is not clipped, else the derivative of the clip's selected branch
-// (candidates F_s, F_{s+1}, MD, UL, LC; F^min / F^max by three-way min /
-// max as in the forward).
-__device__ double face_jacobian(const double (&w)[9], int k) {
-    double dd[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) dd[j] = w[j + 1] - w[j];
-    double t, q;
-    const double fl = mp9_face_linear<double>(dd, w[4], t, q);
-    if (!(q > 0.0)) return linear_weight(k);
-    const double f = w[4], g = w[5], ul = f + t;
-    const double cm = dd[3] - dd[2], c0 = dd[4] - dd[3], cp = dd[5] - dd[4];
-    double vm, v0;
-    const double am[4] = {fma(4.0, cm, -c0), fma(4.0, c0, -cm), cm, c0};
-    const double a0[4] = {fma(4.0, c0, -cp), fma(4.0, cp, -c0), c0, cp};
-    const int sm = minmod4_sel(am, vm);   // d^M4 at s - 1/2
-    const int s0 = minmod4_sel(a0, v0);   // d^M4 at s + 1/2
-    const double lc = fma(4.0 / 3.0, vm, fma(0.5, dd[3], f));
-    const double md = fma(0.5, dd[4] - v0, f);
-    // candidates: 0 f, 1 g, 2 md, 3 ul, 4 lc
-    const double cv[5] = {f, g, md, ul, lc};
-    auto pick_min3 = [&](int i, int j, int l) {  // fmin(fmin(x_i, x_j), x_l)
-        int r = cv[j] < cv[i] ? j : i;
-        return cv[l] < cv[r] ? l : r;
-    };
-    auto pick_max3 = [&](int i, int j, int l) {
-        int r = cv[j] > cv[i] ? j : i;
-        return cv[l] > cv[r] ? l : r;
-    };
-    const int a = pick_min3(0, 1, 2), b = pick_min3(0, 3, 4);
-    const int lo = cv[b] > cv[a] ? b : a;
-    const int c = pick_max3(0, 1, 2), e = pick_max3(0, 3, 4);
-    const int hi = cv[e] < cv[c] ? e : c;
-    int sel;
-    if (fl < cv[lo]) sel = lo;
-    else if (fl > cv[hi]) sel = hi;
-    else return linear_weight(k);
-    const double ek3 = k == 3 ? 1.0 : 0.0, ek4 = k == 4 ? 1.0 : 0.0, ek5 = k == 5 ? 1.0 : 0.0;
-    switch (sel) {
-        case 0: return ek4;                                               // F_s
-        case 1: return ek5;                                               // F_{s+1}
-        case 2: return 0.5 * ek4 + 0.5 * ek5 - 0.5 * dminmod_arg(s0, 4, 5, k);  // MD
-        case 3: return 5.0 * ek4 - 4.0 * ek3;                             // UL
-        default: return 1.5 * ek4 - 0.5 * ek3 + (4.0 / 3.0) * dminmod_arg(sm, 3, 4, k);  // LC
-    }
-}
-
-// The whole row d(face)/d(w[0..8]) of one face: the limiter's decisions
-// are taken once (as in face_jacobian), then all nine entries follow.
+// The Jacobian row d(face)/d(w[0..8]) of one face, upwind-first window w
+// (w[4] = F_s, w[5] = F_{s+1}), with the forward's decisions: the linear
+// weights of F^L (Sec. IV) unless the monotonicity test fails and F^L lies
+// outside [F^min, F^max]; then the derivative of the bound it is clipped
+// to, i.e. of the candidate that bound selected (F_s, F_{s+1}, F^MD, F^UL
+// or F^LC; three-way min / max first on ties).  The candidates are linear
+// in w apart from the M4 limits, whose selected arguments are linear in the
+// curvatures C_{s-1}, C_s, C_{s+1} (stencils (1, -2, 1) at nodes s-1, s,
+// s+1, i.e. slots 2-4, 3-5, 4-6), so a clipped row has entries in slots 2
+// to 6 only:
+//   F_s: e4;  F_{s+1}: e5;  F^UL = 5 F_s - 4 F_{s-1}: 5 e4 - 4 e3;
+//   F^MD = (F_s + F_{s+1})/2 - d^M4_{s+1/2}/2;
+//   F^LC = 3/2 F_s - 1/2 F_{s-1} + 4/3 d^M4_{s-1/2}.
 __device__ __forceinline__ void face_jacobian_row(const double (&w)[9], double (&J)[9]) {
+    constexpr double W[9] = {4.0 / 2520.0,    -41.0 / 2520.0, 199.0 / 2520.0, -641.0 / 2520.0, 1879.0 / 2520.0,
+                             1375.0 / 2520.0, -305.0 / 2520.0, 55.0 / 2520.0, -5.0 / 2520.0};
     double dd[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) dd[j] = w[j + 1] - w[j];
     double t, q;
     const double fl = mp9_face_linear<double>(dd, w[4], t, q);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) J[k] = linear_weight(k);
+    for (int k = 0; k < 9; ++k) J[k] = W[k];
     if (!(q > 0.0)) return;
     const double f = w[4], g = w[5], ul = f + t;
     const double cm = dd[3] - dd[2], c0 = dd[4] - dd[3], cp = dd[5] - dd[4];
-    double vm, v0;
-    const double am[4] = {fma(4.0, cm, -c0), fma(4.0, c0, -cm), cm, c0};
-    const double a0[4] = {fma(4.0, c0, -cp), fma(4.0, cp, -c0), c0, cp};
-    const int sm = minmod4_sel(am, vm);
-    const int s0 = minmod4_sel(a0, v0);
+    double am, bm, a0, b0;
+    minmod4_weights(cm, c0, am, bm);  // d^M4 at s - 1/2 = am C_{s-1} + bm C_s
+    minmod4_weights(c0, cp, a0, b0);  // d^M4 at s + 1/2 = a0 C_s + b0 C_{s+1}
+    const double vm = am * cm + bm * c0, v0 = a0 * c0 + b0 * cp;
     const double lc = fma(4.0 / 3.0, vm, fma(0.5, dd[3], f));
     const double md = fma(0.5, dd[4] - v0, f);
-    const double cv[5] = {f, g, md, ul, lc};
-    auto pick_min3 = [&](int i, int j, int l) {
-        int r = cv[j] < cv[i] ? j : i;
-        return cv[l] < cv[r] ? l : r;
-    };
-    auto pick_max3 = [&](int i, int j, int l) {
-        int r = cv[j] > cv[i] ? j : i;
-        return cv[l] > cv[r] ? l : r;
-    };
-    const int a = pick_min3(0, 1, 2), b = pick_min3(0, 3, 4);
-    const int lo = cv[b] > cv[a] ? b : a;
-    const int c = pick_max3(0, 1, 2), e = pick_max3(0, 3, 4);
-    const int hi = cv[e] < cv[c] ? e : c;
+    // candidates 0 F_s, 1 F_{s+1}, 2 MD, 3 UL, 4 LC: F^min = max(min(0, 1, 2),
+    // min(0, 3, 4)), F^max = min(max(0, 1, 2), max(0, 3, 4))
+    double va = f, vb = f, vc = f, ve = f;
+    int ia = 0, ib = 0, ic = 0, ie = 0;
+    if (g < va) { va = g; ia = 1; }
+    if (md < va) { va = md; ia = 2; }
+    if (ul < vb) { vb = ul; ib = 3; }
+    if (lc < vb) { vb = lc; ib = 4; }
+    if (g > vc) { vc = g; ic = 1; }
+    if (md > vc) { vc = md; ic = 2; }
+    if (ul > ve) { ve = ul; ie = 3; }
+    if (lc > ve) { ve = lc; ie = 4; }
+    const double lo = vb > va ? vb : va, hi = ve < vc ? ve : vc;
+    const int ilo = vb > va ? ib : ia, ihi = ve < vc ? ie : ic;
     int sel;
-    if (fl < cv[lo]) sel = lo;
-    else if (fl > cv[hi]) sel = hi;
+    if (fl < lo) sel = ilo;
+    else if (fl > hi) sel = ihi;
     else return;
+    // coefficients of the selected candidate on e3, e4, e5 and on the
+    // curvature stencils at s-1, s, s+1
+    const double A3 = sel == 3 ? -4.0 : (sel == 4 ? -0.5 : 0.0);
+    const double A4 = sel == 0 ? 1.0 : (sel == 2 ? 0.5 : (sel == 3 ? 5.0 : (sel == 4 ? 1.5 : 0.0)));
+    const double A5 = sel == 1 ? 1.0 : (sel == 2 ? 0.5 : 0.0);
+    const double gm = sel == 4 ? 4.0 / 3.0 : 0.0, g0 = sel == 2 ? -0.5 : 0.0;
+    const double Cm = gm * am, C0 = fma(gm, bm, g0 * a0), Cp = g0 * b0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const double ek3 = k == 3 ? 1.0 : 0.0, ek4 = k == 4 ? 1.0 : 0.0, ek5 = k == 5 ? 1.0 : 0.0;
-        double r;
-        switch (sel) {
-            case 0: r = ek4; break;
-            case 1: r = ek5; break;
-            case 2: r = 0.5 * ek4 + 0.5 * ek5 - 0.5 * dminmod_arg(s0, 4, 5, k); break;
-            case 3: r = 5.0 * ek4 - 4.0 * ek3; break;
-            default: r = 1.5 * ek4 - 0.5 * ek3 + (4.0 / 3.0) * dminmod_arg(sm, 3, 4, k); break;
-        }
-        J[k] = r;
-    }
+    for (int k = 0; k < 9; ++k) J[k] = 0.0;
+    J[2] = Cm;
+    J[3] = fma(-2.0, Cm, A3 + C0);
+    J[4] = fma(-2.0, C0, A4 + Cm + Cp);
+    J[5] = fma(-2.0, Cp, A5 + C0);
+    J[6] = Cp;
 }
 
-// Adjoint contribution along one axis to node t of a line of n nodes
-// (stride st): sum over the faces whose stencils read t (or a ghost node
-// that copies t) of d(face)/d(node) * d(face), where d(face s) =
-// p/ds (dA_s - dA_{s+1}) for the face between s and s+1 and dA is zero
-// outside the line (outflow) or wraps (periodic).  FWD: p > 0 (window
-// F_{s-4} .. F_{s+4}), else the mirrored window F_{s+5} .. F_{s-3}.
-template <bool FWD>
-__device__ double adj_axis_dir(const double* F, const Lin4& dA, size_t base, long long st, int n, int bc, int t,
-                               double pinv) {
+// One entry d(face)/d(w[k]) of the row above.
+__device__ __forceinline__ double face_jacobian(const double (&w)[9], int k) {
+    double J[9];
+    face_jacobian_row(w, J);
+    double r = 0.0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) r = j == k ? J[j] : r;
+    return r;
+}
+
+// ------------------------------------------------ transposed advection V^T
+// The adjoint of the fluxes is dA = sum_j c_j z_j; every form below
+// evaluates V = V^T dA at a node and hands it to adj_store, which writes
+// y1 = e0 V + sum_j e_j z_j and (when y2 is set) y2 = f0 V + sum_j f_j z_j.
+// The face between nodes s and s + 1 of a line carries
+// d(face) = p/ds (dA_s - dA_{s+1}) (dA zero outside an outflow line,
+// wrapped on a periodic one); a node receives, from every face whose
+// window reads it, the face's Jacobian entry times d(face).
+// NZ = o.n, a compile-time constant so that the loads of all z_j issue
+// together.
+template <int NZ>
+__device__ __forceinline__ double adj_dA(const AdvAdjIO& o, size_t i) {
+    double r = 0.0;
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) r = fma(o.c[j], o.z[j][i], r);
+    return r;
+}
+
+template <int NZ>
+__device__ __forceinline__ void adj_store(const AdvAdjIO& o, size_t i, double V) {
+    double y1 = o.e0 * V, y2 = o.f0 * V;
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+        const double z = o.z[j][i];
+        y1 = fma(o.e[j], z, y1);
+        y2 = fma(o.f[j], z, y2);
+    }
+    __builtin_nontemporal_store(y1, o.y1 + i);
+    if (o.y2) __builtin_nontemporal_store(y2, o.y2 + i);
+}
+
+// Gather form along one line (used for 1D periodic lines shorter than 40
+// nodes): node t of a line of n nodes (stride st) sums the faces whose
+// windows read t or a ghost node that copies t; each face is evaluated once
+// per node it feeds.  FWD: p > 0 (window F_{s-4} .. F_{s+4}), else the
+// mirrored window F_{s+5} .. F_{s-3}.
+template <bool FWD, int NZ>
+__device__ double adj_axis_dir(const double* F, const AdvAdjIO& o, size_t base, long long st, int n, int bc,
+                               int t, double pinv) {
     int vlo = t, vhi = t;
     if (bc == 0) {
         if (t == 0) vlo = -5;
@@ -246,9 +215,9 @@ __device__ double adj_axis_dir(const double* F, const Lin4& dA, size_t base, lon
             int j = (FWD ? tv - 4 : tv - 5) + i;
             double v = 0.0;
             if (bc == 0) {
-                if (j >= 0 && j < n) v = lin_at(dA, base + (size_t)j * st);
+                if (j >= 0 && j < n) v = adj_dA<NZ>(o, base + (size_t)j * st);
             } else {
-                v = lin_at(dA, base + (size_t)bc_map(j, n, 1) * st);
+                v = adj_dA<NZ>(o, base + (size_t)bc_map(j, n, 1) * st);
             }
             a10[i] = v;
         }
@@ -267,93 +236,25 @@ __device__ double adj_axis_dir(const double* F, const Lin4& dA, size_t base, lon
     return acc;
 }
 
-__device__ __forceinline__ double adj_axis(const double* F, const Lin4& dA, size_t base, long long st, int n,
-                                           int bc, int t, double p, double inv_ds) {
-    if (p == 0.0) return 0.0;
-    return p > 0.0 ? adj_axis_dir<true>(F, dA, base, st, n, bc, t, p * inv_ds)
-                   : adj_axis_dir<false>(F, dA, base, st, n, bc, t, p * inv_ds);
+template <int NZ>
+__global__ void __launch_bounds__(kAdjBlock) advect_adjoint_gather1d_kernel(const DevTables* __restrict__ tabp,
+                                                                            const double* __restrict__ F,
+                                                                            AdvAdjIO o, int nx, int bc,
+                                                                            double inv_dx) {
+    CTab* tab = (CTab*)tabp;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (x >= nx) return;
+    const double p = tab->plane[v].px;
+    const size_t pl = (size_t)v * nx;
+    double r = 0.0;
+    if (p > 0.0) r = adj_axis_dir<true, NZ>(F, o, pl, 1, nx, bc, x, p * inv_dx);
+    else if (p < 0.0) r = adj_axis_dir<false, NZ>(F, o, pl, 1, nx, bc, x, p * inv_dx);
+    adj_store<NZ>(o, pl + x, r);
 }
 
-// Face-major form along a line (used for y columns): the thread owns the
-// kAdjSeg nodes t0 .. t0+kAdjSeg-1 and streams over the kAdjSeg + 8 faces whose
-// stencils read them, each evaluated once with its whole Jacobian row (a
-// face is evaluated (kAdjSeg + 8) / kAdjSeg times per node instead of nine).
-// Positions p = 0 .. kAdjSeg+15 stand for node t0 - 8 + p; a rolling window
-// holds F at the nine positions of the current face and a rolling
-// accumulator their contributions, so the position leaving the window is
-// complete.  Positions left / right of the segment are the ghost nodes of an
-// outflow line (folded into its end nodes) or, on a periodic line, nodes of
-// other segments (dropped here, counted there).
-constexpr int kAdjSeg = 32;
-
-template <bool FWD>
-__device__ __forceinline__ void adj_stream(const double* F, const Lin4& dA, size_t base, long long st, int n,
-                                           int bc, int t0, double pinv, double* out, int accumulate) {
-    constexpr int L = kAdjSeg;
-    auto fat = [&](int p) { return F[base + (size_t)bc_map(t0 - 8 + p, n, bc) * st]; };
-    const int sa = t0 - (FWD ? 4 : 5);  // node s of face 0
-    auto dat = [&](int q) {             // dA at node sa + q, zero outside an outflow line
-        const int j = sa + q;
-        if (bc == 1) return lin_at(dA, base + (size_t)bc_map(j, n, 1) * st);
-        return (j >= 0 && j < n) ? lin_at(dA, base + (size_t)j * st) : 0.0;
-    };
-    auto emit = [&](int t, double val) {
-        const size_t o = base + (size_t)t * st;
-        __builtin_nontemporal_store(accumulate ? out[o] + val : val, out + o);
-    };
-    double w[9], r[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        w[k] = fat(k);
-        r[k] = 0.0;
-    }
-    double a0 = dat(0), a1 = dat(1);
-    double gl = 0.0, gend = 0.0;  // left ghosts; the last node of an outflow line and its ghosts
-    const bool outflow = bc == 0;
-#pragma unroll 1
-    for (int f = 0; f < L + 8; ++f) {
-        const double dface = pinv * (a0 - a1);
-        double fw[9];
-#pragma unroll
-        for (int kk = 0; kk < 9; ++kk) fw[kk] = w[FWD ? kk : 8 - kk];
-        double J[9];
-        face_jacobian_row(fw, J);
-#pragma unroll
-        for (int kk = 0; kk < 9; ++kk) r[FWD ? kk : 8 - kk] = fma(J[kk], dface, r[FWD ? kk : 8 - kk]);
-        // position f is complete
-        const double val = r[0];
-        if (f < 8) {
-            gl += val;
-        } else {
-            const int t = t0 + f - 8;
-            if (outflow && t >= n - 1) {
-                gend += val;
-            } else if (t < n) {
-                emit(t, (outflow && t == 0) ? val + gl : val);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            r[k] = r[k + 1];
-            w[k] = w[k + 1];
-        }
-        r[8] = 0.0;
-        if (f + 1 < L + 8) {
-            w[8] = fat(f + 9);
-            a0 = a1;
-            a1 = dat(f + 2);
-        }
-    }
-    if (outflow && n - 1 >= t0 && n - 1 < t0 + L) {  // this segment holds the last node
-        double g = gend;
-#pragma unroll
-        for (int k = 1; k < 9; ++k) g += r[k - 1];  // positions L+8 .. L+15, shifted once
-        emit(n - 1, (n - 1 == 0) ? g + gl : g);
-    }
-}
-
-// x lines, wave-cooperative: one wavefront per chunk of kChunk nodes of a
-// row, kChunkWaves chunks per work-group.  Lane l evaluates face
+// x lines, wave-cooperative (1D): one wavefront per chunk of kChunk nodes of
+// a row, kChunkWaves chunks per work-group.  Lane l evaluates face
 // s = c0 - 4 + l (flow to +x; else c0 - 5 + l), the 64 faces whose stencils
 // read the chunk's nodes, with coalesced window loads, and writes its nine
 // weighted Jacobian entries to LDS; node c0 + i then gathers the nine
@@ -369,11 +270,11 @@ __device__ __forceinline__ int chunk_pos(bool fwd, int c0, int lane, int kk) {  
 // Chunks per work-group of the x-row kernel: one per wavefront.
 constexpr int kChunkWaves = 4;
 
+template <int NZ>
 __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel(const DevTables* __restrict__ tabp,
                                                                                  const double* __restrict__ F,
-                                                                                 Lin4 dA, double* out, int nx, int ny,
-                                                                                 int bc, double inv_dx,
-                                                                                 int accumulate) {
+                                                                                 AdvAdjIO o, int nx, int ny, int bc,
+                                                                                 double inv_dx) {
     // per wavefront: F at nodes c0-8 .. c0+63, dA at c0-5 .. c0+66, and the
     // 9 x 64 weighted Jacobian entries of its faces
     __shared__ double contrib_all[kChunkWaves][9 * 64];
@@ -394,14 +295,14 @@ __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel
     const double p = tab->plane[v].px;  // one plane per work-group
     const int t = c0 + lane;
     if (p == 0.0) {
-        if (live && !accumulate && lane < kChunk && t < n) out[base + t] = 0.0;
+        if (live && lane < kChunk && t < n) adj_store<NZ>(o, base + t, 0.0);
         return;
     }
     const bool fwd = p > 0.0;
     // the chunk's windows, read once into LDS (coalesced)
     auto dat = [&](int j) {
-        if (bc == 1) return lin_at(dA, base + (size_t)bc_map(j, n, 1));
-        return (j >= 0 && j < n) ? lin_at(dA, base + (size_t)j) : 0.0;
+        if (bc == 1) return adj_dA<NZ>(o, base + (size_t)bc_map(j, n, 1));
+        return (j >= 0 && j < n) ? adj_dA<NZ>(o, base + (size_t)j) : 0.0;
     };
     if (live) {
         for (int i = lane; i < 72; i += 64) {
@@ -435,49 +336,222 @@ __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel
                     if ((t == 0 && j < 0) || (t == n - 1 && j > n - 1)) val += contrib[kk * 64 + l];
                 }
         }
-        const size_t o = base + (size_t)t;
-        __builtin_nontemporal_store(accumulate ? out[o] + val : val, out + o);
+        adj_store<NZ>(o, base + (size_t)t, val);
     }
 }
 
-// y lines: thread per segment of a column, adjacent lanes on adjacent
-// columns (coalesced), out[v][c] += the y contribution.
-__global__ void __launch_bounds__(kAdjBlock) advect_adjoint_ycol_kernel(const DevTables* __restrict__ tabp,
-                                                                        const double* __restrict__ F, Lin4 dA,
-                                                                        double* out, int nx, int ny, int bc,
-                                                                        double inv_dy) {
-    constexpr int L = kAdjSeg;
-    CTab* tab = (CTab*)tabp;
-    const long long cells = (long long)nx * ny;
-    const int v = blockIdx.y;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int nseg = (ny + L - 1) / L;
-    if (i >= (long long)nseg * nx) return;
-    const int t0 = (int)(i / nx) * L;
-    const size_t base = (size_t)v * cells + (size_t)(i % nx);
-    const double p = tab->plane[v].py;
-    if (p > 0.0) adj_stream<true>(F, dA, base, nx, ny, bc, t0, p * inv_dy, out, 1);
-    else if (p < 0.0) adj_stream<false>(F, dA, base, nx, ny, bc, t0, p * inv_dy, out, 1);
+// 2D, both axes in one pass over tiles of kTT x kTT nodes, one work-group of
+// two wavefronts per tile and kTPB planes.  Per plane the tile's F with an
+// 8-node cross halo (the windows of every face that reads a tile node) and
+// dA with a 5-node cross halo (the nodes of those faces) are staged in LDS.
+// Wavefront 0 streams the x lines, wavefront 1 the y lines: each lane owns
+// kTS nodes of a row (column) and evaluates the kTS + 8 faces that read them,
+// each with its whole Jacobian row, accumulating by position in registers
+// (1.5 face evaluations per node and axis).  Positions left of node 0 and
+// right of node n - 1 of an outflow line are its ghost nodes and fold into
+// those end nodes; positions outside the lane's own nodes are otherwise
+// counted by the lane that owns them.  Both axes' sums meet in LDS and every
+// node is written once, coalesced.  Periodic lines of any length wrap through
+// bc_map: a node gathers the nine faces t - 4 .. t + 4 (unwrapped), which
+// are the faces that read it, so no face is counted twice.
+constexpr int kTT = 32;                  // tile edge, nodes
+constexpr int kTS = 16;                  // nodes per lane
+constexpr int kTF = kTS + 8;             // faces per lane
+constexpr int kFE = kTT + 16, kFP = kFE + 1;  // F tile (8-node halo), pitch
+constexpr int kAE = kTT + 10, kAP = kAE + 1;  // dA tile (5-node halo), pitch
+constexpr int kRP = kTT + 1;                  // pitch of the per-axis results (reusing the F and dA tiles)
+constexpr int kTThreads = 128;
+constexpr int kNFL = (kTT * kFE + 16 * kTT) / kTThreads;  // F loads per thread
+constexpr int kNAL = (kTT * kAE + 10 * kTT) / kTThreads;  // dA loads per thread
+constexpr int kTPB = 8;                                    // planes per work-group
+static_assert(kNFL * kTThreads == kTT * kFE + 16 * kTT, "F cross load split");
+static_assert(kNAL * kTThreads == kTT * kAE + 10 * kTT, "dA cross load split");
+static_assert(2 * kTS == kTT && kTT * kRP <= kAE * kAP, "lanes per line, result tiles");
+
+// The kTF faces of one lane: position q (0 .. kTS + 15) stands for node
+// t0 - 8 + q, its F at f[q FS]; face i has node s = t0 - 4 + i (FWD) or
+// t0 - 5 + i, with dA_s at a[i AS].  Entries at the lane's own nodes
+// (positions 8 .. 8 + kTS - 1) go to own[], those left of them to gl and
+// those right of them to gr (ghost nodes of an outflow line, else nodes of
+// other lanes).  A face that the forward clips carries the Jacobian row of
+// its clipped value, any other the linear weights of F^L.
+template <bool FWD, int FS, int AS>
+__device__ __forceinline__ void seg_faces(const double* f, const double* a, double pinv, double (&own)[kTS],
+                                          double& gl, double& gr) {
+    // 2520 times the weights of F^L: small integers, exact as instruction
+    // literals
+    constexpr double C[9] = {4.0, -41.0, 199.0, -641.0, 1879.0, 1375.0, -305.0, 55.0, -5.0};
+#pragma unroll
+    for (int j = 0; j < kTS; ++j) own[j] = 0.0;
+    gl = 0.0;
+    gr = 0.0;
+    auto add = [&](int p, double v, double x) IMEXLB_INLINE {  // entry at position p += v x
+        if (p < 8) gl = fma(v, x, gl);
+        else if (p >= 8 + kTS) gr = fma(v, x, gr);
+        else own[p - 8] = fma(v, x, own[p - 8]);
+    };
+#pragma unroll
+    for (int i = 0; i < kTF; ++i) {
+        double w[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) w[k] = f[(FWD ? i + k : i + 8 - k) * FS];
+        const double d = pinv * (a[i * AS] - a[(i + 1) * AS]);
+        const double dl = d * (1.0 / 2520.0);
+        double dd[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dd[k] = w[k + 1] - w[k];
+        double t, q;
+        (void)mp9_face_linear<double>(dd, w[4], t, q);
+        // every face first carries the linear weights ...
+#pragma unroll
+        for (int k = 0; k < 9; ++k) add(FWD ? i + k : i + 8 - k, C[k], dl);
+        if (q > 0.0) {
+            // ... and a clipped one trades them for its clipped row, inside
+            // the branch (opaque copies keep the compiler from evaluating it
+            // for every face)
+            double wc[9], dc = d, dlc = dl;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                wc[k] = w[k];
+                opaque(wc[k]);
+            }
+            opaque(dc);
+            opaque(dlc);
+            double J[9];
+            face_jacobian_row(wc, J);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const int p = FWD ? i + k : i + 8 - k;
+                add(p, -C[k], dlc);
+                add(p, J[k], dc);
+            }
+        }
+    }
 }
 
-// out[v][c] (=|+=) V^T dA at every node, both axes in 2D.
-template <int D>
-__global__ void __launch_bounds__(kAdjBlock) advect_adjoint_kernel(const DevTables* __restrict__ tabp,
-                                                                   const double* __restrict__ F, Lin4 dA,
-                                                                   double* out, int nx, int ny, int bcx,
-                                                                   int bcy, double inv_dx, double inv_dy,
-                                                                   int accumulate) {
+// Outflow ghosts of a lane whose nodes start at t0 on a line of n nodes:
+// the entries left of node 0 fold into node 0 (t0 = 0), those right of node
+// n - 1 into node n - 1 (when the lane owns it; own nodes past n - 1 are
+// ghost positions too).
+__device__ __forceinline__ void seg_fold(double (&own)[kTS], double gl, double gr, int t0, int n) {
+    if (t0 == 0) own[0] += gl;
+    const int je = n - 1 - t0;  // own index of node n - 1
+    if (je >= 0 && je < kTS) {
+        double g = gr;
+#pragma unroll
+        for (int j = 1; j < kTS; ++j) g += j > je ? own[j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kTS; ++j) own[j] += j == je ? g : 0.0;
+    }
+}
+
+template <int NZ>
+__global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const DevTables* __restrict__ tabp,
+                                                                        const double* __restrict__ F, AdvAdjIO o,
+                                                                        int nx, int ny, int bcx, int bcy,
+                                                                        double inv_dx, double inv_dy, int ntx,
+                                                                        int nplanes) {
+    __shared__ double sF[kFE * kFP];  // then the x results [row][col]
+    __shared__ double sA[kAE * kAP];  // then the y results [row][col]
     CTab* tab = (CTab*)tabp;
     const long long cells = (long long)nx * ny;
-    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y;
-    if (c >= cells) return;
-    const double px = tab->plane[v].px, py = tab->plane[v].py;
-    const int x = (int)(c % nx), y = (int)(c / nx);
-    const size_t pl = (size_t)v * cells;
-    double r = adj_axis(F, dA, pl + (size_t)y * nx, 1, nx, bcx, x, px, inv_dx);
-    if (D == 2) r += adj_axis(F, dA, pl + (size_t)x, nx, ny, bcy, y, py, inv_dy);
-    out[pl + c] = accumulate ? out[pl + c] + r : r;
+    const int tid = threadIdx.x;
+    const int x0 = (int)(blockIdx.x % ntx) * kTT, y0 = (int)(blockIdx.x / ntx) * kTT;
+    // global offsets and LDS slots of the loads, the same for every plane;
+    // the F cross: rows 8 .. 8 + kTT - 1 across the whole width, then the
+    // columns 8 .. 8 + kTT - 1 of the 8 rows above and below; dA likewise
+    // with a 5-node halo (bit j of amask clear: outside an outflow line,
+    // where dA is zero; the load still reads a valid node so that every
+    // load issues at once)
+    int fo[kNFL], fl[kNFL], ao[kNAL], al[kNAL];
+    unsigned amask = 0u;
+#pragma unroll
+    for (int j = 0; j < kNFL; ++j) {
+        const int i = tid + j * kTThreads;
+        int lx, ly;
+        if (i < kTT * kFE) {
+            ly = 8 + i / kFE;
+            lx = i % kFE;
+        } else {
+            const int k = i - kTT * kFE, q = k / kTT;
+            lx = 8 + k % kTT;
+            ly = q < 8 ? q : kTT + q;
+        }
+        fo[j] = bc_map(y0 - 8 + ly, ny, bcy) * nx + bc_map(x0 - 8 + lx, nx, bcx);
+        fl[j] = ly * kFP + lx;
+    }
+#pragma unroll
+    for (int j = 0; j < kNAL; ++j) {
+        const int i = tid + j * kTThreads;
+        int lx, ly;
+        if (i < kTT * kAE) {
+            ly = 5 + i / kAE;
+            lx = i % kAE;
+        } else {
+            const int k = i - kTT * kAE, q = k / kTT;
+            lx = 5 + k % kTT;
+            ly = q < 5 ? q : kTT + q;
+        }
+        const int gx = x0 - 5 + lx, gy = y0 - 5 + ly;
+        const bool zero = (bcx == 0 && (gx < 0 || gx >= nx)) || (bcy == 0 && (gy < 0 || gy >= ny));
+        ao[j] = bc_map(gy, ny, bcy) * nx + bc_map(gx, nx, bcx);
+        amask |= (zero ? 0u : 1u) << j;
+        al[j] = ly * kAP + lx;
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    const int line = lane & (kTT - 1), seg = lane >> 5;  // row (wave 0) or column (wave 1), half of it
+    const int v1 = min((int)blockIdx.y * kTPB + kTPB, nplanes);
+    for (int v = (int)blockIdx.y * kTPB; v < v1; ++v) {
+        const size_t pl = (size_t)v * cells;
+#pragma unroll
+        for (int j = 0; j < kNFL; ++j) sF[fl[j]] = F[pl + fo[j]];
+#pragma unroll
+        for (int j = 0; j < kNAL; ++j) {
+            const double v = adj_dA<NZ>(o, pl + ao[j]);
+            sA[al[j]] = (amask >> j) & 1u ? v : 0.0;
+        }
+        __syncthreads();
+        double own[kTS], gl, gr;
+        bool live;
+        if (wave == 0) {  // x lines: row `line`, nodes t0 .. t0 + kTS - 1
+            const double p = tab->plane[v].px;
+            const int t0 = x0 + kTS * seg;
+            live = p != 0.0 && y0 + line < ny && t0 < nx;
+            if (live) {
+                const double* f = sF + (8 + line) * kFP + kTS * seg;
+                const double* a = sA + (5 + line) * kAP + kTS * seg;
+                if (p > 0.0) seg_faces<true, 1, 1>(f, a + 1, p * inv_dx, own, gl, gr);
+                else seg_faces<false, 1, 1>(f, a, p * inv_dx, own, gl, gr);
+                if (bcx == 0) seg_fold(own, gl, gr, t0, nx);
+            }
+        } else {  // y lines: column `line`, nodes t0 .. t0 + kTS - 1
+            const double p = tab->plane[v].py;
+            const int t0 = y0 + kTS * seg;
+            live = p != 0.0 && x0 + line < nx && t0 < ny;
+            if (live) {
+                const double* f = sF + kTS * seg * kFP + 8 + line;
+                const double* a = sA + kTS * seg * kAP + 5 + line;
+                if (p > 0.0) seg_faces<true, kFP, kAP>(f, a + kAP, p * inv_dy, own, gl, gr);
+                else seg_faces<false, kFP, kAP>(f, a, p * inv_dy, own, gl, gr);
+                if (bcy == 0) seg_fold(own, gl, gr, t0, ny);
+            }
+        }
+        __syncthreads();  // both tiles are read; they now take the results
+        if (wave == 0) {
+#pragma unroll
+            for (int i = 0; i < kTS; ++i) sF[line * kRP + kTS * seg + i] = live ? own[i] : 0.0;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kTS; ++i) sA[(kTS * seg + i) * kRP + line] = live ? own[i] : 0.0;
+        }
+        __syncthreads();
+        for (int i = tid; i < kTT * kTT; i += kTThreads) {
+            const int r = i / kTT, c = i % kTT;
+            if (x0 + c < nx && y0 + r < ny)
+                adj_store<NZ>(o, pl + (size_t)(y0 + r) * nx + x0 + c, sF[r * kRP + c] + sA[r * kRP + c]);
+        }
+        __syncthreads();  // before the next plane overwrites the tiles
+    }
 }
 
 // out = a src + b E(M) as FP64 (stage value rebuilt from its moments).
@@ -623,36 +697,42 @@ hipError_t launch_materialise(int d, bool f32, const DevTables* tab, const void*
     return hipGetLastError();
 }
 
-hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const double* F, int ny_in,
-                                 const double* const* y, const double* cf, double* out, int nx, int ny,
-                                 int bcx, int bcy, double inv_dx, double inv_dy, bool accumulate,
-                                 hipStream_t s) {
-    const Lin4 L = make_lin(ny_in, y, cf);
-    const long long cells = (long long)nx * ny;
-    // Face-major forms: x rows in 64-face chunks, y columns in streamed
-    // segments.  They need periodic lines of at least kAdjSeg + 8 nodes (on a
-    // shorter ring a segment's face range, or a face's window, would hold one
-    // node twice); shorter periodic lines take the gather form.
-    const bool short_ring = (bcx == 1 && nx < kAdjSeg + 8) || (d == 2 && bcy == 1 && ny < kAdjSeg + 8);
-    if (short_ring) {
-        const dim3 grid((unsigned)((cells + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
-        if (d == 2)
-            hipLaunchKernelGGL((advect_adjoint_kernel<2>), grid, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, ny, bcx, bcy, inv_dx, inv_dy, (int)accumulate);
-        else
-            hipLaunchKernelGGL((advect_adjoint_kernel<1>), grid, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, 1, bcx, 0, inv_dx, 0.0, (int)accumulate);
+namespace {
+
+template <int NZ>
+hipError_t launch_advect_adjoint_n(int d, const DevTables* tab, int nplanes, const double* F, const AdvAdjIO& io,
+                                   int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy, hipStream_t s) {
+    if (d == 2) {
+        const int ntx = (nx + kTT - 1) / kTT, nty = (ny + kTT - 1) / kTT;
+        const dim3 grid((unsigned)(ntx * nty), (unsigned)((nplanes + kTPB - 1) / kTPB));
+        hipLaunchKernelGGL(advect_adjoint_tile_kernel<NZ>, grid, dim3(kTThreads), 0, s, tab, F, io, nx, ny, bcx, bcy,
+                           inv_dx, inv_dy, ntx, nplanes);
         return hipGetLastError();
     }
-    const int nyl = d == 2 ? ny : 1;
-    const long long chx = (long long)((nx + kChunk - 1) / kChunk) * nyl;
-    const long long gx = (chx + kChunkWaves - 1) / kChunkWaves;
-    hipLaunchKernelGGL(advect_adjoint_xchunk_kernel, dim3((unsigned)gx, (unsigned)nplanes), dim3(64 * kChunkWaves), 0, s,
-                       tab, F, L, out, nx, nyl, bcx, inv_dx, (int)accumulate);
-    if (d == 2) {
-        const long long segy = (long long)((ny + kAdjSeg - 1) / kAdjSeg) * nx;
-        const dim3 gy((unsigned)((segy + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
-        hipLaunchKernelGGL(advect_adjoint_ycol_kernel, gy, dim3(kAdjBlock), 0, s, tab, F, L, out, nx, ny, bcy, inv_dy);
+    // 1D: rows in 64-face chunks; periodic lines shorter than a chunk's
+    // window range take the gather form
+    if (bcx == 1 && nx < 40) {
+        const dim3 grid((unsigned)((nx + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
+        hipLaunchKernelGGL(advect_adjoint_gather1d_kernel<NZ>, grid, dim3(kAdjBlock), 0, s, tab, F, io, nx, bcx, inv_dx);
+        return hipGetLastError();
     }
+    const long long gx = ((nx + kChunk - 1) / kChunk + kChunkWaves - 1) / kChunkWaves;
+    hipLaunchKernelGGL(advect_adjoint_xchunk_kernel<NZ>, dim3((unsigned)gx, (unsigned)nplanes), dim3(64 * kChunkWaves),
+                       0, s, tab, F, io, nx, 1, bcx, inv_dx);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const double* F, const AdvAdjIO& io,
+                                 int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy, hipStream_t s) {
+    switch (io.n) {
+        case 1: return launch_advect_adjoint_n<1>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
+        case 2: return launch_advect_adjoint_n<2>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
+        case 3: return launch_advect_adjoint_n<3>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
+        case 4: return launch_advect_adjoint_n<4>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, int ny_in,

@@ -156,10 +156,20 @@ hipError_t launch_check(int d, const double* M, long long ms, long long cells, i
 hipError_t launch_materialise(int d, bool f32, const DevTables* tab, const void* src, const double* M,
                               double a, double b, double* out, long long cells, double chi_fac,
                               hipStream_t s);
-hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const double* F, int ny_in,
-                                 const double* const* y, const double* cf, double* out, int nx, int ny,
-                                 int bcx, int bcy, double inv_dx, double inv_dy, bool accumulate,
-                                 hipStream_t s);
+// Transposed advection: with dA = sum_j c[j] z[j] (the adjoint of the
+// fluxes) and V = V^T dA at every node, writes y1 = e0 V + sum_j e[j] z[j]
+// and, when y2 is not NULL, y2 = f0 V + sum_j f[j] z[j].  The outputs must
+// not alias F or any z[j].
+struct AdvAdjIO {
+    const double* z[4];
+    double c[4], e[4], f[4];
+    double e0, f0;
+    int n;
+    double* y1;
+    double* y2;
+};
+hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const double* F, const AdvAdjIO& io,
+                                 int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy, hipStream_t s);
 hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, int ny_in,
                              const double* const* y, const double* cf, double* dM, long long cells,
                              double chi_fac, hipStream_t s);

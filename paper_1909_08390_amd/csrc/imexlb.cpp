@@ -830,39 +830,60 @@ imexlb_status imexlb_adjoint_step(imexlb_ctx* c, const void* Fn, const double* l
     const int np = c->nplanes, nx = c->cfg.nx, ny = d == 2 ? c->cfg.ny : 1;
     const double idx = a.inv_dx, idy = a.inv_dy;
     const int qm = a.qm;
-    auto adv = [&](const double* F, std::initializer_list<const double*> ys, std::initializer_list<double> cs,
-                   double* out) {
-        return launch_advect_adjoint(d, c->d_tab, np, F, (int)ys.size(), ys.begin(), cs.begin(), out, nx, ny,
-                                     c->cfg.bc_x, c->cfg.bc_y, idx, idy, false, s);
+    // V^T with the linear combinations its two consumers read: the adjoint
+    // of the fluxes dA = sum_j cs_j z_j, then y1 = e0 V + sum_j es_j z_j (the
+    // equilibrium adjoint's input) and y2 = f0 V + sum_j fs_j z_j (the moment
+    // adjoint's), V = V^T dA
+    auto adv = [&](const double* F, std::initializer_list<const double*> zs, std::initializer_list<double> cs,
+                   double e0, std::initializer_list<double> es, double f0, std::initializer_list<double> fs,
+                   double* y1, double* y2) {
+        AdvAdjIO io{};
+        io.n = (int)zs.size();
+        for (int j = 0; j < io.n; ++j) {
+            io.z[j] = zs.begin()[j];
+            io.c[j] = cs.begin()[j];
+            io.e[j] = es.begin()[j];
+            io.f[j] = fs.begin()[j];
+        }
+        io.e0 = e0;
+        io.f0 = f0;
+        io.y1 = y1;
+        io.y2 = y2;
+        return launch_advect_adjoint(d, c->d_tab, np, F, io, nx, ny, c->cfg.bc_x, c->cfg.bc_y, idx, idy, s);
     };
-    auto eqt = [&](const double* M, std::initializer_list<const double*> ys, std::initializer_list<double> cs) {
-        return launch_eq_adjoint(d, qm, c->d_tab, M, (int)ys.size(), ys.begin(), cs.begin(), dM, cells, chi, s);
+    auto eqt = [&](const double* M, const double* y) {
+        const double one = 1.0;
+        return launch_eq_adjoint(d, qm, c->d_tab, M, 1, &y, &one, dM, cells, chi, s);
     };
-    auto momt = [&](const double* M, std::initializer_list<const double*> ys, std::initializer_list<double> cs,
-                    double* out) {
-        return launch_mom_adjoint(d, c->d_tab, M, dM, (int)ys.size(), ys.begin(), cs.begin(), out, cells, dk,
-                                  false, s);
+    auto momt = [&](const double* M, const double* y, double* out) {
+        const double one = 1.0;
+        return launch_mom_adjoint(d, c->d_tab, M, dM, 1, &y, &one, out, cells, dk, false, s);
     };
     const double* L = lam1;
-    // stage 4: F4 = a1 S4 + c a1 E4, dA4 = -(2/3) dt L, d(dF4) = -(2/3) L
+    // stage 4: F4 = a1 S4 + c a1 E4, dA4 = -(2/3) dt L, d(dF4) = -(2/3) L;
+    // dE4 = c a1 V4 + (2/3) w a1 L, dS4 (before the moment term) = a1 V4 - (2/3) w a1 L
     if (e == hipSuccess) e = launch_materialise(d, f32, c->d_tab, G4, M4, a1, cc * a1, X1, cells, chi, s);
-    if (e == hipSuccess) e = adv(X1, {L}, {-(2.0 / 3.0) * dt}, X2);
-    if (e == hipSuccess) e = eqt(M4, {X2, L}, {cc * a1, (2.0 / 3.0) * w * a1});
-    if (e == hipSuccess) e = momt(M4, {X2, L}, {a1, -(2.0 / 3.0) * w * a1}, X3);  // X3 = dS4
+    if (e == hipSuccess)
+        e = adv(X1, {L}, {-(2.0 / 3.0) * dt}, cc * a1, {(2.0 / 3.0) * w * a1}, a1, {-(2.0 / 3.0) * w * a1}, X2, X4);
+    if (e == hipSuccess) e = eqt(M4, X2);
+    if (e == hipSuccess) e = momt(M4, X4, X3);  // X3 = dS4
     // stage 3: dA3 = -(1/6) dt L - dt/4 dS4, d(dF3) = -(1/6) L - kappa dS4
     if (e == hipSuccess) e = launch_materialise(d, f32, c->d_tab, G3, M3, a1, cc * a1, X1, cells, chi, s);
-    if (e == hipSuccess) e = adv(X1, {L, X3}, {-dt / 6.0, -0.25 * dt}, X2);
-    if (e == hipSuccess) e = eqt(M3, {X2, L, X3}, {cc * a1, w * a1 / 6.0, ka * w * a1});
-    if (e == hipSuccess) e = momt(M3, {X2, L, X3}, {a1, -w * a1 / 6.0, -ka * w * a1}, X1);  // X1 = dS3
+    if (e == hipSuccess)
+        e = adv(X1, {L, X3}, {-dt / 6.0, -0.25 * dt}, cc * a1, {w * a1 / 6.0, ka * w * a1}, a1,
+                {-w * a1 / 6.0, -ka * w * a1}, X2, X4);
+    if (e == hipSuccess) e = eqt(M3, X2);
+    if (e == hipSuccess) e = momt(M3, X4, X1);  // X1 = dS3
     // stages 2 and 1: F2 = a2 F^n + b2 E^n, dA2 = -(1/6) dt L - dt/4 dS4 - dt dS3,
-    // d(dF1) = -beta dS4, d(dF2) = -(1/6) L - eta dS4 - (1 - alpha) dS3
+    // d(dF1) = -beta dS4, d(dF2) = -(1/6) L - eta dS4 - (1 - alpha) dS3; the
+    // moment adjoint's input goes straight to lam0 and is completed in place
     if (e == hipSuccess) e = launch_materialise(d, f32, c->d_tab, Fn, Mn, a2, b2, X2, cells, chi, s);
-    if (e == hipSuccess) e = adv(X2, {L, X3, X1}, {-dt / 6.0, -0.25 * dt, -dt}, X4);
     if (e == hipSuccess)
-        e = eqt(Mn, {X4, X3, L, X1}, {b2, w * a1 * be + w * a2 * et, w * a2 / 6.0, w * a2 * (1.0 - kAlpha)});
-    if (e == hipSuccess)
-        e = momt(Mn, {L, X3, X1, X4},
-                 {1.0 - w * a2 / 6.0, 1.0 - w * a1 * be - w * a2 * et, 1.0 - w * a2 * (1.0 - kAlpha), a2}, lam0);
+        e = adv(X2, {L, X3, X1}, {-dt / 6.0, -0.25 * dt, -dt}, b2,
+                {w * a2 / 6.0, w * a1 * be + w * a2 * et, w * a2 * (1.0 - kAlpha)}, a2,
+                {1.0 - w * a2 / 6.0, 1.0 - w * a1 * be - w * a2 * et, 1.0 - w * a2 * (1.0 - kAlpha)}, X4, lam0);
+    if (e == hipSuccess) e = eqt(Mn, X4);
+    if (e == hipSuccess) e = momt(Mn, lam0, lam0);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     return IMEXLB_OK;
 }
@@ -872,11 +893,16 @@ imexlb_status imexlb_advect_adjoint(const imexlb_ctx* c, const double* F, const 
     imexlb_ctx* m = const_cast<imexlb_ctx*>(c);
     if (!F || !dA || !dF) return fail(m, IMEXLB_EINVAL, "advect_adjoint: NULL buffer");
     const StageArgs a = base_args(c);
-    const double* ys[1] = {dA};
-    const double cs[1] = {1.0};
-    hipError_t e = launch_advect_adjoint(c->cfg.d, c->d_tab, c->nplanes, F, 1, ys, cs, dF, c->cfg.nx,
+    if (dF == F || dF == dA) return fail(m, IMEXLB_EINVAL, "advect_adjoint: dF aliases F or dA");
+    AdvAdjIO io{};
+    io.n = 1;
+    io.z[0] = dA;
+    io.c[0] = 1.0;
+    io.e0 = 1.0;
+    io.y1 = dF;
+    hipError_t e = launch_advect_adjoint(c->cfg.d, c->d_tab, c->nplanes, F, io, c->cfg.nx,
                                          c->cfg.d == 2 ? c->cfg.ny : 1, c->cfg.bc_x, c->cfg.bc_y, a.inv_dx,
-                                         a.inv_dy, false, c->stream);
+                                         a.inv_dy, c->stream);
     if (e != hipSuccess) return hip_fail(m, e, "advect_adjoint");
     return IMEXLB_OK;
 }

@@ -80,6 +80,14 @@ STEP_CASES = [
     (dict(d=2, nx=48, ny=41, q_phi=5, q_chi=4, K=2, tau=1e-3, dt=1e-3, bc_x=I.PERIODIC,
           bc_y=I.OUTFLOW), "smooth"),
     (dict(d=1, nx=20, q_phi=5, q_chi=3, K=2, tau=1e-3, dt=1e-3, bc_x=I.OUTFLOW), "rough"),
+    # 2D tiles of 32 x 32 nodes: several tiles with ragged last ones, a
+    # line shorter than one 16-node lane segment, periodic in both axes
+    (dict(d=2, nx=100, ny=37, q_phi=4, q_chi=3, K=2, tau=1e-3, dt=1e-3, bc_x=I.OUTFLOW,
+          bc_y=I.OUTFLOW), "rough"),
+    (dict(d=2, nx=12, ny=70, q_phi=4, q_chi=2, K=2, tau=1e-3, dt=1e-3, bc_x=I.PERIODIC,
+          bc_y=I.OUTFLOW), "rough"),
+    (dict(d=2, nx=66, ny=65, q_phi=4, q_chi=3, K=2, tau=1e-3, dt=1e-3, bc_x=I.PERIODIC,
+          bc_y=I.PERIODIC), "smooth"),
 ]
 
 
