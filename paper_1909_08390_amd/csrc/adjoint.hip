@@ -97,7 +97,8 @@ __device__ __forceinline__ void minmod4_weights(double a, double b, double& al, 
 //   F_s: e4;  F_{s+1}: e5;  F^UL = 5 F_s - 4 F_{s-1}: 5 e4 - 4 e3;
 //   F^MD = (F_s + F_{s+1})/2 - d^M4_{s+1/2}/2;
 //   F^LC = 3/2 F_s - 1/2 F_{s-1} + 4/3 d^M4_{s-1/2}.
-__device__ __forceinline__ void face_jacobian_row(const double (&w)[9], double (&J)[9]) {
+// Returns true when the row is a clipped one.
+__device__ __forceinline__ bool face_jacobian_row(const double (&w)[9], double (&J)[9]) {
     constexpr double W[9] = {4.0 / 2520.0,    -41.0 / 2520.0, 199.0 / 2520.0, -641.0 / 2520.0, 1879.0 / 2520.0,
                              1375.0 / 2520.0, -305.0 / 2520.0, 55.0 / 2520.0, -5.0 / 2520.0};
     double dd[8];
@@ -107,7 +108,7 @@ __device__ __forceinline__ void face_jacobian_row(const double (&w)[9], double (
     const double fl = mp9_face_linear<double>(dd, w[4], t, q);
 #pragma unroll
     for (int k = 0; k < 9; ++k) J[k] = W[k];
-    if (!(q > 0.0)) return;
+    if (!(q > 0.0)) return false;
     const double f = w[4], g = w[5], ul = f + t;
     const double cm = dd[3] - dd[2], c0 = dd[4] - dd[3], cp = dd[5] - dd[4];
     double am, bm, a0, b0;
@@ -133,7 +134,7 @@ __device__ __forceinline__ void face_jacobian_row(const double (&w)[9], double (
     int sel;
     if (fl < lo) sel = ilo;
     else if (fl > hi) sel = ihi;
-    else return;
+    else return false;
     // coefficients of the selected candidate on e3, e4, e5 and on the
     // curvature stencils at s-1, s, s+1
     const double A3 = sel == 3 ? -4.0 : (sel == 4 ? -0.5 : 0.0);
@@ -148,6 +149,7 @@ __device__ __forceinline__ void face_jacobian_row(const double (&w)[9], double (
     J[4] = fma(-2.0, C0, A4 + Cm + Cp);
     J[5] = fma(-2.0, Cp, A5 + C0);
     J[6] = Cp;
+    return true;
 }
 
 // One entry d(face)/d(w[k]) of the row above.
@@ -355,29 +357,34 @@ __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel
 // bc_map: a node gathers the nine faces t - 4 .. t + 4 (unwrapped), which
 // are the faces that read it, so no face is counted twice.
 constexpr int kTT = 32;                  // tile edge, nodes
-constexpr int kTS = 16;                  // nodes per lane
+constexpr int kTS = 8;                   // nodes per lane
 constexpr int kTF = kTS + 8;             // faces per lane
 constexpr int kFE = kTT + 16, kFP = kFE + 1;  // F tile (8-node halo), pitch
 constexpr int kAE = kTT + 10, kAP = kAE + 1;  // dA tile (5-node halo), pitch
 constexpr int kRP = kTT + 1;                  // pitch of the per-axis results (reusing the F and dA tiles)
-constexpr int kTThreads = 128;
-constexpr int kNFL = (kTT * kFE + 16 * kTT) / kTThreads;  // F loads per thread
-constexpr int kNAL = (kTT * kAE + 10 * kTT) / kTThreads;  // dA loads per thread
+constexpr int kTThreads = 256;             // half of them on x lines, half on y lines
+constexpr int kCorrPitch = kTS + 1;        // per-thread LDS row of corrections (odd pitch)
+constexpr int kFLoads = kTT * kFE + 16 * kTT, kALoads = kTT * kAE + 10 * kTT;  // cross sizes
+constexpr int kNFL = (kFLoads + kTThreads - 1) / kTThreads;  // F loads per thread
+constexpr int kNAL = (kALoads + kTThreads - 1) / kTThreads;  // dA loads per thread
 constexpr int kTPB = 8;                                    // planes per work-group
-static_assert(kNFL * kTThreads == kTT * kFE + 16 * kTT, "F cross load split");
-static_assert(kNAL * kTThreads == kTT * kAE + 10 * kTT, "dA cross load split");
-static_assert(2 * kTS == kTT && kTT * kRP <= kAE * kAP, "lanes per line, result tiles");
+static_assert(kTT % kTS == 0 && (kTT / kTS) * kTT * 2 == kTThreads, "lanes per line");
+static_assert(kTT * kRP <= kAE * kAP, "result tiles");
 
 // The kTF faces of one lane: position q (0 .. kTS + 15) stands for node
 // t0 - 8 + q, its F at f[q FS]; face i has node s = t0 - 4 + i (FWD) or
 // t0 - 5 + i, with dA_s at a[i AS].  Entries at the lane's own nodes
 // (positions 8 .. 8 + kTS - 1) go to own[], those left of them to gl and
 // those right of them to gr (ghost nodes of an outflow line, else nodes of
-// other lanes).  A face that the forward clips carries the Jacobian row of
-// its clipped value, any other the linear weights of F^L.
+// other lanes).  Every face first carries the linear weights of F^L and
+// takes the forward's monotonicity test; then the lane walks its faces that
+// failed it (a wavefront takes as many turns as its busiest lane, not one
+// per face position) and trades their linear weights for their clipped
+// rows, accumulated in face order in corr[] (the lane's LDS row: the
+// positions of those entries vary from face to face).
 template <bool FWD, int FS, int AS>
-__device__ __forceinline__ void seg_faces(const double* f, const double* a, double pinv, double (&own)[kTS],
-                                          double& gl, double& gr) {
+__device__ __forceinline__ void seg_faces(const double* f, const double* a, double pinv, double* corr,
+                                          double (&own)[kTS], double& gl, double& gr) {
     // 2520 times the weights of F^L: small integers, exact as instruction
     // literals
     constexpr double C[9] = {4.0, -41.0, 199.0, -641.0, 1879.0, 1375.0, -305.0, 55.0, -5.0};
@@ -385,47 +392,49 @@ __device__ __forceinline__ void seg_faces(const double* f, const double* a, doub
     for (int j = 0; j < kTS; ++j) own[j] = 0.0;
     gl = 0.0;
     gr = 0.0;
-    auto add = [&](int p, double v, double x) IMEXLB_INLINE {  // entry at position p += v x
-        if (p < 8) gl = fma(v, x, gl);
-        else if (p >= 8 + kTS) gr = fma(v, x, gr);
-        else own[p - 8] = fma(v, x, own[p - 8]);
-    };
+    unsigned mask = 0u;
 #pragma unroll
     for (int i = 0; i < kTF; ++i) {
-        double w[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) w[k] = f[(FWD ? i + k : i + 8 - k) * FS];
-        const double d = pinv * (a[i * AS] - a[(i + 1) * AS]);
-        const double dl = d * (1.0 / 2520.0);
         double dd[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) dd[k] = w[k + 1] - w[k];
+        for (int k = 0; k < 8; ++k)
+            dd[k] = FWD ? f[(i + k + 1) * FS] - f[(i + k) * FS] : f[(i + 7 - k) * FS] - f[(i + 8 - k) * FS];
         double t, q;
-        (void)mp9_face_linear<double>(dd, w[4], t, q);
-        // every face first carries the linear weights ...
+        (void)mp9_face_linear<double>(dd, f[(i + 4) * FS], t, q);
+        mask |= (q > 0.0 ? 1u : 0u) << i;
+        const double dl = pinv * (a[i * AS] - a[(i + 1) * AS]) * (1.0 / 2520.0);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) add(FWD ? i + k : i + 8 - k, C[k], dl);
-        if (q > 0.0) {
-            // ... and a clipped one trades them for its clipped row, inside
-            // the branch (opaque copies keep the compiler from evaluating it
-            // for every face)
-            double wc[9], dc = d, dlc = dl;
+        for (int k = 0; k < 9; ++k) {
+            const int p = FWD ? i + k : i + 8 - k;
+            if (p < 8) gl = fma(C[k], dl, gl);
+            else if (p >= 8 + kTS) gr = fma(C[k], dl, gr);
+            else own[p - 8] = fma(C[k], dl, own[p - 8]);
+        }
+    }
+    if (mask) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                wc[k] = w[k];
-                opaque(wc[k]);
-            }
-            opaque(dc);
-            opaque(dlc);
+        for (int j = 0; j < kTS; ++j) corr[j] = 0.0;
+        for (unsigned m = mask; m; m &= m - 1u) {
+            const int i = __builtin_ctz(m);
+            double w[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) w[k] = f[(FWD ? i + k : i + 8 - k) * FS];
             double J[9];
-            face_jacobian_row(wc, J);
+            if (face_jacobian_row(w, J)) {
+                const double d = pinv * (a[i * AS] - a[(i + 1) * AS]);
+                const double dl = d * (1.0 / 2520.0);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const int p = FWD ? i + k : i + 8 - k;
-                add(p, -C[k], dlc);
-                add(p, J[k], dc);
+                for (int k = 0; k < 9; ++k) {
+                    const int p = FWD ? i + k : i + 8 - k;
+                    const double v = fma(J[k], d, -C[k] * dl);
+                    if (p < 8) gl += v;
+                    else if (p >= 8 + kTS) gr += v;
+                    else corr[p - 8] += v;
+                }
             }
         }
+#pragma unroll
+        for (int j = 0; j < kTS; ++j) own[j] += corr[j];
     }
 }
 
@@ -453,6 +462,7 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
                                                                         int nplanes) {
     __shared__ double sF[kFE * kFP];  // then the x results [row][col]
     __shared__ double sA[kAE * kAP];  // then the y results [row][col]
+    __shared__ double sCorr[kTThreads * kCorrPitch];  // per thread: clipped-face corrections
     CTab* tab = (CTab*)tabp;
     const long long cells = (long long)nx * ny;
     const int tid = threadIdx.x;
@@ -467,9 +477,13 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
     unsigned amask = 0u;
 #pragma unroll
     for (int j = 0; j < kNFL; ++j) {
-        const int i = tid + j * kTThreads;
+        // slots past the cross (last round) load node 0 into the unused corner 0
+        const int i = min(tid + j * kTThreads, kFLoads);
         int lx, ly;
-        if (i < kTT * kFE) {
+        if (i == kFLoads) {
+            lx = 0;
+            ly = 0;
+        } else if (i < kTT * kFE) {
             ly = 8 + i / kFE;
             lx = i % kFE;
         } else {
@@ -477,14 +491,17 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
             lx = 8 + k % kTT;
             ly = q < 8 ? q : kTT + q;
         }
-        fo[j] = bc_map(y0 - 8 + ly, ny, bcy) * nx + bc_map(x0 - 8 + lx, nx, bcx);
+        fo[j] = i == kFLoads ? 0 : bc_map(y0 - 8 + ly, ny, bcy) * nx + bc_map(x0 - 8 + lx, nx, bcx);
         fl[j] = ly * kFP + lx;
     }
 #pragma unroll
     for (int j = 0; j < kNAL; ++j) {
-        const int i = tid + j * kTThreads;
+        const int i = min(tid + j * kTThreads, kALoads);
         int lx, ly;
-        if (i < kTT * kAE) {
+        if (i == kALoads) {
+            lx = 0;
+            ly = 0;
+        } else if (i < kTT * kAE) {
             ly = 5 + i / kAE;
             lx = i % kAE;
         } else {
@@ -494,12 +511,15 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
         }
         const int gx = x0 - 5 + lx, gy = y0 - 5 + ly;
         const bool zero = (bcx == 0 && (gx < 0 || gx >= nx)) || (bcy == 0 && (gy < 0 || gy >= ny));
-        ao[j] = bc_map(gy, ny, bcy) * nx + bc_map(gx, nx, bcx);
+        ao[j] = i == kALoads ? 0 : bc_map(gy, ny, bcy) * nx + bc_map(gx, nx, bcx);
         amask |= (zero ? 0u : 1u) << j;
         al[j] = ly * kAP + lx;
     }
-    const int wave = tid >> 6, lane = tid & 63;
-    const int line = lane & (kTT - 1), seg = lane >> 5;  // row (wave 0) or column (wave 1), half of it
+    // the first half of the threads on x lines, the second on y lines: a
+    // row (column) `line`, nodes kTS seg .. kTS seg + kTS - 1 of the tile
+    const bool xl = tid < kTThreads / 2;
+    const int li = xl ? tid : tid - kTThreads / 2;
+    const int line = li % kTT, seg = li / kTT;
     const int v1 = min((int)blockIdx.y * kTPB + kTPB, nplanes);
     for (int v = (int)blockIdx.y * kTPB; v < v1; ++v) {
         const size_t pl = (size_t)v * cells;
@@ -513,15 +533,16 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
         __syncthreads();
         double own[kTS], gl, gr;
         bool live;
-        if (wave == 0) {  // x lines: row `line`, nodes t0 .. t0 + kTS - 1
+        if (xl) {  // x lines: row `line`, nodes t0 .. t0 + kTS - 1
             const double p = tab->plane[v].px;
             const int t0 = x0 + kTS * seg;
             live = p != 0.0 && y0 + line < ny && t0 < nx;
             if (live) {
                 const double* f = sF + (8 + line) * kFP + kTS * seg;
                 const double* a = sA + (5 + line) * kAP + kTS * seg;
-                if (p > 0.0) seg_faces<true, 1, 1>(f, a + 1, p * inv_dx, own, gl, gr);
-                else seg_faces<false, 1, 1>(f, a, p * inv_dx, own, gl, gr);
+                double* corr = sCorr + tid * kCorrPitch;
+                if (p > 0.0) seg_faces<true, 1, 1>(f, a + 1, p * inv_dx, corr, own, gl, gr);
+                else seg_faces<false, 1, 1>(f, a, p * inv_dx, corr, own, gl, gr);
                 if (bcx == 0) seg_fold(own, gl, gr, t0, nx);
             }
         } else {  // y lines: column `line`, nodes t0 .. t0 + kTS - 1
@@ -531,13 +552,14 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
             if (live) {
                 const double* f = sF + kTS * seg * kFP + 8 + line;
                 const double* a = sA + kTS * seg * kAP + 5 + line;
-                if (p > 0.0) seg_faces<true, kFP, kAP>(f, a + kAP, p * inv_dy, own, gl, gr);
-                else seg_faces<false, kFP, kAP>(f, a, p * inv_dy, own, gl, gr);
+                double* corr = sCorr + tid * kCorrPitch;
+                if (p > 0.0) seg_faces<true, kFP, kAP>(f, a + kAP, p * inv_dy, corr, own, gl, gr);
+                else seg_faces<false, kFP, kAP>(f, a, p * inv_dy, corr, own, gl, gr);
                 if (bcy == 0) seg_fold(own, gl, gr, t0, ny);
             }
         }
         __syncthreads();  // both tiles are read; they now take the results
-        if (wave == 0) {
+        if (xl) {
 #pragma unroll
             for (int i = 0; i < kTS; ++i) sF[line * kRP + kTS * seg + i] = live ? own[i] : 0.0;
         } else {
