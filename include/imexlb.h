@@ -211,6 +211,28 @@ imexlb_status imexlb_adjoint_bind(imexlb_ctx* ctx, void* d_adj_workspace);
 imexlb_status imexlb_adjoint_step(imexlb_ctx* ctx, const void* d_Fn, const double* d_lam_np1,
                                   double* d_lam_n);
 
+/* Recorded steps, for reverse sweeps that walk a segment of steps again:
+ * the stage sources G3, G4 of Table I's third and fourth stages (storage
+ * type, ABI layout) and the moments M^n, M3, M4 of one step (FP64, fields
+ * (n, u_x, [u_y], T)), laid out G3 | G4 | M^n | M3 | M4, each part 256-byte
+ * aligned.  imexlb_step_record_bytes: size of one record. */
+size_t imexlb_step_record_bytes(const imexlb_ctx* ctx);
+
+/* One IMEX step, as imexlb_step(ctx, 1), that also leaves the step's stage
+ * sources and moments in d_record (device, 256-byte aligned,
+ * imexlb_step_record_bytes; caller-owned).  Asynchronous unless
+ * check_physical is set.  Errors: as imexlb_step; EINVAL for a NULL or
+ * misaligned record. */
+imexlb_status imexlb_step_recorded(imexlb_ctx* ctx, void* d_record);
+
+/* imexlb_adjoint_step for the step that imexlb_step_recorded took from
+ * d_Fn, reading the step's stage sources and moments from its record
+ * instead of recomputing them (the forward passes 3 and 4).  Same result as
+ * imexlb_adjoint_step.  Errors: as imexlb_adjoint_step; EINVAL for a NULL
+ * or misaligned record. */
+imexlb_status imexlb_adjoint_step_recorded(imexlb_ctx* ctx, const void* d_Fn, const void* d_record,
+                                           const double* d_lam_np1, double* d_lam_n);
+
 /* dF = V^T dA: the transpose of the MP-9 advection operator of
  * imexlb_advect at the FP64 plane-set d_F (Sec. IV), for an FP64 plane-set
  * dA; the linearisation follows the limiter decisions at d_F.  d_dF must not

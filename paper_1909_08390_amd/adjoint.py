@@ -6,8 +6,10 @@ The forward pass starts from the local equilibrium of the initial fields
 the state every ``every`` steps.  The backward pass seeds the adjoint from
 the gradients of the final moments (``imexlb_moments_adjoint``), then walks
 the segments backwards: each segment is recomputed forward from its
-checkpoint, storing its states, and the adjoint steps run through them in
-reverse; the equilibrium adjoint (``imexlb_equilibrium_adjoint``) finally
+checkpoint, storing its states and each step's stage sources and moments
+(``imexlb_step_recorded``), and the adjoint steps run through them in
+reverse without recomputing those (``imexlb_adjoint_step_recorded``); the
+equilibrium adjoint (``imexlb_equilibrium_adjoint``) finally
 maps the adjoint state to gradients of the initial fields.  The density loss
 and its gradient come from ``imexlb_density_loss``.  Every step of this runs
 in the library's HIP kernels; this module only orders the calls and holds
@@ -56,12 +58,13 @@ class EquilibriumRollout(torch.autograd.Function):
             start = seg * ctx.every
             end = min(start + ctx.every, ctx.nsteps)
             s.set_state(ctx.checkpoints[seg])
-            states = []
+            states, records = [], []
             for _ in range(start, end):
                 states.append(s.state.clone())
-                s.step(1)
-            for F in reversed(states):
-                lam = s.adjoint_step(F, lam)
+                records.append(s.new_record())
+                s.step_recorded(records[-1])
+            for F, rec in zip(reversed(states), reversed(records)):
+                lam = s.adjoint_step(F, lam, record=rec)
         dn, dux, duy, dT = s.equilibrium_adjoint(n0, ux0, uy0, T0, lam)
         return dn, dux, duy, dT, None, None, None
 

@@ -568,18 +568,36 @@ imexlb_status imexlb_get_state(const imexlb_ctx* c, void* F) {
 
 namespace {
 
+// Where a recorded step puts its stage sources and moments (caller memory,
+// imexlb_step_record_bytes): G3 | G4 (storage type) | M^n | M3 | M4 (FP64).
+struct StepRecord {
+    void *G3, *G4;
+    double *Mn, *M3, *M4;
+};
+
+size_t record_ps(const imexlb_ctx* c) { return align256((size_t)c->nplanes * c->cells * c->elem); }
+size_t record_ms(const imexlb_ctx* c) { return align256((size_t)c->nf * c->cells * sizeof(double)); }
+
+StepRecord record_of(const imexlb_ctx* c, const void* rec) {
+    char* b = (char*)rec;
+    const size_t ps = record_ps(c), ms = record_ms(c);
+    return StepRecord{b, b + ps, (double*)(b + 2 * ps), (double*)(b + 2 * ps + ms), (double*)(b + 2 * ps + 2 * ms)};
+}
+
 // The launch sequence of nsteps IMEX steps.  When ev is non-NULL it holds
-// 3 * nsteps + 1 events recorded around the passes.
-imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev) {
+// 3 * nsteps + 1 events recorded around the passes.  With rec (one step),
+// the stage sources G3, G4 and the moments M3, M4 go to the record instead
+// of the workspace.
+imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev, const StepRecord* rec = nullptr) {
     const int d = c->cfg.d;
     const bool f32 = c->cfg.storage == IMEXLB_F32;
     StageArgs a = base_args(c);
     void* F = c->d_state;
-    void* G3 = work_g(c, 0);
-    void* G4 = work_g(c, 1);
+    void* G3 = rec ? rec->G3 : work_g(c, 0);
+    void* G4 = rec ? rec->G4 : work_g(c, 1);
     double* Mn = work_m(c, 0);
-    double* M3 = work_m(c, 1);
-    double* M4 = work_m(c, 2);
+    double* M3 = rec ? rec->M3 : work_m(c, 1);
+    double* M4 = rec ? rec->M4 : work_m(c, 2);
     StageArgs pa[3];
     pass_args(a, F, G3, G4, Mn, M3, M4, pa);
     const StageArgs &a3 = pa[0], &a4 = pa[1], &a5 = pa[2];
@@ -624,6 +642,24 @@ imexlb_status imexlb_step(imexlb_ctx* c, int nsteps) {
     if (nsteps < 0) return fail(c, IMEXLB_EINVAL, "step: nsteps < 0");
     if (need_state(c) != IMEXLB_OK) return fail(c, IMEXLB_ESTATE, "step: no bound state");
     imexlb_status st = run_steps(c, nsteps, nullptr);
+    return st == IMEXLB_OK ? finish_check(c) : st;
+}
+
+size_t imexlb_step_record_bytes(const imexlb_ctx* c) {
+    return c ? 2 * record_ps(c) + 3 * record_ms(c) : 0;
+}
+
+imexlb_status imexlb_step_recorded(imexlb_ctx* c, void* d_record) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!d_record) return fail(c, IMEXLB_EINVAL, "step_recorded: NULL record");
+    if ((uintptr_t)d_record & 255) return fail(c, IMEXLB_EINVAL, "step_recorded: record must be 256-byte aligned");
+    if (need_state(c) != IMEXLB_OK) return fail(c, IMEXLB_ESTATE, "step_recorded: no bound state");
+    const StepRecord r = record_of(c, d_record);
+    // M^n before pass 5 overwrites it with M^{n+1}
+    hipError_t e = hipMemcpyAsync(r.Mn, work_m(c, 0), (size_t)c->nf * c->cells * sizeof(double),
+                                  hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "step_recorded");
+    imexlb_status st = run_steps(c, 1, nullptr, &r);
     return st == IMEXLB_OK ? finish_check(c) : st;
 }
 
@@ -799,29 +835,23 @@ imexlb_status imexlb_adjoint_bind(imexlb_ctx* c, void* d_adj) {
     return IMEXLB_OK;
 }
 
-imexlb_status imexlb_adjoint_step(imexlb_ctx* c, const void* Fn, const double* lam1, double* lam0) {
-    if (!c) return IMEXLB_EINVAL;
-    if (!c->d_adj) return fail(c, IMEXLB_ESTATE, "adjoint_step: no adjoint workspace bound");
-    if (!Fn || !lam1 || !lam0) return fail(c, IMEXLB_EINVAL, "adjoint_step: NULL buffer");
-    if ((const void*)lam1 == (const void*)lam0) return fail(c, IMEXLB_EINVAL, "adjoint_step: lam1 and lam0 alias");
+}  // extern "C"
+
+namespace {
+
+// The reverse sweep of one step taken from Fn, given the step's stage
+// sources G3, G4 and the moments M^n, M3, M4.
+imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const void* G4, const double* Mn,
+                           const double* M3, const double* M4, const double* lam1, double* lam0) {
     const int d = c->cfg.d;
     const bool f32 = c->cfg.storage == IMEXLB_F32;
     const long long cells = c->cells;
     const double chi = (double)(c->cfg.K + kDTotal - d), dk = (double)(kDTotal + c->cfg.K);
     hipStream_t s = c->stream;
-    // forward recompute of the stage sources: G3 = S_3, G4 = S_4 and moments
-    void* Fs = adj_s(c, 0);
-    void* G3 = adj_s(c, 1);
-    void* G4 = adj_s(c, 2);
-    double *Mn = adj_m(c, 0), *M3 = adj_m(c, 1), *M4 = adj_m(c, 2), *dM = adj_m(c, 3);
+    double* dM = adj_m(c, 3);
     double *X1 = adj_x(c, 0), *X2 = adj_x(c, 1), *X3 = adj_x(c, 2), *X4 = adj_x(c, 3);
-    StageArgs a = base_args(c);
-    StageArgs pa[3];
-    pass_args(a, Fs, G3, G4, Mn, M3, M4, pa);
-    hipError_t e = hipMemcpyAsync(Fs, Fn, imexlb_state_bytes(c), hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = launch_moments(d, f32, c->d_tab, Fn, Mn, cells, cells, dk, s);
-    if (e == hipSuccess) e = launch_stage(d, f32, kStage3, pa[0], s);
-    if (e == hipSuccess) e = launch_stage(d, f32, kStage4, pa[1], s);
+    const StageArgs a = base_args(c);
+    hipError_t e = hipSuccess;
     // coefficients (w = dt/tau, cc = alpha w)
     const double dt = a.dt, w = a.omega, cc = kAlpha * w, a1 = a.a1, a2 = a.a2;
     const double b2 = cc * cc / ((1.0 + cc) * (1.0 + cc));
@@ -886,6 +916,49 @@ imexlb_status imexlb_adjoint_step(imexlb_ctx* c, const void* Fn, const double* l
     if (e == hipSuccess) e = momt(Mn, lam0, lam0);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     return IMEXLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+
+imexlb_status imexlb_adjoint_step(imexlb_ctx* c, const void* Fn, const double* lam1, double* lam0) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!c->d_adj) return fail(c, IMEXLB_ESTATE, "adjoint_step: no adjoint workspace bound");
+    if (!Fn || !lam1 || !lam0) return fail(c, IMEXLB_EINVAL, "adjoint_step: NULL buffer");
+    if ((const void*)lam1 == (const void*)lam0) return fail(c, IMEXLB_EINVAL, "adjoint_step: lam1 and lam0 alias");
+    const int d = c->cfg.d;
+    const bool f32 = c->cfg.storage == IMEXLB_F32;
+    const long long cells = c->cells;
+    const double dk = (double)(kDTotal + c->cfg.K);
+    hipStream_t s = c->stream;
+    // forward recompute of the stage sources: G3 = S_3, G4 = S_4 and moments
+    void* Fs = adj_s(c, 0);
+    void* G3 = adj_s(c, 1);
+    void* G4 = adj_s(c, 2);
+    double *Mn = adj_m(c, 0), *M3 = adj_m(c, 1), *M4 = adj_m(c, 2);
+    StageArgs pa[3];
+    pass_args(base_args(c), Fs, G3, G4, Mn, M3, M4, pa);
+    hipError_t e = hipMemcpyAsync(Fs, Fn, imexlb_state_bytes(c), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_moments(d, f32, c->d_tab, Fn, Mn, cells, cells, dk, s);
+    if (e == hipSuccess) e = launch_stage(d, f32, kStage3, pa[0], s);
+    if (e == hipSuccess) e = launch_stage(d, f32, kStage4, pa[1], s);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
+    return adjoint_core(c, Fn, G3, G4, Mn, M3, M4, lam1, lam0);
+}
+
+imexlb_status imexlb_adjoint_step_recorded(imexlb_ctx* c, const void* Fn, const void* d_record,
+                                           const double* lam1, double* lam0) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!c->d_adj) return fail(c, IMEXLB_ESTATE, "adjoint_step_recorded: no adjoint workspace bound");
+    if (!Fn || !d_record || !lam1 || !lam0) return fail(c, IMEXLB_EINVAL, "adjoint_step_recorded: NULL buffer");
+    if ((uintptr_t)d_record & 255)
+        return fail(c, IMEXLB_EINVAL, "adjoint_step_recorded: record must be 256-byte aligned");
+    if ((const void*)lam1 == (const void*)lam0)
+        return fail(c, IMEXLB_EINVAL, "adjoint_step_recorded: lam1 and lam0 alias");
+    const StepRecord r = record_of(c, d_record);
+    return adjoint_core(c, Fn, r.G3, r.G4, r.Mn, r.M3, r.M4, lam1, lam0);
 }
 
 imexlb_status imexlb_advect_adjoint(const imexlb_ctx* c, const double* F, const double* dA, double* dF) {

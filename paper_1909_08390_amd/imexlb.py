@@ -113,6 +113,10 @@ def lib():
         L.imexlb_adjoint_workspace_bytes.restype = ctypes.c_size_t
         L.imexlb_adjoint_bind.argtypes = [_vp, _vp]
         L.imexlb_adjoint_step.argtypes = [_vp, _vp, _vp, _vp]
+        L.imexlb_step_record_bytes.argtypes = [_vp]
+        L.imexlb_step_record_bytes.restype = ctypes.c_size_t
+        L.imexlb_step_recorded.argtypes = [_vp, _vp]
+        L.imexlb_adjoint_step_recorded.argtypes = [_vp] * 5
         L.imexlb_moments_adjoint.argtypes = [_vp] * 7
         L.imexlb_advect_adjoint.argtypes = [_vp] * 4
         L.imexlb_equilibrium_adjoint.argtypes = [_vp] * 10
@@ -395,14 +399,33 @@ class Solver:
         assert tuple(t.shape) == tuple(self.cfg.shape)
         return t
 
-    def adjoint_step(self, Fn, lam1):
-        """(dF^{n+1}/dF^n)^T lam1 for the step taken from state Fn."""
+    def new_record(self):
+        """A device buffer for one recorded step (imexlb_step_record_bytes)."""
+        nb = self.L.imexlb_step_record_bytes(self._h)
+        return self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+
+    def step_recorded(self, record):
+        """One step that also leaves its stage sources and moments in record
+        (a buffer from new_record) for adjoint_step."""
+        assert record.numel() >= self.L.imexlb_step_record_bytes(self._h) and record.data_ptr() % 256 == 0
+        self._check(self.L.imexlb_step_recorded(self._h, _vp(record.data_ptr())), "step_recorded")
+
+    def adjoint_step(self, Fn, lam1, record=None):
+        """(dF^{n+1}/dF^n)^T lam1 for the step taken from state Fn; with the
+        record that step_recorded left for that step, the forward stage
+        sources are read instead of recomputed."""
         self.adjoint_bind()
         Fn = self.torch.as_tensor(Fn, dtype=self.state_dtype, device=self.device).contiguous()
         lam1 = self._dev_planes64(lam1)
         lam0 = self.torch.empty_like(lam1)
-        self._check(self.L.imexlb_adjoint_step(self._h, _vp(Fn.data_ptr()), _vp(lam1.data_ptr()),
-                                               _vp(lam0.data_ptr())), "adjoint_step")
+        if record is None:
+            st = self.L.imexlb_adjoint_step(self._h, _vp(Fn.data_ptr()), _vp(lam1.data_ptr()),
+                                            _vp(lam0.data_ptr()))
+        else:
+            assert record.numel() >= self.L.imexlb_step_record_bytes(self._h)
+            st = self.L.imexlb_adjoint_step_recorded(self._h, _vp(Fn.data_ptr()), _vp(record.data_ptr()),
+                                                     _vp(lam1.data_ptr()), _vp(lam0.data_ptr()))
+        self._check(st, "adjoint_step")
         return lam0
 
     def advect_adjoint(self, F, dA):

@@ -73,6 +73,9 @@ def test_null_arguments():
     assert L.imexlb_step(None, 1) == I.EINVAL
     assert L.imexlb_bind(None, None, None) == I.EINVAL
     assert L.imexlb_density_loss(None, None, None, None, None) == I.EINVAL
+    assert L.imexlb_step_recorded(None, None) == I.EINVAL
+    assert L.imexlb_adjoint_step_recorded(None, None, None, None, None) == I.EINVAL
+    assert L.imexlb_step_record_bytes(None) == 0
 
 
 def test_config_mirror_matches_header_layout(tmp_path):

@@ -128,6 +128,30 @@ def test_adjoint_step_dot_product(case, kind):
     assert err < tol, (lhs, err)
 
 
+@pytest.mark.parametrize("case,kind", [STEP_CASES[1], STEP_CASES[4], STEP_CASES[7]])
+def test_recorded_step_and_adjoint_match_the_recomputing_ones(case, kind):
+    """step_recorded steps exactly like step, and the adjoint step that reads
+    the record equals the one that recomputes the stage sources, bit for bit
+    (the same kernels on the same inputs); FP64 and FP32 storage."""
+    torch = _torch()
+    for storage in (I.F64, I.F32):
+        c = I.Config(storage=storage, **case)
+        s = base_state(c, kind, 5)
+        F = s.state.clone()
+        s.set_state(F)  # both runs start from the moments set_state computes
+        s.step(1)
+        plain = s.state.clone()
+        s.set_state(F)
+        rec = s.new_record()
+        s.step_recorded(rec)
+        assert torch.equal(s.state, plain)
+        rng = np.random.Generator(np.random.PCG64(3))
+        lam = torch.as_tensor(rng.normal(size=c.shape), device="cuda")
+        a = s.adjoint_step(F, lam)
+        b = s.adjoint_step(F, lam, record=rec)
+        assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("d", [1, 2])
 def test_moment_and_equilibrium_adjoints(d):
     torch = _torch()
