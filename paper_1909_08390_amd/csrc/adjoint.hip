@@ -26,19 +26,6 @@ namespace {
 
 constexpr int kAdjBlock = 256;
 
-// Up to four FP64 plane-sets combined as sum_j c_j Y_j.
-struct Lin4 {
-    const double* y[4];
-    double c[4];
-    int n;
-};
-
-__device__ __forceinline__ double lin_at(const Lin4& L, size_t i) {
-    double r = 0.0;
-    for (int j = 0; j < L.n; ++j) r = fma(L.c[j], L.y[j][i], r);
-    return r;
-}
-
 // g, dg/du, dg/dT of one axis factor (runtime order Q <= kQMax).
 __device__ __forceinline__ void herm_factor_d(CDp h, int Q, double u, double th, double& g, double& gu,
                                               double& gT) {
@@ -576,13 +563,15 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
     }
 }
 
-// out = a src + b E(M) as FP64 (stage value rebuilt from its moments).
-template <typename S, int D>
+// out = a src + b E(M) as FP64 (stage value rebuilt from its moments).  The
+// x factors of a set are evaluated once per cell; a row of planes (one y
+// node) is read with all its loads in flight.
+template <typename S, int D, int QM>
 __global__ void __launch_bounds__(kAdjBlock) materialise_kernel(const DevTables* __restrict__ tabp,
                                                                 const S* __restrict__ src,
                                                                 const double* __restrict__ M, double a,
-                                                                double b, double* out, long long cells,
-                                                                double chi_fac) {
+                                                                double b, double* __restrict__ out,
+                                                                long long cells, double chi_fac) {
     CTab* tab = (CTab*)tabp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
@@ -592,23 +581,32 @@ __global__ void __launch_bounds__(kAdjBlock) materialise_kernel(const DevTables*
     for (int set = 0; set < 2; ++set) {
         const int Q = tab->q[set];
         const double pre = set ? chi_fac * nn * (th + 1.0) : nn;
+        double gx[QM];
+#pragma unroll
+        for (int kx = 0; kx < QM; ++kx) gx[kx] = kx < Q ? herm_factor(tab->h[set][kx], Q, u, th) : 0.0;
         for (int ky = 0; ky < (D == 2 ? Q : 1); ++ky) {
-            const double gy = D == 2 ? pre * herm_factor(tab->h[set][ky], Q, w, th) : pre;
-            for (int kx = 0; kx < Q; ++kx, ++v) {
-                const size_t i = (size_t)v * cells + c;
-                out[i] = fma(a, (double)src[i], b * gy * herm_factor(tab->h[set][kx], Q, u, th));
-            }
+            const double gy = b * (D == 2 ? pre * herm_factor(tab->h[set][ky], Q, w, th) : pre);
+            double sv[QM];
+#pragma unroll
+            for (int kx = 0; kx < QM; ++kx) sv[kx] = kx < Q ? (double)src[(size_t)(v + kx) * cells + c] : 0.0;
+#pragma unroll
+            for (int kx = 0; kx < QM; ++kx)
+                if (kx < Q) out[(size_t)(v + kx) * cells + c] = fma(a, sv[kx], gy * gx[kx]);
+            v += Q;
         }
     }
 }
 
-// dM = (dE/dM)^T dE per cell, dE = sum_j c_j Y_j.  Moments (n, u, T) of M.
-// The x factors (and their u and T derivatives) of the QM or fewer nodes of
-// a set are evaluated once per cell and set, then reused by every y group.
+// dM = (dE/dM)^T dE per cell for the FP64 plane-set dE.  Moments (n, u, T)
+// of M.  The x factors (and their u and T derivatives) of the QM or fewer
+// nodes of a set are evaluated once per cell and set, then reused by every
+// y group.
 template <int D, int QM>
 __global__ void __launch_bounds__(kAdjBlock) eq_adjoint_kernel(const DevTables* __restrict__ tabp,
-                                                               const double* __restrict__ M, Lin4 dE,
-                                                               double* dM, long long cells, double chi_fac) {
+                                                               const double* __restrict__ M,
+                                                               const double* __restrict__ dE,
+                                                               double* __restrict__ dM, long long cells,
+                                                               double chi_fac) {
     CTab* tab = (CTab*)tabp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
@@ -630,12 +628,15 @@ __global__ void __launch_bounds__(kAdjBlock) eq_adjoint_kernel(const DevTables* 
             if (kx < Q) herm_factor_d(tab->h[set][kx], Q, u, th, gx[kx], gxu[kx], gxT[kx]);
         }
         for (int ky = 0; ky < (D == 2 ? Q : 1); ++ky) {
+            double ev[QM];  // the row's loads, all in flight
+#pragma unroll
+            for (int kx = 0; kx < QM; ++kx) ev[kx] = kx < Q ? dE[(size_t)(v + kx) * cells + c] : 0.0;
             double gy = 1.0, gyu = 0.0, gyT = 0.0;
             if (D == 2) herm_factor_d(tab->h[set][ky], Q, w, th, gy, gyu, gyT);
 #pragma unroll
             for (int kx = 0; kx < QM; ++kx) {
                 if (kx < Q) {
-                    const double e = lin_at(dE, (size_t)(v + kx) * cells + c);
+                    const double e = ev[kx];
                     dn = fma(e, pre_n * gx[kx] * gy, dn);
                     dux = fma(e, pre * gxu[kx] * gy, dux);
                     if (D == 2) duy = fma(e, pre * gx[kx] * gyu, duy);
@@ -651,71 +652,66 @@ __global__ void __launch_bounds__(kAdjBlock) eq_adjoint_kernel(const DevTables* 
     dM[(D + 1) * cells + c] = dT;
 }
 
-// out (=|+=) sum_j c_j Y_j + (dM/dF)^T dM per plane (dM may be NULL).
+// out = y + (dM/dF)^T dM per plane (y may be NULL: zero; it may also be out
+// itself, each element being read before it is written).
 // n = sum_phi F, n u = sum_phi p F, (D+K) n T = sum_phi |p|^2 F + sum_chi F - n |u|^2:
 //   dn/dF = [phi], du/dF = [phi] (p - u)/n,
 //   dT/dF = ([phi] |p - u|^2 + [chi]) / ((D+K) n) - [phi] T / n.
+// Planes go in groups of kMomGroup, the group's loads in flight together.
+constexpr int kMomGroup = 8;
+
 template <int D>
 __global__ void __launch_bounds__(kAdjBlock) mom_adjoint_kernel(const DevTables* __restrict__ tabp,
                                                                 const double* __restrict__ M,
-                                                                const double* __restrict__ dM, Lin4 Y,
-                                                                double* out, long long cells, double dk,
-                                                                int accumulate) {
+                                                                const double* __restrict__ dM, const double* y,
+                                                                double* out, long long cells, double dk) {
     CTab* tab = (CTab*)tabp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
-    double nn = 1.0, u = 0.0, w = 0.0, T = 0.0, gn = 0.0, gu = 0.0, gw = 0.0, gT = 0.0;
-    if (dM) {
-        nn = M[c];
-        u = M[cells + c];
-        w = D == 2 ? M[2 * cells + c] : 0.0;
-        T = M[(D + 1) * cells + c];
-        gn = dM[c];
-        gu = dM[cells + c];
-        gw = D == 2 ? dM[2 * cells + c] : 0.0;
-        gT = dM[(D + 1) * cells + c];
-    }
+    const double nn = M[c], u = M[cells + c], w = D == 2 ? M[2 * cells + c] : 0.0;
+    const double T = M[(D + 1) * cells + c];
+    const double gn = dM[c], gu = dM[cells + c], gw = D == 2 ? dM[2 * cells + c] : 0.0;
+    const double gT = dM[(D + 1) * cells + c];
     const double inv_n = 1.0 / nn, inv_dkn = 1.0 / (dk * nn);
+    // the terms of a phi plane: gn + (gu (px - u) + gw (py - w)) / n + gT (|p - u|^2 / ((D+K) n) - T / n);
+    // of a chi plane: gT / ((D+K) n)
+    const double chi_term = gT * inv_dkn;
     const int np = tab->nplanes;
-    for (int v = 0; v < np; ++v) {
-        const size_t i = (size_t)v * cells + c;
-        double r = lin_at(Y, i);
-        if (dM) {
-            const double px = tab->plane[v].px, py = tab->plane[v].py;
-            if (tab->plane[v].set == 0) {
-                const double ex = px - u, ey = py - w;
-                r += gn + (gu * ex + gw * ey) * inv_n + gT * ((ex * ex + ey * ey) * inv_dkn - T * inv_n);
-            } else {
-                r += gT * inv_dkn;
+    for (int v0 = 0; v0 < np; v0 += kMomGroup) {
+        double r[kMomGroup];
+#pragma unroll
+        for (int k = 0; k < kMomGroup; ++k) r[k] = (y && v0 + k < np) ? y[(size_t)(v0 + k) * cells + c] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kMomGroup; ++k) {
+            const int v = v0 + k;
+            if (v < np) {
+                double t = chi_term;
+                if (tab->plane[v].set == 0) {
+                    const double ex = tab->plane[v].px - u, ey = tab->plane[v].py - w;
+                    t = gn + (gu * ex + gw * ey) * inv_n + gT * ((ex * ex + ey * ey) * inv_dkn - T * inv_n);
+                }
+                out[(size_t)v * cells + c] = r[k] + t;
             }
         }
-        out[i] = accumulate ? out[i] + r : r;
     }
-}
-
-Lin4 make_lin(int n, const double* const* y, const double* cf) {
-    Lin4 L;
-    L.n = n;
-    for (int j = 0; j < 4; ++j) {
-        L.y[j] = j < n ? y[j] : nullptr;
-        L.c[j] = j < n ? cf[j] : 0.0;
-    }
-    return L;
 }
 
 }  // namespace
 
-hipError_t launch_materialise(int d, bool f32, const DevTables* tab, const void* src, const double* M,
+hipError_t launch_materialise(int d, int qm, bool f32, const DevTables* tab, const void* src, const double* M,
                               double a, double b, double* out, long long cells, double chi_fac,
                               hipStream_t s) {
     const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
+#define IMEXLB_MAT(S, D, QM) \
+    hipLaunchKernelGGL((materialise_kernel<S, D, QM>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const S*)src, M, a, b, out, cells, chi_fac)
     if (d == 2) {
-        if (f32) hipLaunchKernelGGL((materialise_kernel<float, 2>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const float*)src, M, a, b, out, cells, chi_fac);
-        else hipLaunchKernelGGL((materialise_kernel<double, 2>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const double*)src, M, a, b, out, cells, chi_fac);
+        if (qm == 8) { if (f32) IMEXLB_MAT(float, 2, 8); else IMEXLB_MAT(double, 2, 8); }
+        else { if (f32) IMEXLB_MAT(float, 2, 16); else IMEXLB_MAT(double, 2, 16); }
     } else {
-        if (f32) hipLaunchKernelGGL((materialise_kernel<float, 1>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const float*)src, M, a, b, out, cells, chi_fac);
-        else hipLaunchKernelGGL((materialise_kernel<double, 1>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const double*)src, M, a, b, out, cells, chi_fac);
+        if (qm == 8) { if (f32) IMEXLB_MAT(float, 1, 8); else IMEXLB_MAT(double, 1, 8); }
+        else { if (f32) IMEXLB_MAT(float, 1, 16); else IMEXLB_MAT(double, 1, 16); }
     }
+#undef IMEXLB_MAT
     return hipGetLastError();
 }
 
@@ -757,28 +753,24 @@ hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const
     }
 }
 
-hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, int ny_in,
-                             const double* const* y, const double* cf, double* dM, long long cells,
-                             double chi_fac, hipStream_t s) {
-    const Lin4 L = make_lin(ny_in, y, cf);
+hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, const double* dE, double* dM,
+                             long long cells, double chi_fac, hipStream_t s) {
     const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
     if (d == 2) {
-        if (qm == 8) hipLaunchKernelGGL((eq_adjoint_kernel<2, 8>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
-        else hipLaunchKernelGGL((eq_adjoint_kernel<2, 16>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
+        if (qm == 8) hipLaunchKernelGGL((eq_adjoint_kernel<2, 8>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dE, dM, cells, chi_fac);
+        else hipLaunchKernelGGL((eq_adjoint_kernel<2, 16>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dE, dM, cells, chi_fac);
     } else {
-        if (qm == 8) hipLaunchKernelGGL((eq_adjoint_kernel<1, 8>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
-        else hipLaunchKernelGGL((eq_adjoint_kernel<1, 16>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, L, dM, cells, chi_fac);
+        if (qm == 8) hipLaunchKernelGGL((eq_adjoint_kernel<1, 8>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dE, dM, cells, chi_fac);
+        else hipLaunchKernelGGL((eq_adjoint_kernel<1, 16>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dE, dM, cells, chi_fac);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, const double* dM, int ny_in,
-                              const double* const* y, const double* cf, double* out, long long cells,
-                              double dk, bool accumulate, hipStream_t s) {
-    const Lin4 L = make_lin(ny_in, y, cf);
+hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, const double* dM, const double* y,
+                              double* out, long long cells, double dk, hipStream_t s) {
     const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
-    if (d == 2) hipLaunchKernelGGL((mom_adjoint_kernel<2>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dM, L, out, cells, dk, (int)accumulate);
-    else hipLaunchKernelGGL((mom_adjoint_kernel<1>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dM, L, out, cells, dk, (int)accumulate);
+    if (d == 2) hipLaunchKernelGGL((mom_adjoint_kernel<2>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dM, y, out, cells, dk);
+    else hipLaunchKernelGGL((mom_adjoint_kernel<1>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dM, y, out, cells, dk);
     return hipGetLastError();
 }
 

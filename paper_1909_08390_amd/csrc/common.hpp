@@ -151,9 +151,10 @@ hipError_t launch_density_loss(const double* n, const double* target, long long 
 hipError_t launch_check_reset(int* flag, hipStream_t s);
 hipError_t launch_check(int d, const double* M, long long ms, long long cells, int code, int* flag,
                         hipStream_t s);
-// Adjoint building blocks (adjoint.hip).  y / cf: up to four FP64
-// plane-sets combined as sum_j cf[j] y[j].
-hipError_t launch_materialise(int d, bool f32, const DevTables* tab, const void* src, const double* M,
+// Adjoint building blocks (adjoint.hip): the stage value F = a src + b E(M)
+// as FP64; dM = (dE/dM)^T dE; out = y + (dM/dF)^T dM (y NULL: zero; y may
+// be out).
+hipError_t launch_materialise(int d, int qm, bool f32, const DevTables* tab, const void* src, const double* M,
                               double a, double b, double* out, long long cells, double chi_fac,
                               hipStream_t s);
 // Transposed advection: with dA = sum_j c[j] z[j] (the adjoint of the
@@ -170,12 +171,10 @@ struct AdvAdjIO {
 };
 hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const double* F, const AdvAdjIO& io,
                                  int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy, hipStream_t s);
-hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, int ny_in,
-                             const double* const* y, const double* cf, double* dM, long long cells,
-                             double chi_fac, hipStream_t s);
-hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, const double* dM, int ny_in,
-                              const double* const* y, const double* cf, double* out, long long cells,
-                              double dk, bool accumulate, hipStream_t s);
+hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, const double* dE, double* dM,
+                             long long cells, double chi_fac, hipStream_t s);
+hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, const double* dM, const double* y,
+                              double* out, long long cells, double dk, hipStream_t s);
 
 // Batched 1D passes: one launch covers every tile of every tube.  targs[i]
 // holds tube i's arguments for this pass; tiles[j] = (tube, first cell).

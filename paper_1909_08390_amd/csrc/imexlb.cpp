@@ -882,23 +882,21 @@ imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const 
         return launch_advect_adjoint(d, c->d_tab, np, F, io, nx, ny, c->cfg.bc_x, c->cfg.bc_y, idx, idy, s);
     };
     auto eqt = [&](const double* M, const double* y) {
-        const double one = 1.0;
-        return launch_eq_adjoint(d, qm, c->d_tab, M, 1, &y, &one, dM, cells, chi, s);
+        return launch_eq_adjoint(d, qm, c->d_tab, M, y, dM, cells, chi, s);
     };
     auto momt = [&](const double* M, const double* y, double* out) {
-        const double one = 1.0;
-        return launch_mom_adjoint(d, c->d_tab, M, dM, 1, &y, &one, out, cells, dk, false, s);
+        return launch_mom_adjoint(d, c->d_tab, M, dM, y, out, cells, dk, s);
     };
     const double* L = lam1;
     // stage 4: F4 = a1 S4 + c a1 E4, dA4 = -(2/3) dt L, d(dF4) = -(2/3) L;
     // dE4 = c a1 V4 + (2/3) w a1 L, dS4 (before the moment term) = a1 V4 - (2/3) w a1 L
-    if (e == hipSuccess) e = launch_materialise(d, f32, c->d_tab, G4, M4, a1, cc * a1, X1, cells, chi, s);
+    if (e == hipSuccess) e = launch_materialise(d, qm, f32, c->d_tab, G4, M4, a1, cc * a1, X1, cells, chi, s);
     if (e == hipSuccess)
         e = adv(X1, {L}, {-(2.0 / 3.0) * dt}, cc * a1, {(2.0 / 3.0) * w * a1}, a1, {-(2.0 / 3.0) * w * a1}, X2, X4);
     if (e == hipSuccess) e = eqt(M4, X2);
     if (e == hipSuccess) e = momt(M4, X4, X3);  // X3 = dS4
     // stage 3: dA3 = -(1/6) dt L - dt/4 dS4, d(dF3) = -(1/6) L - kappa dS4
-    if (e == hipSuccess) e = launch_materialise(d, f32, c->d_tab, G3, M3, a1, cc * a1, X1, cells, chi, s);
+    if (e == hipSuccess) e = launch_materialise(d, qm, f32, c->d_tab, G3, M3, a1, cc * a1, X1, cells, chi, s);
     if (e == hipSuccess)
         e = adv(X1, {L, X3}, {-dt / 6.0, -0.25 * dt}, cc * a1, {w * a1 / 6.0, ka * w * a1}, a1,
                 {-w * a1 / 6.0, -ka * w * a1}, X2, X4);
@@ -907,7 +905,7 @@ imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const 
     // stages 2 and 1: F2 = a2 F^n + b2 E^n, dA2 = -(1/6) dt L - dt/4 dS4 - dt dS3,
     // d(dF1) = -beta dS4, d(dF2) = -(1/6) L - eta dS4 - (1 - alpha) dS3; the
     // moment adjoint's input goes straight to lam0 and is completed in place
-    if (e == hipSuccess) e = launch_materialise(d, f32, c->d_tab, Fn, Mn, a2, b2, X2, cells, chi, s);
+    if (e == hipSuccess) e = launch_materialise(d, qm, f32, c->d_tab, Fn, Mn, a2, b2, X2, cells, chi, s);
     if (e == hipSuccess)
         e = adv(X2, {L, X3, X1}, {-dt / 6.0, -0.25 * dt, -dt}, b2,
                 {w * a2 / 6.0, w * a1 * be + w * a2 * et, w * a2 * (1.0 - kAlpha)}, a2,
@@ -997,8 +995,7 @@ imexlb_status imexlb_moments_adjoint(imexlb_ctx* c, const void* F, const double*
     for (int f = 0; f < c->nf && e == hipSuccess; ++f)
         e = hipMemcpyAsync(dM + (size_t)f * cells, src[f], fb, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess)
-        e = launch_mom_adjoint(d, c->d_tab, M, dM, 0, nullptr, nullptr, lam, cells, (double)(kDTotal + c->cfg.K),
-                               false, s);
+        e = launch_mom_adjoint(d, c->d_tab, M, dM, nullptr, lam, cells, (double)(kDTotal + c->cfg.K), s);
     if (e != hipSuccess) return hip_fail(c, e, "moments_adjoint");
     return IMEXLB_OK;
 }
@@ -1019,10 +1016,8 @@ imexlb_status imexlb_equilibrium_adjoint(imexlb_ctx* c, const double* n, const d
     hipError_t e = hipSuccess;
     for (int f = 0; f < c->nf && e == hipSuccess; ++f)
         e = hipMemcpyAsync(M + (size_t)f * cells, src[f], fb, hipMemcpyDeviceToDevice, s);
-    const double* ys[1] = {lam};
-    const double cs[1] = {1.0};
     if (e == hipSuccess)
-        e = launch_eq_adjoint(d, base_args(c).qm, c->d_tab, M, 1, ys, cs, dM, cells, (double)(c->cfg.K + kDTotal - d), s);
+        e = launch_eq_adjoint(d, base_args(c).qm, c->d_tab, M, lam, dM, cells, (double)(c->cfg.K + kDTotal - d), s);
     double* dst[4] = {dn, dux, d == 2 ? duy : dT, dT};
     for (int f = 0; f < c->nf && e == hipSuccess; ++f)
         e = hipMemcpyAsync(dst[f], dM + (size_t)f * cells, fb, hipMemcpyDeviceToDevice, s);
