@@ -8,9 +8,10 @@
 //     Sec. IV.  A face value is linear in its nine upwind-biased nodes with
 //     the weights of F^L unless the monotonicity test clips it; a clipped
 //     face takes the derivative of the candidate the clip selected (F^min or
-//     F^max, through the minmod selections).  Gather form: each cell sums
-//     the contributions of the faces whose stencils read it (ghost nodes
-//     route to the cell they copy);
+//     F^max, through the minmod selections).  A node sums the contributions
+//     of the faces whose stencils read it (ghost nodes route to the node
+//     they copy): in 2D one tiled kernel for both axes, in 1D a row kernel
+//     with one face per lane;
 //   * the equilibrium Jacobian transposed: dM = (dE/dM)^T dE per cell, with
 //     dg/du = sum_l h_l l a_{l-1} and dg/dT = sum_l h_l l (l-1)/2 a_{l-2}
 //     (Eq. gExpanded; the a_l are Appell polynomials in u with variance T-1);
