@@ -36,6 +36,11 @@ METRIC = "velocity-node updates/s per IMEX step, FP32 vs FP64, % of HBM roofline
 KERNEL_SOURCES = ("paper_1909_08390_amd/csrc/kernels.hip", "paper_1909_08390_amd/csrc/common.hpp",
                   "paper_1909_08390_amd/csrc/device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_passes_riemann4096_hbm_traffic.txt")
+INSTS_FILE = os.path.join(ROOT, "profiles", "stage_passes_riemann4096_inst_mix.txt")
+# VALU lane-instruction peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes per cycle x 2.4 GHz.  An FP64 FMA and an
+# unpacked FP32 FMA each take one lane-slot; the 157.3 TFLOP/s FP32 figure counts packed FP32 (two FMAs per slot),
+# which this code does not use.
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -90,6 +95,28 @@ def read_traffic(size):
                 kv = dict(t.split("=") for t in tail.split())
                 out[f"{prec} {stage}"] = float(kv["traffic_bytes"])
     if meta.get("sha") != kernel_source_hash() or meta.get("size") != size:
+        return {}
+    return out
+
+
+def read_valu_per_vn(size):
+    """VALU lane-instructions per velocity node of each stage pass ("f64
+    stage4" etc.) from the committed instruction-mix summary; empty when it
+    is missing, was taken at another size or on other kernel sources."""
+    out, meta = {}, {}
+    if not os.path.exists(INSTS_FILE):
+        return out
+    with open(INSTS_FILE) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("source_sha256:"):
+                meta["sha"] = line.split(":", 1)[1].strip()
+            elif line.startswith("pass "):
+                head, tail = line.split(":", 1)
+                _, prec, stage = head.split()
+                kv = dict(t.split("=") for t in tail.split())
+                out[f"{prec} {stage}"] = float(kv["valu_per_vn"])
+    if meta.get("sha") != kernel_source_hash() or size != 4096:
         return {}
     return out
 
@@ -166,6 +193,23 @@ def run_precision(I, W, N, storage, steps, warmup, seed, horizon=0, tau=1e-7):
                        "algorithmic_bytes_per_launch": pb["stage4"],
                        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                        "copy-calibrated)"}
+    # the VALU view of every pass: lane-instructions per VN (committed
+    # counter summary) x VN / pass time, against the lane-slot peak
+    vpv = read_valu_per_vn(N)
+    if vpv:
+        valu = {}
+        for k2 in ("stage3", "stage4", "stage5"):
+            rate = vpv[f"{prec} {k2}"] * cells * planes / (per[k2] * 1e-3) / 1e12
+            valu[k2] = {"lane_insts_per_vn": vpv[f"{prec} {k2}"], "achieved": rate, "frac": rate / VALU_PEAK_T}
+        res["roofline"]["valu"] = {"peak": VALU_PEAK_T, "unit": "T lane-instructions/s", "passes": valu,
+                                   "source": "profiles/stage_passes_riemann4096_inst_mix.txt (SQ_INSTS_VALU)"}
+        if valu["stage4"]["frac"] > res["roofline"]["frac"]:
+            # the pass is closer to its VALU peak than to HBM: report that bound,
+            # the HBM view beside it
+            hbm = {key: res["roofline"][key] for key in ("achieved", "peak", "unit", "frac")}
+            res["roofline"].update({"bound": "alu", "achieved": valu["stage4"]["achieved"], "peak": VALU_PEAK_T,
+                                    "unit": "T lane-instructions/s", "frac": valu["stage4"]["frac"],
+                                    "hbm": hbm})
     res["moments"] = s.moments()  # (n, ux, uy, T) after warmup + timed steps
     done = warmup + steps
     if horizon > done:

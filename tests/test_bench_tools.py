@@ -42,3 +42,20 @@ def test_committed_traffic_summary_matches_the_kernels():
         alg = bench.pass_bytes(128, 4096 * 4096, 8 if prec == "f64" else 4, 4)[stage]
         assert 1.0 <= traffic / alg < 2.0, (key, traffic / alg)
     assert bench.read_traffic(1024) == {}
+
+
+def test_valu_peak_from_unit_counts():
+    # 256 CUs x 4 SIMDs x 16 lanes per cycle at 2.4 GHz
+    assert abs(bench.VALU_PEAK_T - 39.3216) < 1e-9
+
+
+def test_committed_instruction_mix_matches_the_kernels():
+    v = bench.read_valu_per_vn(4096)
+    if not v:
+        pytest.skip("the instruction-mix summary was taken on other kernel code")
+    assert set(v) == {f"{p} stage{k}" for p in ("f64", "f32") for k in (3, 4, 5)}
+    # tens of lane-instructions per velocity node; stage 4 (two outputs, E^n
+    # at the own cells) the most
+    for prec in ("f64", "f32"):
+        assert 50 < v[f"{prec} stage3"] < v[f"{prec} stage4"] < 200
+    assert bench.read_valu_per_vn(1024) == {}
