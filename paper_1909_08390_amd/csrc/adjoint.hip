@@ -186,8 +186,8 @@ __device__ __forceinline__ void adj_store(const AdvAdjIO& o, size_t i, double V)
 // windows read t or a ghost node that copies t; each face is evaluated once
 // per node it feeds.  FWD: p > 0 (window F_{s-4} .. F_{s+4}), else the
 // mirrored window F_{s+5} .. F_{s-3}.
-template <bool FWD, int NZ>
-__device__ double adj_axis_dir(const double* F, const AdvAdjIO& o, size_t base, long long st, int n, int bc,
+template <bool FWD, int NZ, typename S>
+__device__ double adj_axis_dir(const S* F, const AdvAdjIO& o, size_t base, long long st, int n, int bc,
                                int t, double pinv) {
     int vlo = t, vhi = t;
     if (bc == 0) {
@@ -198,7 +198,7 @@ __device__ double adj_axis_dir(const double* F, const AdvAdjIO& o, size_t base, 
     for (int tv = vlo; tv <= vhi; ++tv) {
         double w17[17];  // nodes tv-8 .. tv+8
 #pragma unroll
-        for (int i = 0; i < 17; ++i) w17[i] = F[base + (size_t)bc_map(tv - 8 + i, n, bc) * st];
+        for (int i = 0; i < 17; ++i) w17[i] = (double)F[base + (size_t)bc_map(tv - 8 + i, n, bc) * st];
         double a10[10];  // dA at faces' nodes: FWD s = tv-4 .. tv+5, else s = tv-5 .. tv+4
 #pragma unroll
         for (int i = 0; i < 10; ++i) {
@@ -226,9 +226,9 @@ __device__ double adj_axis_dir(const double* F, const AdvAdjIO& o, size_t base, 
     return acc;
 }
 
-template <int NZ>
+template <int NZ, typename S>
 __global__ void __launch_bounds__(kAdjBlock) advect_adjoint_gather1d_kernel(const DevTables* __restrict__ tabp,
-                                                                            const double* __restrict__ F,
+                                                                            const S* __restrict__ F,
                                                                             AdvAdjIO o, int nx, int bc,
                                                                             double inv_dx) {
     CTab* tab = (CTab*)tabp;
@@ -238,8 +238,8 @@ __global__ void __launch_bounds__(kAdjBlock) advect_adjoint_gather1d_kernel(cons
     const double p = tab->plane[v].px;
     const size_t pl = (size_t)v * nx;
     double r = 0.0;
-    if (p > 0.0) r = adj_axis_dir<true, NZ>(F, o, pl, 1, nx, bc, x, p * inv_dx);
-    else if (p < 0.0) r = adj_axis_dir<false, NZ>(F, o, pl, 1, nx, bc, x, p * inv_dx);
+    if (p > 0.0) r = adj_axis_dir<true, NZ, S>(F, o, pl, 1, nx, bc, x, p * inv_dx);
+    else if (p < 0.0) r = adj_axis_dir<false, NZ, S>(F, o, pl, 1, nx, bc, x, p * inv_dx);
     adj_store<NZ>(o, pl + x, r);
 }
 
@@ -260,9 +260,9 @@ __device__ __forceinline__ int chunk_pos(bool fwd, int c0, int lane, int kk) {  
 // Chunks per work-group of the x-row kernel: one per wavefront.
 constexpr int kChunkWaves = 4;
 
-template <int NZ>
+template <int NZ, typename S>
 __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel(const DevTables* __restrict__ tabp,
-                                                                                 const double* __restrict__ F,
+                                                                                 const S* __restrict__ F,
                                                                                  AdvAdjIO o, int nx, int ny, int bc,
                                                                                  double inv_dx) {
     // per wavefront: F at nodes c0-8 .. c0+63, dA at c0-5 .. c0+66, and the
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel
     };
     if (live) {
         for (int i = lane; i < 72; i += 64) {
-            sF[i] = F[base + bc_map(c0 - 8 + i, n, bc)];
+            sF[i] = (double)F[base + bc_map(c0 - 8 + i, n, bc)];
             sA[i] = dat(c0 - 5 + i);
         }
     }
@@ -442,9 +442,9 @@ __device__ __forceinline__ void seg_fold(double (&own)[kTS], double gl, double g
     }
 }
 
-template <int NZ>
+template <int NZ, typename S>
 __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const DevTables* __restrict__ tabp,
-                                                                        const double* __restrict__ F, AdvAdjIO o,
+                                                                        const S* __restrict__ F, AdvAdjIO o,
                                                                         int nx, int ny, int bcx, int bcy,
                                                                         double inv_dx, double inv_dy, int ntx,
                                                                         int nplanes) {
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
     for (int v = (int)blockIdx.y * kTPB; v < v1; ++v) {
         const size_t pl = (size_t)v * cells;
 #pragma unroll
-        for (int j = 0; j < kNFL; ++j) sF[fl[j]] = F[pl + fo[j]];
+        for (int j = 0; j < kNFL; ++j) sF[fl[j]] = (double)F[pl + fo[j]];
 #pragma unroll
         for (int j = 0; j < kNAL; ++j) {
             const double v = adj_dA<NZ>(o, pl + ao[j]);
@@ -564,14 +564,16 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
     }
 }
 
-// out = a src + b E(M) as FP64 (stage value rebuilt from its moments).  The
-// x factors of a set are evaluated once per cell; a row of planes (one y
-// node) is read with all its loads in flight.
+// out = a src + b E(M) (stage value rebuilt from its moments), evaluated in
+// FP64 and stored in the storage type, as the forward's relax on read
+// stores it before the MP-9 sweeps.  The x factors of a set are evaluated
+// once per cell; a row of planes (one y node) is read with all its loads in
+// flight.
 template <typename S, int D, int QM>
 __global__ void __launch_bounds__(kAdjBlock) materialise_kernel(const DevTables* __restrict__ tabp,
                                                                 const S* __restrict__ src,
                                                                 const double* __restrict__ M, double a,
-                                                                double b, double* __restrict__ out,
+                                                                double b, S* __restrict__ out,
                                                                 long long cells, double chi_fac) {
     CTab* tab = (CTab*)tabp;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -592,7 +594,7 @@ __global__ void __launch_bounds__(kAdjBlock) materialise_kernel(const DevTables*
             for (int kx = 0; kx < QM; ++kx) sv[kx] = kx < Q ? (double)src[(size_t)(v + kx) * cells + c] : 0.0;
 #pragma unroll
             for (int kx = 0; kx < QM; ++kx)
-                if (kx < Q) out[(size_t)(v + kx) * cells + c] = fma(a, sv[kx], gy * gx[kx]);
+                if (kx < Q) out[(size_t)(v + kx) * cells + c] = (S)fma(a, sv[kx], gy * gx[kx]);
             v += Q;
         }
     }
@@ -700,11 +702,11 @@ __global__ void __launch_bounds__(kAdjBlock) mom_adjoint_kernel(const DevTables*
 }  // namespace
 
 hipError_t launch_materialise(int d, int qm, bool f32, const DevTables* tab, const void* src, const double* M,
-                              double a, double b, double* out, long long cells, double chi_fac,
+                              double a, double b, void* out, long long cells, double chi_fac,
                               hipStream_t s) {
     const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
 #define IMEXLB_MAT(S, D, QM) \
-    hipLaunchKernelGGL((materialise_kernel<S, D, QM>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const S*)src, M, a, b, out, cells, chi_fac)
+    hipLaunchKernelGGL((materialise_kernel<S, D, QM>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const S*)src, M, a, b, (S*)out, cells, chi_fac)
     if (d == 2) {
         if (qm == 8) { if (f32) IMEXLB_MAT(float, 2, 8); else IMEXLB_MAT(double, 2, 8); }
         else { if (f32) IMEXLB_MAT(float, 2, 16); else IMEXLB_MAT(double, 2, 16); }
@@ -718,40 +720,50 @@ hipError_t launch_materialise(int d, int qm, bool f32, const DevTables* tab, con
 
 namespace {
 
-template <int NZ>
-hipError_t launch_advect_adjoint_n(int d, const DevTables* tab, int nplanes, const double* F, const AdvAdjIO& io,
+template <int NZ, typename S>
+hipError_t launch_advect_adjoint_n(int d, const DevTables* tab, int nplanes, const S* F, const AdvAdjIO& io,
                                    int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy, hipStream_t s) {
     if (d == 2) {
         const int ntx = (nx + kTT - 1) / kTT, nty = (ny + kTT - 1) / kTT;
         const dim3 grid((unsigned)(ntx * nty), (unsigned)((nplanes + kTPB - 1) / kTPB));
-        hipLaunchKernelGGL(advect_adjoint_tile_kernel<NZ>, grid, dim3(kTThreads), 0, s, tab, F, io, nx, ny, bcx, bcy,
-                           inv_dx, inv_dy, ntx, nplanes);
+        hipLaunchKernelGGL((advect_adjoint_tile_kernel<NZ, S>), grid, dim3(kTThreads), 0, s, tab, F, io, nx, ny, bcx,
+                           bcy, inv_dx, inv_dy, ntx, nplanes);
         return hipGetLastError();
     }
     // 1D: rows in 64-face chunks; periodic lines shorter than a chunk's
     // window range take the gather form
     if (bcx == 1 && nx < 40) {
         const dim3 grid((unsigned)((nx + kAdjBlock - 1) / kAdjBlock), (unsigned)nplanes);
-        hipLaunchKernelGGL(advect_adjoint_gather1d_kernel<NZ>, grid, dim3(kAdjBlock), 0, s, tab, F, io, nx, bcx, inv_dx);
+        hipLaunchKernelGGL((advect_adjoint_gather1d_kernel<NZ, S>), grid, dim3(kAdjBlock), 0, s, tab, F, io, nx, bcx,
+                           inv_dx);
         return hipGetLastError();
     }
     const long long gx = ((nx + kChunk - 1) / kChunk + kChunkWaves - 1) / kChunkWaves;
-    hipLaunchKernelGGL(advect_adjoint_xchunk_kernel<NZ>, dim3((unsigned)gx, (unsigned)nplanes), dim3(64 * kChunkWaves),
-                       0, s, tab, F, io, nx, 1, bcx, inv_dx);
+    hipLaunchKernelGGL((advect_adjoint_xchunk_kernel<NZ, S>), dim3((unsigned)gx, (unsigned)nplanes),
+                       dim3(64 * kChunkWaves), 0, s, tab, F, io, nx, 1, bcx, inv_dx);
     return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_advect_adjoint_s(int d, const DevTables* tab, int nplanes, const S* F, const AdvAdjIO& io,
+                                   int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy, hipStream_t s) {
+    switch (io.n) {
+        case 1: return launch_advect_adjoint_n<1, S>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
+        case 2: return launch_advect_adjoint_n<2, S>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
+        case 3: return launch_advect_adjoint_n<3, S>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
+        case 4: return launch_advect_adjoint_n<4, S>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const double* F, const AdvAdjIO& io,
-                                 int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy, hipStream_t s) {
-    switch (io.n) {
-        case 1: return launch_advect_adjoint_n<1>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
-        case 2: return launch_advect_adjoint_n<2>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
-        case 3: return launch_advect_adjoint_n<3>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
-        case 4: return launch_advect_adjoint_n<4>(d, tab, nplanes, F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s);
-        default: return hipErrorInvalidValue;
-    }
+hipError_t launch_advect_adjoint(int d, bool f32, const DevTables* tab, int nplanes, const void* F,
+                                 const AdvAdjIO& io, int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy,
+                                 hipStream_t s) {
+    return f32 ? launch_advect_adjoint_s<float>(d, tab, nplanes, (const float*)F, io, nx, ny, bcx, bcy, inv_dx, inv_dy, s)
+               : launch_advect_adjoint_s<double>(d, tab, nplanes, (const double*)F, io, nx, ny, bcx, bcy, inv_dx,
+                                                 inv_dy, s);
 }
 
 hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, const double* dE, double* dM,

@@ -152,15 +152,16 @@ hipError_t launch_check_reset(int* flag, hipStream_t s);
 hipError_t launch_check(int d, const double* M, long long ms, long long cells, int code, int* flag,
                         hipStream_t s);
 // Adjoint building blocks (adjoint.hip): the stage value F = a src + b E(M)
-// as FP64; dM = (dE/dM)^T dE; out = y + (dM/dF)^T dM (y NULL: zero; y may
-// be out).
+// in the storage type (f32: float, else double); dM = (dE/dM)^T dE; out =
+// y + (dM/dF)^T dM (y NULL: zero; y may be out).
 hipError_t launch_materialise(int d, int qm, bool f32, const DevTables* tab, const void* src, const double* M,
-                              double a, double b, double* out, long long cells, double chi_fac,
+                              double a, double b, void* out, long long cells, double chi_fac,
                               hipStream_t s);
 // Transposed advection: with dA = sum_j c[j] z[j] (the adjoint of the
 // fluxes) and V = V^T dA at every node, writes y1 = e0 V + sum_j e[j] z[j]
-// and, when y2 is not NULL, y2 = f0 V + sum_j f[j] z[j].  The outputs must
-// not alias F or any z[j].
+// and, when y2 is not NULL, y2 = f0 V + sum_j f[j] z[j] (FP64 plane-sets).
+// F is the linearisation point in the storage type (f32: float, else
+// double).  The outputs must not alias F or any z[j].
 struct AdvAdjIO {
     const double* z[4];
     double c[4], e[4], f[4];
@@ -169,8 +170,9 @@ struct AdvAdjIO {
     double* y1;
     double* y2;
 };
-hipError_t launch_advect_adjoint(int d, const DevTables* tab, int nplanes, const double* F, const AdvAdjIO& io,
-                                 int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy, hipStream_t s);
+hipError_t launch_advect_adjoint(int d, bool f32, const DevTables* tab, int nplanes, const void* F,
+                                 const AdvAdjIO& io, int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy,
+                                 hipStream_t s);
 hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, const double* dE, double* dM,
                              long long cells, double chi_fac, hipStream_t s);
 hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, const double* dM, const double* y,

@@ -864,7 +864,7 @@ imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const 
     // of the fluxes dA = sum_j cs_j z_j, then y1 = e0 V + sum_j es_j z_j (the
     // equilibrium adjoint's input) and y2 = f0 V + sum_j fs_j z_j (the moment
     // adjoint's), V = V^T dA
-    auto adv = [&](const double* F, std::initializer_list<const double*> zs, std::initializer_list<double> cs,
+    auto adv = [&](const void* F, std::initializer_list<const double*> zs, std::initializer_list<double> cs,
                    double e0, std::initializer_list<double> es, double f0, std::initializer_list<double> fs,
                    double* y1, double* y2) {
         AdvAdjIO io{};
@@ -879,7 +879,7 @@ imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const 
         io.f0 = f0;
         io.y1 = y1;
         io.y2 = y2;
-        return launch_advect_adjoint(d, c->d_tab, np, F, io, nx, ny, c->cfg.bc_x, c->cfg.bc_y, idx, idy, s);
+        return launch_advect_adjoint(d, f32, c->d_tab, np, F, io, nx, ny, c->cfg.bc_x, c->cfg.bc_y, idx, idy, s);
     };
     auto eqt = [&](const double* M, const double* y) {
         return launch_eq_adjoint(d, qm, c->d_tab, M, y, dM, cells, chi, s);
@@ -971,7 +971,7 @@ imexlb_status imexlb_advect_adjoint(const imexlb_ctx* c, const double* F, const 
     io.c[0] = 1.0;
     io.e0 = 1.0;
     io.y1 = dF;
-    hipError_t e = launch_advect_adjoint(c->cfg.d, c->d_tab, c->nplanes, F, io, c->cfg.nx,
+    hipError_t e = launch_advect_adjoint(c->cfg.d, false, c->d_tab, c->nplanes, F, io, c->cfg.nx,
                                          c->cfg.d == 2 ? c->cfg.ny : 1, c->cfg.bc_x, c->cfg.bc_y, a.inv_dx,
                                          a.inv_dy, c->stream);
     if (e != hipSuccess) return hip_fail(m, e, "advect_adjoint");
