@@ -187,7 +187,9 @@ imexlb_status imexlb_check_state(const imexlb_ctx* ctx);
  * final state with respect to an earlier state or to initial fields.
  *
  * Adjoint variables are FP64 plane-sets lam[v][y][x] (the derivative of the
- * loss with respect to each population), whatever the storage type.  The
+ * loss with respect to each population), whatever the storage type; the
+ * stage adjoints inside a step are held in the storage type (arithmetic
+ * FP64 throughout).  The
  * adjoint step recomputes the stage sources of the step from its input
  * state (Sec. III, Table I) in a caller-owned adjoint workspace and then
  * runs the stages backwards: MP-9 advection transposed (a face that the
@@ -199,8 +201,7 @@ imexlb_status imexlb_check_state(const imexlb_ctx* ctx);
  * ------------------------------------------------------------------------ */
 
 /* Size of, and binding of, the adjoint workspace (256-byte aligned device
- * buffer): three plane-sets of the storage type, four FP64 moment sets and
- * four FP64 plane-sets. */
+ * buffer): seven plane-sets of the storage type and four FP64 moment sets. */
 size_t imexlb_adjoint_workspace_bytes(const imexlb_ctx* ctx);
 imexlb_status imexlb_adjoint_bind(imexlb_ctx* ctx, void* d_adj_workspace);
 

@@ -17,8 +17,10 @@
 //     (Eq. gExpanded; the a_l are Appell polynomials in u with variance T-1);
 //   * the moment Jacobian transposed: dF_v = dM . dM/dF_v (Sec. II,
 //     Eq. Moments_discrete).
-// All adjoint arrays are FP64 plane-sets F[v][cell] and FP64 moment sets
-// M[field][cell] (d + 2 fields: n, u_x, [u_y], T).
+// Adjoint plane-sets F[v][cell] between the kernels are held in the storage
+// type (the adjoint of the following step, lam^{n+1}, in FP64), moment sets
+// M[field][cell] (d + 2 fields: n, u_x, [u_y], T) in FP64; all arithmetic is
+// FP64.
 #include "common.hpp"
 #include "device.hpp"
 
@@ -160,25 +162,35 @@ __device__ __forceinline__ double face_jacobian(const double (&w)[9], int k) {
 // window reads it, the face's Jacobian entry times d(face).
 // NZ = o.n, a compile-time constant so that the loads of all z_j issue
 // together.
-template <int NZ>
+// Element i of adjoint input j: z[0] is FP64, the others are in the storage
+// type S (j is a compile-time constant at every use).
+template <typename S>
+__device__ __forceinline__ double adj_z(const AdvAdjIO& o, int j, size_t i) {
+    return j == 0 ? static_cast<const double*>(o.z[0])[i] : (double)static_cast<const S*>(o.z[j])[i];
+}
+
+template <int NZ, typename S>
 __device__ __forceinline__ double adj_dA(const AdvAdjIO& o, size_t i) {
     double r = 0.0;
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) r = fma(o.c[j], o.z[j][i], r);
+    for (int j = 0; j < NZ; ++j) r = fma(o.c[j], adj_z<S>(o, j, i), r);
     return r;
 }
 
-template <int NZ>
+template <int NZ, typename S>
 __device__ __forceinline__ void adj_store(const AdvAdjIO& o, size_t i, double V) {
     double y1 = o.e0 * V, y2 = o.f0 * V;
 #pragma unroll
     for (int j = 0; j < NZ; ++j) {
-        const double z = o.z[j][i];
+        const double z = adj_z<S>(o, j, i);
         y1 = fma(o.e[j], z, y1);
         y2 = fma(o.f[j], z, y2);
     }
-    __builtin_nontemporal_store(y1, o.y1 + i);
-    if (o.y2) __builtin_nontemporal_store(y2, o.y2 + i);
+    __builtin_nontemporal_store((S)y1, static_cast<S*>(o.y1) + i);
+    if (o.y2) {
+        if (o.y2_f64) __builtin_nontemporal_store(y2, static_cast<double*>(o.y2) + i);
+        else __builtin_nontemporal_store((S)y2, static_cast<S*>(o.y2) + i);
+    }
 }
 
 // Gather form along one line (used for 1D periodic lines shorter than 40
@@ -205,9 +217,9 @@ __device__ double adj_axis_dir(const S* F, const AdvAdjIO& o, size_t base, long 
             int j = (FWD ? tv - 4 : tv - 5) + i;
             double v = 0.0;
             if (bc == 0) {
-                if (j >= 0 && j < n) v = adj_dA<NZ>(o, base + (size_t)j * st);
+                if (j >= 0 && j < n) v = adj_dA<NZ, S>(o, base + (size_t)j * st);
             } else {
-                v = adj_dA<NZ>(o, base + (size_t)bc_map(j, n, 1) * st);
+                v = adj_dA<NZ, S>(o, base + (size_t)bc_map(j, n, 1) * st);
             }
             a10[i] = v;
         }
@@ -240,7 +252,7 @@ __global__ void __launch_bounds__(kAdjBlock) advect_adjoint_gather1d_kernel(cons
     double r = 0.0;
     if (p > 0.0) r = adj_axis_dir<true, NZ, S>(F, o, pl, 1, nx, bc, x, p * inv_dx);
     else if (p < 0.0) r = adj_axis_dir<false, NZ, S>(F, o, pl, 1, nx, bc, x, p * inv_dx);
-    adj_store<NZ>(o, pl + x, r);
+    adj_store<NZ, S>(o, pl + x, r);
 }
 
 // x lines, wave-cooperative (1D): one wavefront per chunk of kChunk nodes of
@@ -285,14 +297,14 @@ __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel
     const double p = tab->plane[v].px;  // one plane per work-group
     const int t = c0 + lane;
     if (p == 0.0) {
-        if (live && lane < kChunk && t < n) adj_store<NZ>(o, base + t, 0.0);
+        if (live && lane < kChunk && t < n) adj_store<NZ, S>(o, base + t, 0.0);
         return;
     }
     const bool fwd = p > 0.0;
     // the chunk's windows, read once into LDS (coalesced)
     auto dat = [&](int j) {
-        if (bc == 1) return adj_dA<NZ>(o, base + (size_t)bc_map(j, n, 1));
-        return (j >= 0 && j < n) ? adj_dA<NZ>(o, base + (size_t)j) : 0.0;
+        if (bc == 1) return adj_dA<NZ, S>(o, base + (size_t)bc_map(j, n, 1));
+        return (j >= 0 && j < n) ? adj_dA<NZ, S>(o, base + (size_t)j) : 0.0;
     };
     if (live) {
         for (int i = lane; i < 72; i += 64) {
@@ -326,7 +338,7 @@ __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel
                     if ((t == 0 && j < 0) || (t == n - 1 && j > n - 1)) val += contrib[kk * 64 + l];
                 }
         }
-        adj_store<NZ>(o, base + (size_t)t, val);
+        adj_store<NZ, S>(o, base + (size_t)t, val);
     }
 }
 
@@ -515,7 +527,7 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
         for (int j = 0; j < kNFL; ++j) sF[fl[j]] = (double)F[pl + fo[j]];
 #pragma unroll
         for (int j = 0; j < kNAL; ++j) {
-            const double v = adj_dA<NZ>(o, pl + ao[j]);
+            const double v = adj_dA<NZ, S>(o, pl + ao[j]);
             sA[al[j]] = (amask >> j) & 1u ? v : 0.0;
         }
         __syncthreads();
@@ -558,119 +570,192 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
         for (int i = tid; i < kTT * kTT; i += kTThreads) {
             const int r = i / kTT, c = i % kTT;
             if (x0 + c < nx && y0 + r < ny)
-                adj_store<NZ>(o, pl + (size_t)(y0 + r) * nx + x0 + c, sF[r * kRP + c] + sA[r * kRP + c]);
+                adj_store<NZ, S>(o, pl + (size_t)(y0 + r) * nx + x0 + c, sF[r * kRP + c] + sA[r * kRP + c]);
         }
         __syncthreads();  // before the next plane overwrites the tiles
     }
 }
 
+// The pointwise adjoint kernels: a work-group of kParts wavefronts covers 64
+// consecutive cells (one per lane), and its wavefronts split the planes
+// between them (rows of one y node each, in plane order), so that a grid of
+// a few hundred thousand cells still keeps several wavefronts per SIMD, each
+// with a row of loads in flight.  (Two parts measured faster than four: each
+// part evaluates the x factors of its sets again.)
+constexpr int kParts = 2;
+
+// Row r of the plane order: set, y node and first plane; a set holds Q_set
+// rows of Q_set planes in 2D and one row of Q_set planes in 1D.
+template <int D>
+__device__ __forceinline__ void plane_row(CTab* tab, int r, int& set, int& ky, int& v) {
+    const int q0 = tab->q[0];
+    if (D == 2) {
+        set = r >= q0 ? 1 : 0;
+        ky = set ? r - q0 : r;
+        v = set ? q0 * q0 + ky * tab->q[1] : ky * q0;
+    } else {
+        set = r;
+        ky = 0;
+        v = r ? q0 : 0;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ int plane_rows(CTab* tab) {
+    return D == 2 ? tab->q[0] + tab->q[1] : 2;
+}
+
 // out = a src + b E(M) (stage value rebuilt from its moments), evaluated in
 // FP64 and stored in the storage type, as the forward's relax on read
 // stores it before the MP-9 sweeps.  The x factors of a set are evaluated
-// once per cell; a row of planes (one y node) is read with all its loads in
+// once per cell and wavefront; a row of planes is read with all its loads in
 // flight.
 template <typename S, int D, int QM>
-__global__ void __launch_bounds__(kAdjBlock) materialise_kernel(const DevTables* __restrict__ tabp,
-                                                                const S* __restrict__ src,
-                                                                const double* __restrict__ M, double a,
-                                                                double b, S* __restrict__ out,
-                                                                long long cells, double chi_fac) {
+__global__ void __launch_bounds__(64 * kParts) materialise_kernel(const DevTables* __restrict__ tabp,
+                                                                     const S* __restrict__ src,
+                                                                     const double* __restrict__ M, double a,
+                                                                     double b, S* __restrict__ out,
+                                                                     long long cells, double chi_fac) {
     CTab* tab = (CTab*)tabp;
-    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long c = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
     if (c >= cells) return;
+    const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const double nn = M[c], u = M[cells + c], w = D == 2 ? M[2 * cells + c] : 0.0;
     const double th = M[(D + 1) * cells + c] - 1.0;
-    int v = 0;
-    for (int set = 0; set < 2; ++set) {
+    const int nrow = plane_rows<D>(tab);
+    const int r0 = part * nrow / kParts, r1 = (part + 1) * nrow / kParts;
+    int cur = -1;
+    double pre = 0.0, gx[QM];
+#pragma unroll
+    for (int kx = 0; kx < QM; ++kx) gx[kx] = 0.0;
+    for (int r = r0; r < r1; ++r) {
+        int set, ky, v;
+        plane_row<D>(tab, r, set, ky, v);
         const int Q = tab->q[set];
-        const double pre = set ? chi_fac * nn * (th + 1.0) : nn;
-        double gx[QM];
+        if (set != cur) {
+            cur = set;
+            pre = set ? chi_fac * nn * (th + 1.0) : nn;
 #pragma unroll
-        for (int kx = 0; kx < QM; ++kx) gx[kx] = kx < Q ? herm_factor(tab->h[set][kx], Q, u, th) : 0.0;
-        for (int ky = 0; ky < (D == 2 ? Q : 1); ++ky) {
-            const double gy = b * (D == 2 ? pre * herm_factor(tab->h[set][ky], Q, w, th) : pre);
-            double sv[QM];
-#pragma unroll
-            for (int kx = 0; kx < QM; ++kx) sv[kx] = kx < Q ? (double)src[(size_t)(v + kx) * cells + c] : 0.0;
-#pragma unroll
-            for (int kx = 0; kx < QM; ++kx)
-                if (kx < Q) out[(size_t)(v + kx) * cells + c] = (S)fma(a, sv[kx], gy * gx[kx]);
-            v += Q;
+            for (int kx = 0; kx < QM; ++kx) gx[kx] = kx < Q ? herm_factor(tab->h[set][kx], Q, u, th) : 0.0;
         }
+        double sv[QM];  // every load issued, none behind a branch (past the row's end: its first plane again)
+#pragma unroll
+        for (int kx = 0; kx < QM; ++kx) sv[kx] = (double)src[(size_t)(v + (kx < Q ? kx : 0)) * cells + c];
+        const double gy = b * (D == 2 ? pre * herm_factor(tab->h[set][ky], Q, w, th) : pre);
+#pragma unroll
+        for (int kx = 0; kx < QM; ++kx)
+            if (kx < Q) out[(size_t)(v + kx) * cells + c] = (S)fma(a, sv[kx], gy * gx[kx]);
     }
 }
 
-// dM = (dE/dM)^T dE per cell for the FP64 plane-set dE.  Moments (n, u, T)
-// of M.  The x factors (and their u and T derivatives) of the QM or fewer
-// nodes of a set are evaluated once per cell and set, then reused by every
-// y group.
-template <int D, int QM>
-__global__ void __launch_bounds__(kAdjBlock) eq_adjoint_kernel(const DevTables* __restrict__ tabp,
-                                                               const double* __restrict__ M,
-                                                               const double* __restrict__ dE,
-                                                               double* __restrict__ dM, long long cells,
-                                                               double chi_fac) {
+// dM = (dE/dM)^T dE per cell for the plane-set dE (type A).  Moments (n, u, T)
+// of M.  Each wavefront sums its rows' terms; the partial sums meet in LDS
+// and are added in wavefront order (deterministic).  The x factors (and
+// their u and T derivatives) of a set are evaluated once per cell and
+// wavefront.
+template <int D, int QM, typename A>
+__global__ void __launch_bounds__(64 * kParts) eq_adjoint_kernel(const DevTables* __restrict__ tabp,
+                                                                    const double* __restrict__ M,
+                                                                    const A* __restrict__ dE,
+                                                                    double* __restrict__ dM, long long cells,
+                                                                    double chi_fac) {
+    constexpr int NP = kParts;
+    __shared__ double red[NP - 1][4][64];
     CTab* tab = (CTab*)tabp;
-    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cells) return;
+    const int lane = threadIdx.x & 63;
+    const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long cl = (long long)blockIdx.x * 64 + lane;
+    const bool live = cl < cells;
+    const long long c = live ? cl : 0;  // lanes past the end work on cell 0 and store nothing
     const double nn = M[c], u = M[cells + c], w = D == 2 ? M[2 * cells + c] : 0.0;
     const double T = M[(D + 1) * cells + c], th = T - 1.0;
     double dn = 0.0, dux = 0.0, duy = 0.0, dT = 0.0;
-    int v = 0;
-    for (int set = 0; set < 2; ++set) {
+    const int nrow = plane_rows<D>(tab);
+    const int r0 = part * nrow / NP, r1 = (part + 1) * nrow / NP;
+    int cur = -1;
+    double pre = 0.0, pre_n = 0.0, pre_T = 0.0;
+    double gx[QM], gxu[QM], gxT[QM];
+#pragma unroll
+    for (int kx = 0; kx < QM; ++kx) {
+        gx[kx] = 0.0;
+        gxu[kx] = 0.0;
+        gxT[kx] = 0.0;
+    }
+    for (int r = r0; r < r1; ++r) {
+        int set, ky, v;
+        plane_row<D>(tab, r, set, ky, v);
         const int Q = tab->q[set];
-        const double pre = set ? chi_fac * nn * T : nn;       // P_phi = n, P_chi = (K+D-d) n T
-        const double pre_n = set ? chi_fac * T : 1.0;
-        const double pre_T = set ? chi_fac * nn : 0.0;
-        double gx[QM], gxu[QM], gxT[QM];
+        double ev[QM];  // the row's loads, all in flight (past the row's end: its first plane again)
 #pragma unroll
-        for (int kx = 0; kx < QM; ++kx) {
-            gx[kx] = 0.0;
-            gxu[kx] = 0.0;
-            gxT[kx] = 0.0;
-            if (kx < Q) herm_factor_d(tab->h[set][kx], Q, u, th, gx[kx], gxu[kx], gxT[kx]);
-        }
-        for (int ky = 0; ky < (D == 2 ? Q : 1); ++ky) {
-            double ev[QM];  // the row's loads, all in flight
-#pragma unroll
-            for (int kx = 0; kx < QM; ++kx) ev[kx] = kx < Q ? dE[(size_t)(v + kx) * cells + c] : 0.0;
-            double gy = 1.0, gyu = 0.0, gyT = 0.0;
-            if (D == 2) herm_factor_d(tab->h[set][ky], Q, w, th, gy, gyu, gyT);
+        for (int kx = 0; kx < QM; ++kx) ev[kx] = (double)dE[(size_t)(v + (kx < Q ? kx : 0)) * cells + c];
+        if (set != cur) {
+            cur = set;
+            pre = set ? chi_fac * nn * T : nn;  // P_phi = n, P_chi = (K+D-d) n T
+            pre_n = set ? chi_fac * T : 1.0;
+            pre_T = set ? chi_fac * nn : 0.0;
 #pragma unroll
             for (int kx = 0; kx < QM; ++kx) {
-                if (kx < Q) {
-                    const double e = ev[kx];
-                    dn = fma(e, pre_n * gx[kx] * gy, dn);
-                    dux = fma(e, pre * gxu[kx] * gy, dux);
-                    if (D == 2) duy = fma(e, pre * gx[kx] * gyu, duy);
-                    dT = fma(e, pre_T * gx[kx] * gy + pre * (gxT[kx] * gy + gx[kx] * gyT), dT);
-                }
+                gx[kx] = 0.0;
+                gxu[kx] = 0.0;
+                gxT[kx] = 0.0;
+                if (kx < Q) herm_factor_d(tab->h[set][kx], Q, u, th, gx[kx], gxu[kx], gxT[kx]);
             }
-            v += Q;
+        }
+        double gy = 1.0, gyu = 0.0, gyT = 0.0;
+        if (D == 2) herm_factor_d(tab->h[set][ky], Q, w, th, gy, gyu, gyT);
+#pragma unroll
+        for (int kx = 0; kx < QM; ++kx) {
+            if (kx < Q) {
+                const double e = ev[kx];
+                dn = fma(e, pre_n * gx[kx] * gy, dn);
+                dux = fma(e, pre * gxu[kx] * gy, dux);
+                if (D == 2) duy = fma(e, pre * gx[kx] * gyu, duy);
+                dT = fma(e, pre_T * gx[kx] * gy + pre * (gxT[kx] * gy + gx[kx] * gyT), dT);
+            }
         }
     }
-    dM[c] = dn;
-    dM[cells + c] = dux;
-    if (D == 2) dM[2 * cells + c] = duy;
-    dM[(D + 1) * cells + c] = dT;
+    if (part > 0) {
+        red[part - 1][0][lane] = dn;
+        red[part - 1][1][lane] = dux;
+        red[part - 1][2][lane] = duy;
+        red[part - 1][3][lane] = dT;
+    }
+    __syncthreads();
+    if (part == 0 && live) {
+#pragma unroll
+        for (int p = 0; p < NP - 1; ++p) {
+            dn += red[p][0][lane];
+            dux += red[p][1][lane];
+            duy += red[p][2][lane];
+            dT += red[p][3][lane];
+        }
+        dM[c] = dn;
+        dM[cells + c] = dux;
+        if (D == 2) dM[2 * cells + c] = duy;
+        dM[(D + 1) * cells + c] = dT;
+    }
 }
 
-// out = y + (dM/dF)^T dM per plane (y may be NULL: zero; it may also be out
-// itself, each element being read before it is written).
+// out = y + (dM/dF)^T dM per plane, y and out of type A (y may be NULL:
+// zero; it may also be out itself, each element being read before it is
+// written).
 // n = sum_phi F, n u = sum_phi p F, (D+K) n T = sum_phi |p|^2 F + sum_chi F - n |u|^2:
 //   dn/dF = [phi], du/dF = [phi] (p - u)/n,
 //   dT/dF = ([phi] |p - u|^2 + [chi]) / ((D+K) n) - [phi] T / n.
-// Planes go in groups of kMomGroup, the group's loads in flight together.
+// Each wavefront takes a contiguous range of planes, in groups of
+// kMomGroup with the group's loads in flight together.
 constexpr int kMomGroup = 8;
 
-template <int D>
-__global__ void __launch_bounds__(kAdjBlock) mom_adjoint_kernel(const DevTables* __restrict__ tabp,
-                                                                const double* __restrict__ M,
-                                                                const double* __restrict__ dM, const double* y,
-                                                                double* out, long long cells, double dk) {
+template <int D, typename A>
+__global__ void __launch_bounds__(64 * kParts) mom_adjoint_kernel(const DevTables* __restrict__ tabp,
+                                                                     const double* __restrict__ M,
+                                                                     const double* __restrict__ dM,
+                                                                     const A* y, A* out, long long cells,
+                                                                     double dk) {
     CTab* tab = (CTab*)tabp;
-    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long c = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
     if (c >= cells) return;
+    const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const double nn = M[c], u = M[cells + c], w = D == 2 ? M[2 * cells + c] : 0.0;
     const double T = M[(D + 1) * cells + c];
     const double gn = dM[c], gu = dM[cells + c], gw = D == 2 ? dM[2 * cells + c] : 0.0;
@@ -680,20 +765,21 @@ __global__ void __launch_bounds__(kAdjBlock) mom_adjoint_kernel(const DevTables*
     // of a chi plane: gT / ((D+K) n)
     const double chi_term = gT * inv_dkn;
     const int np = tab->nplanes;
-    for (int v0 = 0; v0 < np; v0 += kMomGroup) {
+    const int v0 = part * np / kParts, v1 = (part + 1) * np / kParts;
+    for (int vb = v0; vb < v1; vb += kMomGroup) {
         double r[kMomGroup];
 #pragma unroll
-        for (int k = 0; k < kMomGroup; ++k) r[k] = (y && v0 + k < np) ? y[(size_t)(v0 + k) * cells + c] : 0.0;
+        for (int k = 0; k < kMomGroup; ++k) r[k] = y ? (double)y[(size_t)(vb + k < v1 ? vb + k : vb) * cells + c] : 0.0;
 #pragma unroll
         for (int k = 0; k < kMomGroup; ++k) {
-            const int v = v0 + k;
-            if (v < np) {
+            const int v = vb + k;
+            if (v < v1) {
                 double t = chi_term;
                 if (tab->plane[v].set == 0) {
                     const double ex = tab->plane[v].px - u, ey = tab->plane[v].py - w;
                     t = gn + (gu * ex + gw * ey) * inv_n + gT * ((ex * ex + ey * ey) * inv_dkn - T * inv_n);
                 }
-                out[(size_t)v * cells + c] = r[k] + t;
+                out[(size_t)v * cells + c] = (A)(r[k] + t);
             }
         }
     }
@@ -704,9 +790,9 @@ __global__ void __launch_bounds__(kAdjBlock) mom_adjoint_kernel(const DevTables*
 hipError_t launch_materialise(int d, int qm, bool f32, const DevTables* tab, const void* src, const double* M,
                               double a, double b, void* out, long long cells, double chi_fac,
                               hipStream_t s) {
-    const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
+    const int grid = (int)((cells + 63) / 64);
 #define IMEXLB_MAT(S, D, QM) \
-    hipLaunchKernelGGL((materialise_kernel<S, D, QM>), dim3(grid), dim3(kAdjBlock), 0, s, tab, (const S*)src, M, a, b, (S*)out, cells, chi_fac)
+    hipLaunchKernelGGL((materialise_kernel<S, D, QM>), dim3(grid), dim3(64 * kParts), 0, s, tab, (const S*)src, M, a, b, (S*)out, cells, chi_fac)
     if (d == 2) {
         if (qm == 8) { if (f32) IMEXLB_MAT(float, 2, 8); else IMEXLB_MAT(double, 2, 8); }
         else { if (f32) IMEXLB_MAT(float, 2, 16); else IMEXLB_MAT(double, 2, 16); }
@@ -766,24 +852,30 @@ hipError_t launch_advect_adjoint(int d, bool f32, const DevTables* tab, int npla
                                                  inv_dy, s);
 }
 
-hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, const double* dE, double* dM,
-                             long long cells, double chi_fac, hipStream_t s) {
-    const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
+hipError_t launch_eq_adjoint(int d, int qm, bool f32, const DevTables* tab, const double* M, const void* dE,
+                             double* dM, long long cells, double chi_fac, hipStream_t s) {
+    const int grid = (int)((cells + 63) / 64);
+#define IMEXLB_EQT(D, QM, T) \
+    hipLaunchKernelGGL((eq_adjoint_kernel<D, QM, T>), dim3(grid), dim3(64 * kParts), 0, s, tab, M, (const T*)dE, dM, cells, chi_fac)
     if (d == 2) {
-        if (qm == 8) hipLaunchKernelGGL((eq_adjoint_kernel<2, 8>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dE, dM, cells, chi_fac);
-        else hipLaunchKernelGGL((eq_adjoint_kernel<2, 16>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dE, dM, cells, chi_fac);
+        if (qm == 8) { if (f32) IMEXLB_EQT(2, 8, float); else IMEXLB_EQT(2, 8, double); }
+        else { if (f32) IMEXLB_EQT(2, 16, float); else IMEXLB_EQT(2, 16, double); }
     } else {
-        if (qm == 8) hipLaunchKernelGGL((eq_adjoint_kernel<1, 8>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dE, dM, cells, chi_fac);
-        else hipLaunchKernelGGL((eq_adjoint_kernel<1, 16>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dE, dM, cells, chi_fac);
+        if (qm == 8) { if (f32) IMEXLB_EQT(1, 8, float); else IMEXLB_EQT(1, 8, double); }
+        else { if (f32) IMEXLB_EQT(1, 16, float); else IMEXLB_EQT(1, 16, double); }
     }
+#undef IMEXLB_EQT
     return hipGetLastError();
 }
 
-hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, const double* dM, const double* y,
-                              double* out, long long cells, double dk, hipStream_t s) {
-    const int grid = (int)((cells + kAdjBlock - 1) / kAdjBlock);
-    if (d == 2) hipLaunchKernelGGL((mom_adjoint_kernel<2>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dM, y, out, cells, dk);
-    else hipLaunchKernelGGL((mom_adjoint_kernel<1>), dim3(grid), dim3(kAdjBlock), 0, s, tab, M, dM, y, out, cells, dk);
+hipError_t launch_mom_adjoint(int d, bool f32, const DevTables* tab, const double* M, const double* dM,
+                              const void* y, void* out, long long cells, double dk, hipStream_t s) {
+    const int grid = (int)((cells + 63) / 64);
+#define IMEXLB_MOMT(D, T) \
+    hipLaunchKernelGGL((mom_adjoint_kernel<D, T>), dim3(grid), dim3(64 * kParts), 0, s, tab, M, dM, (const T*)y, (T*)out, cells, dk)
+    if (d == 2) { if (f32) IMEXLB_MOMT(2, float); else IMEXLB_MOMT(2, double); }
+    else { if (f32) IMEXLB_MOMT(1, float); else IMEXLB_MOMT(1, double); }
+#undef IMEXLB_MOMT
     return hipGetLastError();
 }
 

@@ -152,31 +152,34 @@ hipError_t launch_check_reset(int* flag, hipStream_t s);
 hipError_t launch_check(int d, const double* M, long long ms, long long cells, int code, int* flag,
                         hipStream_t s);
 // Adjoint building blocks (adjoint.hip): the stage value F = a src + b E(M)
-// in the storage type (f32: float, else double); dM = (dE/dM)^T dE; out =
-// y + (dM/dF)^T dM (y NULL: zero; y may be out).
+// in the storage type (f32: float, else double); dM = (dE/dM)^T dE with dE
+// in the storage type; out = y + (dM/dF)^T dM with y and out in the storage
+// type (y NULL: zero; y may be out).  Arithmetic is FP64 throughout.
 hipError_t launch_materialise(int d, int qm, bool f32, const DevTables* tab, const void* src, const double* M,
                               double a, double b, void* out, long long cells, double chi_fac,
                               hipStream_t s);
 // Transposed advection: with dA = sum_j c[j] z[j] (the adjoint of the
 // fluxes) and V = V^T dA at every node, writes y1 = e0 V + sum_j e[j] z[j]
-// and, when y2 is not NULL, y2 = f0 V + sum_j f[j] z[j] (FP64 plane-sets).
-// F is the linearisation point in the storage type (f32: float, else
-// double).  The outputs must not alias F or any z[j].
+// and, when y2 is not NULL, y2 = f0 V + sum_j f[j] z[j].  z[0] is an FP64
+// plane-set; F (the linearisation point), z[1..], y1 and, unless y2_f64 is
+// set, y2 are plane-sets of the storage type (f32: float, else double).
+// The outputs must not alias F or any z[j].
 struct AdvAdjIO {
-    const double* z[4];
+    const void* z[4];
     double c[4], e[4], f[4];
     double e0, f0;
     int n;
-    double* y1;
-    double* y2;
+    int y2_f64;
+    void* y1;
+    void* y2;
 };
 hipError_t launch_advect_adjoint(int d, bool f32, const DevTables* tab, int nplanes, const void* F,
                                  const AdvAdjIO& io, int nx, int ny, int bcx, int bcy, double inv_dx, double inv_dy,
                                  hipStream_t s);
-hipError_t launch_eq_adjoint(int d, int qm, const DevTables* tab, const double* M, const double* dE, double* dM,
-                             long long cells, double chi_fac, hipStream_t s);
-hipError_t launch_mom_adjoint(int d, const DevTables* tab, const double* M, const double* dM, const double* y,
-                              double* out, long long cells, double dk, hipStream_t s);
+hipError_t launch_eq_adjoint(int d, int qm, bool f32, const DevTables* tab, const double* M, const void* dE,
+                             double* dM, long long cells, double chi_fac, hipStream_t s);
+hipError_t launch_mom_adjoint(int d, bool f32, const DevTables* tab, const double* M, const double* dM,
+                              const void* y, void* out, long long cells, double dk, hipStream_t s);
 
 // Batched 1D passes: one launch covers every tile of every tube.  targs[i]
 // holds tube i's arguments for this pass; tiles[j] = (tube, first cell).

@@ -796,29 +796,27 @@ imexlb_status imexlb_check_state(const imexlb_ctx* c) {
 // ---------------------------------------------------------------------------
 namespace {
 
-// Adjoint workspace: F scratch | G3 | G4 (storage type) | M^n | M3 | M4 | dM
-// (FP64 moment sets) | X1 | X2 | X3 | X4 (FP64 plane-sets).
+// Adjoint workspace: F scratch | G3 | G4 | X1 | X2 | X3 | X4 (plane-sets of
+// the storage type: the recomputed stage sources, then the stage adjoints
+// between the kernels of the reverse sweep) | M^n | M3 | M4 | dM (FP64
+// moment sets).
 struct AdjLayout {
-    size_t ps, ms, pd;  // bytes: storage plane-set, FP64 moment set, FP64 plane-set
-    size_t total() const { return 3 * ps + 4 * ms + 4 * pd; }
+    size_t ps, ms;  // bytes: storage plane-set, FP64 moment set
+    size_t total() const { return 7 * ps + 4 * ms; }
 };
 
 AdjLayout adj_layout(const imexlb_ctx* c) {
     AdjLayout L;
     L.ps = align256((size_t)c->nplanes * c->cells * c->elem);
     L.ms = align256((size_t)c->nf * c->cells * sizeof(double));
-    L.pd = align256((size_t)c->nplanes * c->cells * sizeof(double));
     return L;
 }
 
 void* adj_s(const imexlb_ctx* c, int i) { return (char*)c->d_adj + (size_t)i * adj_layout(c).ps; }
+void* adj_x(const imexlb_ctx* c, int i) { return adj_s(c, 3 + i); }
 double* adj_m(const imexlb_ctx* c, int i) {
     const AdjLayout L = adj_layout(c);
-    return (double*)((char*)c->d_adj + 3 * L.ps + (size_t)i * L.ms);
-}
-double* adj_x(const imexlb_ctx* c, int i) {
-    const AdjLayout L = adj_layout(c);
-    return (double*)((char*)c->d_adj + 3 * L.ps + 4 * L.ms + (size_t)i * L.pd);
+    return (double*)((char*)c->d_adj + 7 * L.ps + (size_t)i * L.ms);
 }
 
 }  // namespace
@@ -849,7 +847,7 @@ imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const 
     const double chi = (double)(c->cfg.K + kDTotal - d), dk = (double)(kDTotal + c->cfg.K);
     hipStream_t s = c->stream;
     double* dM = adj_m(c, 3);
-    double *X1 = adj_x(c, 0), *X2 = adj_x(c, 1), *X3 = adj_x(c, 2), *X4 = adj_x(c, 3);
+    void *X1 = adj_x(c, 0), *X2 = adj_x(c, 1), *X3 = adj_x(c, 2), *X4 = adj_x(c, 3);
     const StageArgs a = base_args(c);
     hipError_t e = hipSuccess;
     // coefficients (w = dt/tau, cc = alpha w)
@@ -863,12 +861,15 @@ imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const 
     // V^T with the linear combinations its two consumers read: the adjoint
     // of the fluxes dA = sum_j cs_j z_j, then y1 = e0 V + sum_j es_j z_j (the
     // equilibrium adjoint's input) and y2 = f0 V + sum_j fs_j z_j (the moment
-    // adjoint's), V = V^T dA
-    auto adv = [&](const void* F, std::initializer_list<const double*> zs, std::initializer_list<double> cs,
+    // adjoint's), V = V^T dA.  zs[0] is lam^{n+1} (FP64); the other stage
+    // adjoints, y1 and y2 are in the storage type, except a y2 that is lam^n
+    // itself (y2_f64).
+    auto adv = [&](const void* F, std::initializer_list<const void*> zs, std::initializer_list<double> cs,
                    double e0, std::initializer_list<double> es, double f0, std::initializer_list<double> fs,
-                   double* y1, double* y2) {
+                   void* y1, void* y2, bool y2_f64) {
         AdvAdjIO io{};
         io.n = (int)zs.size();
+        io.y2_f64 = y2_f64 ? 1 : 0;
         for (int j = 0; j < io.n; ++j) {
             io.z[j] = zs.begin()[j];
             io.c[j] = cs.begin()[j];
@@ -881,27 +882,29 @@ imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const 
         io.y2 = y2;
         return launch_advect_adjoint(d, f32, c->d_tab, np, F, io, nx, ny, c->cfg.bc_x, c->cfg.bc_y, idx, idy, s);
     };
-    auto eqt = [&](const double* M, const double* y) {
-        return launch_eq_adjoint(d, qm, c->d_tab, M, y, dM, cells, chi, s);
+    auto eqt = [&](const double* M, const void* y) {
+        return launch_eq_adjoint(d, qm, f32, c->d_tab, M, y, dM, cells, chi, s);
     };
-    auto momt = [&](const double* M, const double* y, double* out) {
-        return launch_mom_adjoint(d, c->d_tab, M, dM, y, out, cells, dk, s);
+    // y and out in the storage type, or both FP64 (f64)
+    auto momt = [&](const double* M, const void* y, void* out, bool f64) {
+        return launch_mom_adjoint(d, f32 && !f64, c->d_tab, M, dM, y, out, cells, dk, s);
     };
     const double* L = lam1;
     // stage 4: F4 = a1 S4 + c a1 E4, dA4 = -(2/3) dt L, d(dF4) = -(2/3) L;
     // dE4 = c a1 V4 + (2/3) w a1 L, dS4 (before the moment term) = a1 V4 - (2/3) w a1 L
     if (e == hipSuccess) e = launch_materialise(d, qm, f32, c->d_tab, G4, M4, a1, cc * a1, X1, cells, chi, s);
     if (e == hipSuccess)
-        e = adv(X1, {L}, {-(2.0 / 3.0) * dt}, cc * a1, {(2.0 / 3.0) * w * a1}, a1, {-(2.0 / 3.0) * w * a1}, X2, X4);
+        e = adv(X1, {L}, {-(2.0 / 3.0) * dt}, cc * a1, {(2.0 / 3.0) * w * a1}, a1, {-(2.0 / 3.0) * w * a1}, X2, X4,
+                false);
     if (e == hipSuccess) e = eqt(M4, X2);
-    if (e == hipSuccess) e = momt(M4, X4, X3);  // X3 = dS4
+    if (e == hipSuccess) e = momt(M4, X4, X3, false);  // X3 = dS4
     // stage 3: dA3 = -(1/6) dt L - dt/4 dS4, d(dF3) = -(1/6) L - kappa dS4
     if (e == hipSuccess) e = launch_materialise(d, qm, f32, c->d_tab, G3, M3, a1, cc * a1, X1, cells, chi, s);
     if (e == hipSuccess)
         e = adv(X1, {L, X3}, {-dt / 6.0, -0.25 * dt}, cc * a1, {w * a1 / 6.0, ka * w * a1}, a1,
-                {-w * a1 / 6.0, -ka * w * a1}, X2, X4);
+                {-w * a1 / 6.0, -ka * w * a1}, X2, X4, false);
     if (e == hipSuccess) e = eqt(M3, X2);
-    if (e == hipSuccess) e = momt(M3, X4, X1);  // X1 = dS3
+    if (e == hipSuccess) e = momt(M3, X4, X1, false);  // X1 = dS3
     // stages 2 and 1: F2 = a2 F^n + b2 E^n, dA2 = -(1/6) dt L - dt/4 dS4 - dt dS3,
     // d(dF1) = -beta dS4, d(dF2) = -(1/6) L - eta dS4 - (1 - alpha) dS3; the
     // moment adjoint's input goes straight to lam0 and is completed in place
@@ -909,9 +912,10 @@ imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const 
     if (e == hipSuccess)
         e = adv(X2, {L, X3, X1}, {-dt / 6.0, -0.25 * dt, -dt}, b2,
                 {w * a2 / 6.0, w * a1 * be + w * a2 * et, w * a2 * (1.0 - kAlpha)}, a2,
-                {1.0 - w * a2 / 6.0, 1.0 - w * a1 * be - w * a2 * et, 1.0 - w * a2 * (1.0 - kAlpha)}, X4, lam0);
+                {1.0 - w * a2 / 6.0, 1.0 - w * a1 * be - w * a2 * et, 1.0 - w * a2 * (1.0 - kAlpha)}, X4, lam0,
+                true);
     if (e == hipSuccess) e = eqt(Mn, X4);
-    if (e == hipSuccess) e = momt(Mn, lam0, lam0);
+    if (e == hipSuccess) e = momt(Mn, lam0, lam0, true);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     return IMEXLB_OK;
 }
@@ -995,7 +999,7 @@ imexlb_status imexlb_moments_adjoint(imexlb_ctx* c, const void* F, const double*
     for (int f = 0; f < c->nf && e == hipSuccess; ++f)
         e = hipMemcpyAsync(dM + (size_t)f * cells, src[f], fb, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess)
-        e = launch_mom_adjoint(d, c->d_tab, M, dM, nullptr, lam, cells, (double)(kDTotal + c->cfg.K), s);
+        e = launch_mom_adjoint(d, false, c->d_tab, M, dM, nullptr, lam, cells, (double)(kDTotal + c->cfg.K), s);
     if (e != hipSuccess) return hip_fail(c, e, "moments_adjoint");
     return IMEXLB_OK;
 }
@@ -1017,7 +1021,8 @@ imexlb_status imexlb_equilibrium_adjoint(imexlb_ctx* c, const double* n, const d
     for (int f = 0; f < c->nf && e == hipSuccess; ++f)
         e = hipMemcpyAsync(M + (size_t)f * cells, src[f], fb, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess)
-        e = launch_eq_adjoint(d, base_args(c).qm, c->d_tab, M, lam, dM, cells, (double)(c->cfg.K + kDTotal - d), s);
+        e = launch_eq_adjoint(d, base_args(c).qm, false, c->d_tab, M, lam, dM, cells,
+                              (double)(c->cfg.K + kDTotal - d), s);
     double* dst[4] = {dn, dux, d == 2 ? duy : dT, dT};
     for (int f = 0; f < c->nf && e == hipSuccess; ++f)
         e = hipMemcpyAsync(dst[f], dM + (size_t)f * cells, fb, hipMemcpyDeviceToDevice, s);
