@@ -712,7 +712,7 @@ def run_adjoint(args, emit=True):
         "metric": "velocity-node updates/s per IMEX step, forward + adjoint (gradient)",
         "value": vn / t_grad, "unit": "VN/s", "n_gpus": 1, "steps": steps, "warmup": 1,
         "ms_per_step": 1e3 * t_grad / steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 storage, f64 moments and adjoint", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32 storage (state and stage adjoints), f64 moments, lambda and arithmetic", "data": "synthetic",
         "config": {"workload": f"2D periodic {N}x{N}, 8x8 velocities per f and g, {steps} steps, "
                                f"checkpoint every {every}; loss 1/2 sum (n - n*)^2, gradient "
                                "w.r.t. the initial density (u = 0, P = 1)",
