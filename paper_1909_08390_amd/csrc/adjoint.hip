@@ -58,18 +58,20 @@ __device__ __forceinline__ void herm_factor_d(CDp h, int Q, double u, double th,
 // the two curvatures a, b in it: 4a - b -> (4, -1), 4b - a -> (-1, 4),
 // a -> (1, 0), b -> (0, 1), 0 -> (0, 0).  The smallest / largest argument is
 // the first one on ties, the order the forward's nested min / max resolves
-// them.
-__device__ __forceinline__ void minmod4_weights(double a, double b, double& al, double& be) {
-    const double x0 = fma(4.0, a, -b), x1 = fma(4.0, b, -a);
+// them.  The comparisons run in the precision R of the forward's sweep.
+template <typename R>
+__device__ __forceinline__ void minmod4_weights(R a, R b, double& al, double& be) {
+    const R x0 = fma(R(4), a, -b), x1 = fma(R(4), b, -a);
     // argmin and argmax over (x0, x1, a, b), first on ties
-    double vmin = x0, vmax = x0, amin = 4.0, bmin = -1.0, amax = 4.0, bmax = -1.0;
+    R vmin = x0, vmax = x0;
+    double amin = 4.0, bmin = -1.0, amax = 4.0, bmax = -1.0;
     if (x1 < vmin) { vmin = x1; amin = -1.0; bmin = 4.0; }
     if (a < vmin) { vmin = a; amin = 1.0; bmin = 0.0; }
     if (b < vmin) { vmin = b; amin = 0.0; bmin = 1.0; }
     if (x1 > vmax) { vmax = x1; amax = -1.0; bmax = 4.0; }
     if (a > vmax) { vmax = a; amax = 1.0; bmax = 0.0; }
     if (b > vmax) { vmax = b; amax = 0.0; bmax = 1.0; }
-    const bool pos = vmin > 0.0, neg = vmax < 0.0;
+    const bool pos = vmin > R(0), neg = vmax < R(0);
     al = pos ? amin : (neg ? amax : 0.0);
     be = pos ? bmin : (neg ? bmax : 0.0);
 }
@@ -87,29 +89,34 @@ __device__ __forceinline__ void minmod4_weights(double a, double b, double& al, 
 //   F_s: e4;  F_{s+1}: e5;  F^UL = 5 F_s - 4 F_{s-1}: 5 e4 - 4 e3;
 //   F^MD = (F_s + F_{s+1})/2 - d^M4_{s+1/2}/2;
 //   F^LC = 3/2 F_s - 1/2 F_{s-1} + 4/3 d^M4_{s-1/2}.
-// Returns true when the row is a clipped one.
-__device__ __forceinline__ bool face_jacobian_row(const double (&w)[9], double (&J)[9]) {
+// The decisions are taken in the precision R of the forward's sweep (the
+// storage type), with the forward's operations, so that they are the
+// forward's own; the row's weights are exact in FP64.  Returns true when
+// the row is a clipped one.
+template <typename R>
+__device__ __forceinline__ bool face_jacobian_row(const R (&w)[9], double (&J)[9]) {
     constexpr double W[9] = {4.0 / 2520.0,    -41.0 / 2520.0, 199.0 / 2520.0, -641.0 / 2520.0, 1879.0 / 2520.0,
                              1375.0 / 2520.0, -305.0 / 2520.0, 55.0 / 2520.0, -5.0 / 2520.0};
-    double dd[8];
+    R dd[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) dd[j] = w[j + 1] - w[j];
-    double t, q;
-    const double fl = mp9_face_linear<double>(dd, w[4], t, q);
+    R t, q;
+    const R fl = mp9_face_linear<R>(dd, w[4], t, q);
 #pragma unroll
     for (int k = 0; k < 9; ++k) J[k] = W[k];
-    if (!(q > 0.0)) return false;
-    const double f = w[4], g = w[5], ul = f + t;
-    const double cm = dd[3] - dd[2], c0 = dd[4] - dd[3], cp = dd[5] - dd[4];
+    if (!(q > R(0))) return false;
+    const R f = w[4], g = w[5], ul = f + t;
+    const R cm = dd[3] - dd[2], c0 = dd[4] - dd[3], cp = dd[5] - dd[4];
     double am, bm, a0, b0;
     minmod4_weights(cm, c0, am, bm);  // d^M4 at s - 1/2 = am C_{s-1} + bm C_s
     minmod4_weights(c0, cp, a0, b0);  // d^M4 at s + 1/2 = a0 C_s + b0 C_{s+1}
-    const double vm = am * cm + bm * c0, v0 = a0 * c0 + b0 * cp;
-    const double lc = fma(4.0 / 3.0, vm, fma(0.5, dd[3], f));
-    const double md = fma(0.5, dd[4] - v0, f);
+    // the selected M4 arguments (exact: the weights are 0, +-1 or 4)
+    const R vm = fma(R(am), cm, R(bm) * c0), v0 = fma(R(a0), c0, R(b0) * cp);
+    const R lc = fma(R(4.0 / 3.0), vm, fma(R(0.5), dd[3], f));
+    const R md = fma(R(0.5), dd[4] - v0, f);
     // candidates 0 F_s, 1 F_{s+1}, 2 MD, 3 UL, 4 LC: F^min = max(min(0, 1, 2),
     // min(0, 3, 4)), F^max = min(max(0, 1, 2), max(0, 3, 4))
-    double va = f, vb = f, vc = f, ve = f;
+    R va = f, vb = f, vc = f, ve = f;
     int ia = 0, ib = 0, ic = 0, ie = 0;
     if (g < va) { va = g; ia = 1; }
     if (md < va) { va = md; ia = 2; }
@@ -119,7 +126,7 @@ __device__ __forceinline__ bool face_jacobian_row(const double (&w)[9], double (
     if (md > vc) { vc = md; ic = 2; }
     if (ul > ve) { ve = ul; ie = 3; }
     if (lc > ve) { ve = lc; ie = 4; }
-    const double lo = vb > va ? vb : va, hi = ve < vc ? ve : vc;
+    const R lo = vb > va ? vb : va, hi = ve < vc ? ve : vc;
     const int ilo = vb > va ? ib : ia, ihi = ve < vc ? ie : ic;
     int sel;
     if (fl < lo) sel = ilo;
@@ -143,7 +150,8 @@ __device__ __forceinline__ bool face_jacobian_row(const double (&w)[9], double (
 }
 
 // One entry d(face)/d(w[k]) of the row above.
-__device__ __forceinline__ double face_jacobian(const double (&w)[9], int k) {
+template <typename R>
+__device__ __forceinline__ double face_jacobian(const R (&w)[9], int k) {
     double J[9];
     face_jacobian_row(w, J);
     double r = 0.0;
@@ -177,6 +185,34 @@ __device__ __forceinline__ double adj_dA(const AdvAdjIO& o, size_t i) {
     return r;
 }
 
+// dA at element i, and the combinations sum_j e[j] z[j], sum_j f[j] z[j]
+// of the same loads.
+template <int NZ, typename S>
+__device__ __forceinline__ double adj_dA_ef(const AdvAdjIO& o, size_t i, double& ze, double& zf) {
+    double r = 0.0;
+    ze = 0.0;
+    zf = 0.0;
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+        const double z = adj_z<S>(o, j, i);
+        r = fma(o.c[j], z, r);
+        ze = fma(o.e[j], z, ze);
+        zf = fma(o.f[j], z, zf);
+    }
+    return r;
+}
+
+// y1 = e0 V + ze, y2 = f0 V + zf from the combinations formed at load time.
+template <typename S>
+__device__ __forceinline__ void adj_store_ef(const AdvAdjIO& o, size_t i, double V, double ze, double zf) {
+    __builtin_nontemporal_store((S)fma(o.e0, V, ze), static_cast<S*>(o.y1) + i);
+    if (o.y2) {
+        const double y2 = fma(o.f0, V, zf);
+        if (o.y2_f64) __builtin_nontemporal_store(y2, static_cast<double*>(o.y2) + i);
+        else __builtin_nontemporal_store((S)y2, static_cast<S*>(o.y2) + i);
+    }
+}
+
 template <int NZ, typename S>
 __device__ __forceinline__ void adj_store(const AdvAdjIO& o, size_t i, double V) {
     double y1 = o.e0 * V, y2 = o.f0 * V;
@@ -208,9 +244,9 @@ __device__ double adj_axis_dir(const S* F, const AdvAdjIO& o, size_t base, long 
     }
     double acc = 0.0;
     for (int tv = vlo; tv <= vhi; ++tv) {
-        double w17[17];  // nodes tv-8 .. tv+8
+        S w17[17];  // nodes tv-8 .. tv+8
 #pragma unroll
-        for (int i = 0; i < 17; ++i) w17[i] = (double)F[base + (size_t)bc_map(tv - 8 + i, n, bc) * st];
+        for (int i = 0; i < 17; ++i) w17[i] = F[base + (size_t)bc_map(tv - 8 + i, n, bc) * st];
         double a10[10];  // dA at faces' nodes: FWD s = tv-4 .. tv+5, else s = tv-5 .. tv+4
 #pragma unroll
         for (int i = 0; i < 10; ++i) {
@@ -227,7 +263,7 @@ __device__ double adj_axis_dir(const S* F, const AdvAdjIO& o, size_t base, long 
         for (int k = 0; k < 9; ++k) {
             const int s = FWD ? tv + 4 - k : tv - 5 + k;  // face between s and s+1
             if (bc == 0 && (s < -1 || s > n - 1)) continue;
-            double fw[9];
+            S fw[9];
 #pragma unroll
             for (int kk = 0; kk < 9; ++kk) fw[kk] = w17[FWD ? 8 - k + kk : 8 + k - kk];
             const int ia = FWD ? 8 - k : k;  // a10 index of s
@@ -280,13 +316,14 @@ __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel
     // per wavefront: F at nodes c0-8 .. c0+63, dA at c0-5 .. c0+66, and the
     // 9 x 64 weighted Jacobian entries of its faces
     __shared__ double contrib_all[kChunkWaves][9 * 64];
-    __shared__ double sF_all[kChunkWaves][72], sA_all[kChunkWaves][72];
+    __shared__ S sF_all[kChunkWaves][72];
+    __shared__ double sA_all[kChunkWaves][72];
     CTab* tab = (CTab*)tabp;
     const long long cells = (long long)nx * ny;
     const int v = blockIdx.y;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, n = nx;
     double* contrib = contrib_all[wave];
-    double* sF = sF_all[wave];
+    S* sF = sF_all[wave];
     double* sA = sA_all[wave];
     const int nch = (nx + kChunk - 1) / kChunk;
     const long long chunk = (long long)blockIdx.x * kChunkWaves + wave;
@@ -308,7 +345,7 @@ __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel
     };
     if (live) {
         for (int i = lane; i < 72; i += 64) {
-            sF[i] = (double)F[base + bc_map(c0 - 8 + i, n, bc)];
+            sF[i] = F[base + bc_map(c0 - 8 + i, n, bc)];
             sA[i] = dat(c0 - 5 + i);
         }
     }
@@ -316,7 +353,7 @@ __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel
     // face s = c0 - 4 + lane (flow to +x) or c0 - 5 + lane: window nodes
     // s - 4 + kk = c0 - 8 + lane + kk, or s + 5 - kk = c0 + lane - kk
     if (live) {
-        double w[9];
+        S w[9];
 #pragma unroll
         for (int kk = 0; kk < 9; ++kk) w[kk] = sF[fwd ? lane + kk : lane + 8 - kk];
         const int ia = lane + (fwd ? 1 : 0);  // sA index of node s
@@ -343,13 +380,13 @@ __global__ void __launch_bounds__(64 * kChunkWaves) advect_adjoint_xchunk_kernel
 }
 
 // 2D, both axes in one pass over tiles of kTT x kTT nodes, one work-group of
-// two wavefronts per tile and kTPB planes.  Per plane the tile's F with an
+// four wavefronts per tile and kTPB planes.  Per plane the tile's F with an
 // 8-node cross halo (the windows of every face that reads a tile node) and
 // dA with a 5-node cross halo (the nodes of those faces) are staged in LDS.
-// Wavefront 0 streams the x lines, wavefront 1 the y lines: each lane owns
-// kTS nodes of a row (column) and evaluates the kTS + 8 faces that read them,
+// Wavefronts 0-1 take the x lines, 2-3 the y lines: each lane owns kTS
+// nodes of a row (column) and evaluates the kTS + 8 faces that read them,
 // each with its whole Jacobian row, accumulating by position in registers
-// (1.5 face evaluations per node and axis).  Positions left of node 0 and
+// (two face evaluations per node and axis).  Positions left of node 0 and
 // right of node n - 1 of an outflow line are its ghost nodes and fold into
 // those end nodes; positions outside the lane's own nodes are otherwise
 // counted by the lane that owns them.  Both axes' sums meet in LDS and every
@@ -362,14 +399,16 @@ constexpr int kTF = kTS + 8;             // faces per lane
 constexpr int kFE = kTT + 16, kFP = kFE + 1;  // F tile (8-node halo), pitch
 constexpr int kAE = kTT + 10, kAP = kAE + 1;  // dA tile (5-node halo), pitch
 constexpr int kRP = kTT + 1;                  // pitch of the per-axis results (reusing the F and dA tiles)
+constexpr int kZP = kTT;                      // pitch of the own nodes' input combinations (FP32 storage)
 constexpr int kTThreads = 256;             // half of them on x lines, half on y lines
-constexpr int kCorrPitch = kTS + 1;        // per-thread LDS row of corrections (odd pitch)
+constexpr int kCorrStride = kTThreads;     // per-thread LDS column of corrections (entry j at j * kCorrStride)
 constexpr int kFLoads = kTT * kFE + 16 * kTT, kALoads = kTT * kAE + 10 * kTT;  // cross sizes
 constexpr int kNFL = (kFLoads + kTThreads - 1) / kTThreads;  // F loads per thread
 constexpr int kNAL = (kALoads + kTThreads - 1) / kTThreads;  // dA loads per thread
 constexpr int kTPB = 8;                                    // planes per work-group
 static_assert(kTT % kTS == 0 && (kTT / kTS) * kTT * 2 == kTThreads, "lanes per line");
-static_assert(kTT * kRP <= kAE * kAP, "result tiles");
+static_assert(kTT * kRP <= kAE * kAP && kTT * kRP * 2 <= kFE * kFP, "result tiles");
+static_assert(kAE * kAP < 4096 && kTT * kZP < (1 << 19), "packed LDS slots");
 
 // The kTF faces of one lane: position q (0 .. kTS + 15) stands for node
 // t0 - 8 + q, its F at f[q FS]; face i has node s = t0 - 4 + i (FWD) or
@@ -380,10 +419,10 @@ static_assert(kTT * kRP <= kAE * kAP, "result tiles");
 // takes the forward's monotonicity test; then the lane walks its faces that
 // failed it (a wavefront takes as many turns as its busiest lane, not one
 // per face position) and trades their linear weights for their clipped
-// rows, accumulated in face order in corr[] (the lane's LDS row: the
+// rows, accumulated in face order in corr[] (the lane's LDS column: the
 // positions of those entries vary from face to face).
-template <bool FWD, int FS, int AS>
-__device__ __forceinline__ void seg_faces(const double* f, const double* a, double pinv, double* corr,
+template <bool FWD, int FS, int AS, typename FT>
+__device__ __forceinline__ void seg_faces(const FT* f, const double* a, double pinv, double* corr,
                                           double (&own)[kTS], double& gl, double& gr) {
     // 2520 times the weights of F^L: small integers, exact as instruction
     // literals
@@ -395,13 +434,14 @@ __device__ __forceinline__ void seg_faces(const double* f, const double* a, doub
     unsigned mask = 0u;
 #pragma unroll
     for (int i = 0; i < kTF; ++i) {
-        double dd[8];
+        // the forward's monotonicity test, in its precision FT
+        FT dd[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             dd[k] = FWD ? f[(i + k + 1) * FS] - f[(i + k) * FS] : f[(i + 7 - k) * FS] - f[(i + 8 - k) * FS];
-        double t, q;
-        (void)mp9_face_linear<double>(dd, f[(i + 4) * FS], t, q);
-        mask |= (q > 0.0 ? 1u : 0u) << i;
+        FT t, q;
+        (void)mp9_face_linear<FT>(dd, f[(i + 4) * FS], t, q);
+        mask |= (q > FT(0) ? 1u : 0u) << i;
         const double dl = pinv * (a[i * AS] - a[(i + 1) * AS]) * (1.0 / 2520.0);
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -413,10 +453,10 @@ __device__ __forceinline__ void seg_faces(const double* f, const double* a, doub
     }
     if (mask) {
 #pragma unroll
-        for (int j = 0; j < kTS; ++j) corr[j] = 0.0;
+        for (int j = 0; j < kTS; ++j) corr[j * kCorrStride] = 0.0;
         for (unsigned m = mask; m; m &= m - 1u) {
             const int i = __builtin_ctz(m);
-            double w[9];
+            FT w[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) w[k] = f[(FWD ? i + k : i + 8 - k) * FS];
             double J[9];
@@ -429,12 +469,12 @@ __device__ __forceinline__ void seg_faces(const double* f, const double* a, doub
                     const double v = fma(J[k], d, -C[k] * dl);
                     if (p < 8) gl += v;
                     else if (p >= 8 + kTS) gr += v;
-                    else corr[p - 8] += v;
+                    else corr[(p - 8) * kCorrStride] += v;
                 }
             }
         }
 #pragma unroll
-        for (int j = 0; j < kTS; ++j) own[j] += corr[j];
+        for (int j = 0; j < kTS; ++j) own[j] += corr[j * kCorrStride];
     }
 }
 
@@ -454,15 +494,32 @@ __device__ __forceinline__ void seg_fold(double (&own)[kTS], double gl, double g
     }
 }
 
-template <int NZ, typename S>
+template <int NZ, typename S, bool ZL>
 __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const DevTables* __restrict__ tabp,
                                                                         const S* __restrict__ F, AdvAdjIO o,
                                                                         int nx, int ny, int bcx, int bcy,
                                                                         double inv_dx, double inv_dy, int ntx,
                                                                         int nplanes) {
-    __shared__ double sF[kFE * kFP];  // then the x results [row][col]
+    // ZL (FP32 storage): the combinations sum e_j z_j and sum f_j z_j of the
+    // tile's own nodes are formed as the dA halo loads arrive and kept in
+    // LDS, so the closing stores need no second round of loads (with FP64
+    // storage the LDS would not hold them at three work-groups per compute
+    // unit, and the closing stores load the z_j again).  F is staged in its
+    // storage type.
+    static_assert(!ZL || sizeof(S) == 4, "combinations in LDS with FP32 storage only");
+    constexpr bool kZL = ZL;
+    __shared__ double sFbuf[(kFE * kFP * sizeof(S) + 7) / 8];  // F, then the x results [row][col] (FP64)
     __shared__ double sA[kAE * kAP];  // then the y results [row][col]
-    __shared__ double sCorr[kTThreads * kCorrPitch];  // per thread: clipped-face corrections
+    __shared__ double sCorr[kTS * kCorrStride];  // per thread: clipped-face corrections
+    // e.z (FP32, as y1 is stored) and f.z (FP64: y2 may be lam^n) at the own
+    // nodes [row][col], then one dummy entry per lane for the loads of other
+    // nodes (unconditional stores: a store behind a branch would hold the
+    // next loads back)
+    constexpr int kZN = kTT * kZP + 64;
+    __shared__ float sZe[kZL ? kZN : 1];
+    __shared__ double sZf[kZL ? kZN : 1];
+    S* const sF = reinterpret_cast<S*>(sFbuf);
+    double* const sX = sFbuf;
     CTab* tab = (CTab*)tabp;
     const long long cells = (long long)nx * ny;
     const int tid = threadIdx.x;
@@ -472,7 +529,9 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
     // columns 8 .. 8 + kTT - 1 of the 8 rows above and below; dA likewise
     // with a 5-node halo (bit j of amask clear: outside an outflow line,
     // where dA is zero; the load still reads a valid node so that every
-    // load issues at once)
+    // load issues at once).  al[j] packs the dA slot (bits 0-11) and the
+    // slot of the node's combinations in sZ (bits 12 up: its own-node index,
+    // or the lane's dummy entry).
     int fo[kNFL], fl[kNFL], ao[kNAL], al[kNAL];
     unsigned amask = 0u;
 #pragma unroll
@@ -513,7 +572,8 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
         const bool zero = (bcx == 0 && (gx < 0 || gx >= nx)) || (bcy == 0 && (gy < 0 || gy >= ny));
         ao[j] = i == kALoads ? 0 : bc_map(gy, ny, bcy) * nx + bc_map(gx, nx, bcx);
         amask |= (zero ? 0u : 1u) << j;
-        al[j] = ly * kAP + lx;
+        const bool tile_node = i < kTT * kAE && lx >= 5 && lx < 5 + kTT;
+        al[j] = ly * kAP + lx + ((tile_node ? (ly - 5) * kZP + lx - 5 : kTT * kZP + (tid & 63)) << 12);
     }
     // the first half of the threads on x lines, the second on y lines: a
     // row (column) `line`, nodes kTS seg .. kTS seg + kTS - 1 of the tile
@@ -524,11 +584,20 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
     for (int v = (int)blockIdx.y * kTPB; v < v1; ++v) {
         const size_t pl = (size_t)v * cells;
 #pragma unroll
-        for (int j = 0; j < kNFL; ++j) sF[fl[j]] = (double)F[pl + fo[j]];
+        for (int j = 0; j < kNFL; ++j) sF[fl[j]] = F[pl + fo[j]];
 #pragma unroll
         for (int j = 0; j < kNAL; ++j) {
-            const double v = adj_dA<NZ, S>(o, pl + ao[j]);
-            sA[al[j]] = (amask >> j) & 1u ? v : 0.0;
+            // (slots from j = kTT kAE / kTThreads on hold halo rows only)
+            if (kZL && j * kTThreads < kTT * kAE) {  // constant once unrolled
+                double ze, zf;
+                const double v = adj_dA_ef<NZ, S>(o, pl + ao[j], ze, zf);
+                sA[al[j] & 4095] = (amask >> j) & 1u ? v : 0.0;
+                sZe[al[j] >> 12] = (float)ze;
+                sZf[al[j] >> 12] = zf;
+            } else {
+                const double v = adj_dA<NZ, S>(o, pl + ao[j]);
+                sA[al[j] & 4095] = (amask >> j) & 1u ? v : 0.0;
+            }
         }
         __syncthreads();
         double own[kTS], gl, gr;
@@ -538,9 +607,9 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
             const int t0 = x0 + kTS * seg;
             live = p != 0.0 && y0 + line < ny && t0 < nx;
             if (live) {
-                const double* f = sF + (8 + line) * kFP + kTS * seg;
+                const S* f = sF + (8 + line) * kFP + kTS * seg;
                 const double* a = sA + (5 + line) * kAP + kTS * seg;
-                double* corr = sCorr + tid * kCorrPitch;
+                double* corr = sCorr + tid;
                 if (p > 0.0) seg_faces<true, 1, 1>(f, a + 1, p * inv_dx, corr, own, gl, gr);
                 else seg_faces<false, 1, 1>(f, a, p * inv_dx, corr, own, gl, gr);
                 if (bcx == 0) seg_fold(own, gl, gr, t0, nx);
@@ -550,9 +619,9 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
             const int t0 = y0 + kTS * seg;
             live = p != 0.0 && x0 + line < nx && t0 < ny;
             if (live) {
-                const double* f = sF + kTS * seg * kFP + 8 + line;
+                const S* f = sF + kTS * seg * kFP + 8 + line;
                 const double* a = sA + kTS * seg * kAP + 5 + line;
-                double* corr = sCorr + tid * kCorrPitch;
+                double* corr = sCorr + tid;
                 if (p > 0.0) seg_faces<true, kFP, kAP>(f, a + kAP, p * inv_dy, corr, own, gl, gr);
                 else seg_faces<false, kFP, kAP>(f, a, p * inv_dy, corr, own, gl, gr);
                 if (bcy == 0) seg_fold(own, gl, gr, t0, ny);
@@ -561,7 +630,7 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
         __syncthreads();  // both tiles are read; they now take the results
         if (xl) {
 #pragma unroll
-            for (int i = 0; i < kTS; ++i) sF[line * kRP + kTS * seg + i] = live ? own[i] : 0.0;
+            for (int i = 0; i < kTS; ++i) sX[line * kRP + kTS * seg + i] = live ? own[i] : 0.0;
         } else {
 #pragma unroll
             for (int i = 0; i < kTS; ++i) sA[(kTS * seg + i) * kRP + line] = live ? own[i] : 0.0;
@@ -569,8 +638,12 @@ __global__ void __launch_bounds__(kTThreads) advect_adjoint_tile_kernel(const De
         __syncthreads();
         for (int i = tid; i < kTT * kTT; i += kTThreads) {
             const int r = i / kTT, c = i % kTT;
-            if (x0 + c < nx && y0 + r < ny)
-                adj_store<NZ, S>(o, pl + (size_t)(y0 + r) * nx + x0 + c, sF[r * kRP + c] + sA[r * kRP + c]);
+            if (x0 + c < nx && y0 + r < ny) {
+                const size_t g = pl + (size_t)(y0 + r) * nx + x0 + c;
+                const double V = sX[r * kRP + c] + sA[r * kRP + c];
+                if constexpr (kZL) adj_store_ef<S>(o, g, V, (double)sZe[r * kZP + c], sZf[r * kZP + c]);
+                else adj_store<NZ, S>(o, g, V);
+            }
         }
         __syncthreads();  // before the next plane overwrites the tiles
     }
@@ -812,8 +885,8 @@ hipError_t launch_advect_adjoint_n(int d, const DevTables* tab, int nplanes, con
     if (d == 2) {
         const int ntx = (nx + kTT - 1) / kTT, nty = (ny + kTT - 1) / kTT;
         const dim3 grid((unsigned)(ntx * nty), (unsigned)((nplanes + kTPB - 1) / kTPB));
-        hipLaunchKernelGGL((advect_adjoint_tile_kernel<NZ, S>), grid, dim3(kTThreads), 0, s, tab, F, io, nx, ny, bcx,
-                           bcy, inv_dx, inv_dy, ntx, nplanes);
+        hipLaunchKernelGGL((advect_adjoint_tile_kernel<NZ, S, sizeof(S) == 4>), grid, dim3(kTThreads), 0, s, tab, F,
+                           io, nx, ny, bcx, bcy, inv_dx, inv_dy, ntx, nplanes);
         return hipGetLastError();
     }
     // 1D: rows in 64-face chunks; periodic lines shorter than a chunk's
