@@ -722,10 +722,11 @@ __global__ void __launch_bounds__(64 * kParts) materialise_kernel(const DevTable
 }
 
 // dM = (dE/dM)^T dE per cell for the plane-set dE (type A).  Moments (n, u, T)
-// of M.  Each wavefront sums its rows' terms; the partial sums meet in LDS
-// and are added in wavefront order (deterministic).  The x factors (and
-// their u and T derivatives) of a set are evaluated once per cell and
-// wavefront.
+// of M.  With E = P_set g_x g_y per plane, the sums over a set's planes
+// factor: the wavefront accumulates, per x node, sum_y e g_y, sum_y e dg_y/du
+// and sum_y e dg_y/dT over its rows (three FMAs per plane) and applies the x
+// factors and their derivatives once per set.  The wavefronts' partial sums
+// meet in LDS and are added in wavefront order (deterministic).
 template <int D, int QM, typename A>
 __global__ void __launch_bounds__(64 * kParts) eq_adjoint_kernel(const DevTables* __restrict__ tabp,
                                                                     const double* __restrict__ M,
@@ -745,15 +746,42 @@ __global__ void __launch_bounds__(64 * kParts) eq_adjoint_kernel(const DevTables
     double dn = 0.0, dux = 0.0, duy = 0.0, dT = 0.0;
     const int nrow = plane_rows<D>(tab);
     const int r0 = part * nrow / NP, r1 = (part + 1) * nrow / NP;
-    int cur = -1;
-    double pre = 0.0, pre_n = 0.0, pre_T = 0.0;
-    double gx[QM], gxu[QM], gxT[QM];
+    // per x node of the current set: sum_y e g_y, sum_y e g_y,u, sum_y e g_y,T
+    double sg[QM], su[QM], sT[QM];
 #pragma unroll
     for (int kx = 0; kx < QM; ++kx) {
-        gx[kx] = 0.0;
-        gxu[kx] = 0.0;
-        gxT[kx] = 0.0;
+        sg[kx] = 0.0;
+        su[kx] = 0.0;
+        sT[kx] = 0.0;
     }
+    // folds the sums of set `set` into dn .. dT and clears them
+    auto flush = [&](int set) {
+        const int Q = tab->q[set];
+        const double pre = set ? chi_fac * nn * T : nn;  // P_phi = n, P_chi = (K+D-d) n T
+        const double pre_n = set ? chi_fac * T : 1.0;
+        const double pre_T = set ? chi_fac * nn : 0.0;
+        double xg = 0.0, xu = 0.0, xgy = 0.0, xT = 0.0, xgT = 0.0;
+#pragma unroll
+        for (int kx = 0; kx < QM; ++kx) {
+            if (kx < Q) {
+                double gx, gxu, gxT;
+                herm_factor_d(tab->h[set][kx], Q, u, th, gx, gxu, gxT);
+                xg = fma(gx, sg[kx], xg);     // sum e g_x g_y
+                xu = fma(gxu, sg[kx], xu);    // sum e g_x,u g_y
+                xgy = fma(gx, su[kx], xgy);   // sum e g_x g_y,u
+                xT = fma(gxT, sg[kx], xT);    // sum e g_x,T g_y
+                xgT = fma(gx, sT[kx], xgT);   // sum e g_x g_y,T
+            }
+            sg[kx] = 0.0;
+            su[kx] = 0.0;
+            sT[kx] = 0.0;
+        }
+        dn = fma(pre_n, xg, dn);
+        dux = fma(pre, xu, dux);
+        if (D == 2) duy = fma(pre, xgy, duy);
+        dT = fma(pre_T, xg, fma(pre, xT + xgT, dT));
+    };
+    int cur = -1;
     for (int r = r0; r < r1; ++r) {
         int set, ky, v;
         plane_row<D>(tab, r, set, ky, v);
@@ -762,31 +790,20 @@ __global__ void __launch_bounds__(64 * kParts) eq_adjoint_kernel(const DevTables
 #pragma unroll
         for (int kx = 0; kx < QM; ++kx) ev[kx] = (double)dE[(size_t)(v + (kx < Q ? kx : 0)) * cells + c];
         if (set != cur) {
+            if (cur >= 0) flush(cur);
             cur = set;
-            pre = set ? chi_fac * nn * T : nn;  // P_phi = n, P_chi = (K+D-d) n T
-            pre_n = set ? chi_fac * T : 1.0;
-            pre_T = set ? chi_fac * nn : 0.0;
-#pragma unroll
-            for (int kx = 0; kx < QM; ++kx) {
-                gx[kx] = 0.0;
-                gxu[kx] = 0.0;
-                gxT[kx] = 0.0;
-                if (kx < Q) herm_factor_d(tab->h[set][kx], Q, u, th, gx[kx], gxu[kx], gxT[kx]);
-            }
         }
         double gy = 1.0, gyu = 0.0, gyT = 0.0;
         if (D == 2) herm_factor_d(tab->h[set][ky], Q, w, th, gy, gyu, gyT);
 #pragma unroll
         for (int kx = 0; kx < QM; ++kx) {
-            if (kx < Q) {
-                const double e = ev[kx];
-                dn = fma(e, pre_n * gx[kx] * gy, dn);
-                dux = fma(e, pre * gxu[kx] * gy, dux);
-                if (D == 2) duy = fma(e, pre * gx[kx] * gyu, duy);
-                dT = fma(e, pre_T * gx[kx] * gy + pre * (gxT[kx] * gy + gx[kx] * gyT), dT);
-            }
+            const double e = kx < Q ? ev[kx] : 0.0;
+            sg[kx] = fma(e, gy, sg[kx]);
+            if (D == 2) su[kx] = fma(e, gyu, su[kx]);
+            sT[kx] = fma(e, gyT, sT[kx]);
         }
     }
+    if (cur >= 0) flush(cur);
     if (part > 0) {
         red[part - 1][0][lane] = dn;
         red[part - 1][1][lane] = dux;
