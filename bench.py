@@ -680,16 +680,22 @@ def run_adjoint(args, emit=True):
     target = torch.as_tensor(W.fourier_density(N, N, seed=args.seed + 1), device="cuda")
     A.density_loss_gradient(s, n0, target, 2, every=every)  # warm-up
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     zero = torch.zeros_like(n0)
-    s.set_equilibrium(n0, zero, zero, 1.0 / n0)
-    s.step(steps)
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    loss, grad = A.density_loss_gradient(s, n0, target, steps, every=every)
-    torch.cuda.synchronize()
-    t_grad = time.perf_counter() - t0
+    # forward-only rollouts and gradients interleaved, medians of three each
+    # (a single forward of 200 steps lasts about 0.1 s, so one sample moves
+    # with the clock state)
+    t_fwds, t_grads = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        s.set_equilibrium(n0, zero, zero, 1.0 / n0)
+        s.step(steps)
+        torch.cuda.synchronize()
+        t_fwds.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        loss, grad = A.density_loss_gradient(s, n0, target, steps, every=every)
+        torch.cuda.synchronize()
+        t_grads.append(time.perf_counter() - t0)
+    t_fwd, t_grad = float(np.median(t_fwds)), float(np.median(t_grads))
     vn = N * N * cfg.planes * steps
     cpu = None
     if not args.no_cpu:
@@ -712,13 +718,16 @@ def run_adjoint(args, emit=True):
         "metric": "velocity-node updates/s per IMEX step, forward + adjoint (gradient)",
         "value": vn / t_grad, "unit": "VN/s", "n_gpus": 1, "steps": steps, "warmup": 1,
         "ms_per_step": 1e3 * t_grad / steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 storage (state and stage adjoints), f64 moments, lambda and arithmetic", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32 storage (state and stage adjoints), f64 moments, lambda and arithmetic",
+        "data": "synthetic",
         "config": {"workload": f"2D periodic {N}x{N}, 8x8 velocities per f and g, {steps} steps, "
                                f"checkpoint every {every}; loss 1/2 sum (n - n*)^2, gradient "
                                "w.r.t. the initial density (u = 0, P = 1)",
                    "cells": N * N, "planes": cfg.planes, "seed": args.seed},
         "forward_only_ms_per_step": 1e3 * t_fwd / steps,
         "gradient_over_forward": t_grad / t_fwd,
+        "reps": {"forward_ms_per_step": [1e3 * t / steps for t in t_fwds],
+                 "gradient_ms_per_step": [1e3 * t / steps for t in t_grads]},
         "loss": loss,
         "grad_norm": float(grad.norm()),
         "cpu_baseline": cpu,
@@ -749,7 +758,7 @@ def other_workloads(args):
         "gradient_rollout": {"value": ra["value"], "unit": "VN/s", "ms_per_step": ra["ms_per_step"],
                              "steps": ra["steps"], "dtype": ra["dtype"], "workload": ra["config"]["workload"],
                              "forward_only_ms_per_step": ra["forward_only_ms_per_step"],
-                             "gradient_over_forward": ra["gradient_over_forward"]},
+                             "gradient_over_forward": ra["gradient_over_forward"], "reps": ra["reps"]},
     }
 
 
