@@ -226,6 +226,18 @@ size_t imexlb_step_record_bytes(const imexlb_ctx* ctx);
  * misaligned record. */
 imexlb_status imexlb_step_recorded(imexlb_ctx* ctx, void* d_record);
 
+/* imexlb_step_recorded out of place (Sec. III, Table I): the step reads the
+ * bound state F^n without modifying it, writes F^{n+1} (and, in between,
+ * the stage-4 combination R) into d_next, and then binds d_next as the
+ * state, so a reverse sweep keeps every state of a segment without copies.
+ * d_next: caller-owned device buffer of imexlb_state_bytes, 256-byte
+ * aligned, distinct from the bound state, the workspace and the record; the
+ * buffer bound before the call stays the caller's and keeps F^n.
+ * Asynchronous unless check_physical is set.  Errors: as
+ * imexlb_step_recorded; EINVAL for a NULL or misaligned d_next or one equal
+ * to the bound state (nothing is launched and the binding is unchanged). */
+imexlb_status imexlb_step_recorded_to(imexlb_ctx* ctx, void* d_record, void* d_next);
+
 /* imexlb_adjoint_step for the step that imexlb_step_recorded took from
  * d_Fn, reading the step's stage sources and moments from its record
  * instead of recomputing them (the forward passes 3 and 4).  Same result as

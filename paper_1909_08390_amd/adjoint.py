@@ -3,17 +3,23 @@ forward step and its hand-written adjoint (``imexlb_adjoint_step``).
 
 The forward pass starts from the local equilibrium of the initial fields
 (n, u_x, u_y, T), runs nsteps IMEX steps in the library and keeps a copy of
-the state every ``every`` steps.  The backward pass seeds the adjoint from
-the gradients of the final moments (``imexlb_moments_adjoint``), then walks
-the segments backwards: each segment is recomputed forward from its
-checkpoint, storing its states and each step's stage sources and moments
-(``imexlb_step_recorded``), and the adjoint steps run through them in
-reverse without recomputing those (``imexlb_adjoint_step_recorded``); the
-equilibrium adjoint (``imexlb_equilibrium_adjoint``) finally
-maps the adjoint state to gradients of the initial fields.  The density loss
-and its gradient come from ``imexlb_density_loss``.  Every step of this runs
-in the library's HIP kernels; this module only orders the calls and holds
-the checkpoints.
+the state every ``every`` steps.  The last segment is taken with recorded
+out-of-place steps (``imexlb_step_recorded_to``): its states and each step's
+stage sources and moments stay on the device, so the reverse sweep starts
+without a recomputation.  The backward pass seeds the adjoint from the
+gradients of the final moments (``imexlb_moments_adjoint``), then walks the
+segments backwards: each earlier segment is recomputed forward from its
+checkpoint with recorded out-of-place steps, and the adjoint steps run
+through the records in reverse (``imexlb_adjoint_step_recorded``).  The
+recomputation of segment k - 1 runs on a second stream while the adjoint
+runs through segment k on the caller's stream (they touch disjoint
+buffers: the recomputation the solver's workspace, its own records and
+states; the adjoint those of segment k and the adjoint workspace).  The
+equilibrium adjoint (``imexlb_equilibrium_adjoint``) finally maps the
+adjoint state to gradients of the initial fields.  The density loss and its
+gradient come from ``imexlb_density_loss``.  Every step of this runs in the
+library's HIP kernels; this module only orders the calls and holds the
+checkpoints.
 """
 from __future__ import annotations
 
@@ -26,6 +32,18 @@ def _zeros_like_field(solver):
     return torch.zeros(solver.cfg.field_shape, dtype=torch.float64, device=solver.device)
 
 
+def _recorded_segment(solver, nsteps: int):
+    """nsteps recorded out-of-place steps from the bound state on the
+    solver's stream: the states F^k before each step (the first is the
+    tensor bound on entry) and the records of the steps."""
+    states, records = [], []
+    for _ in range(nsteps):
+        states.append(solver.state)
+        records.append(solver.new_record())
+        solver.step_recorded(records[-1], out=torch.empty_like(solver.state))
+    return states, records
+
+
 class EquilibriumRollout(torch.autograd.Function):
     """(n0, ux0, uy0, T0) -> (n, ux, uy, T) after nsteps steps from the
     equilibrium of the initial fields (FP64 device tensors of the grid's
@@ -34,16 +52,20 @@ class EquilibriumRollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, n0, ux0, uy0, T0, solver, nsteps: int, every: int):
         every = max(1, int(every))
+        need = any(ctx.needs_input_grad[:4])
         solver.set_equilibrium(n0.detach(), ux0.detach(), uy0.detach(), T0.detach())
+        nseg = (nsteps + every - 1) // every
+        tail0 = (nseg - 1) * every if (need and nseg) else nsteps
         checkpoints = []
-        for k in range(nsteps):
+        for k in range(tail0):
             if k % every == 0:
                 checkpoints.append(solver.state.clone())
             solver.step(1)
+        tail = _recorded_segment(solver, nsteps - tail0) if tail0 < nsteps else None
         final_state = solver.state.clone()
         n, ux, uy, T = solver.moments()
         ctx.solver, ctx.nsteps, ctx.every = solver, nsteps, every
-        ctx.checkpoints, ctx.final_state = checkpoints, final_state
+        ctx.checkpoints, ctx.tail, ctx.final_state = checkpoints, tail, final_state
         ctx.save_for_backward(n0.detach(), ux0.detach(), uy0.detach(), T0.detach())
         return n, ux, uy, T
 
@@ -53,18 +75,39 @@ class EquilibriumRollout(torch.autograd.Function):
         n0, ux0, uy0, T0 = ctx.saved_tensors
         g = [x if x is not None else _zeros_like_field(s) for x in (gn, gux, guy, gT)]
         lam = s.moments_adjoint(ctx.final_state, *g)
-        nseg = len(ctx.checkpoints)
+        main = torch.cuda.current_stream(s.device)
+        side = torch.cuda.Stream(device=s.device)  # default priority
+        every, nsteps = ctx.every, ctx.nsteps
+
+        def recompute(seg):
+            # starts once the caller's stream has finished what it was given
+            # so far (at most one segment is recomputed ahead of the adjoint)
+            side.wait_stream(main)
+            with torch.cuda.stream(side):
+                s.set_stream(side)
+                ck = ctx.checkpoints[seg]
+                ck.record_stream(side)
+                s.bind_state(ck)  # read only by the out-of-place steps
+                start = seg * every
+                states, records = _recorded_segment(s, min(start + every, nsteps) - start)
+                ev = torch.cuda.Event()
+                ev.record(side)
+            s.set_stream(main)
+            for t in states[1:] + records:
+                t.record_stream(main)
+            return states, records, ev
+
+        nseg = len(ctx.checkpoints) + (1 if ctx.tail is not None else 0)
+        pending = (*ctx.tail, None) if ctx.tail is not None else (recompute(nseg - 1) if nseg else None)
         for seg in reversed(range(nseg)):
-            start = seg * ctx.every
-            end = min(start + ctx.every, ctx.nsteps)
-            s.set_state(ctx.checkpoints[seg])
-            states, records = [], []
-            for _ in range(start, end):
-                states.append(s.state.clone())
-                records.append(s.new_record())
-                s.step_recorded(records[-1])
+            states, records, ev = pending
+            if ev is not None:
+                main.wait_event(ev)
+            if seg > 0:
+                pending = recompute(seg - 1)
             for F, rec in zip(reversed(states), reversed(records)):
                 lam = s.adjoint_step(F, lam, record=rec)
+        s.state.record_stream(main)
         dn, dux, duy, dT = s.equilibrium_adjoint(n0, ux0, uy0, T0, lam)
         return dn, dux, duy, dT, None, None, None
 

@@ -99,6 +99,8 @@ struct StageArgs {
     void* out;             // output plane-set (G3, G4) or FP64 VF (advect)
     double* mout;          // output moments
     void* fbuf;            // state buffer: F^n / R / F^{n+1}
+    void* rbuf;            // stage 4: where R goes (fbuf, or the next state
+                           // buffer of an out-of-place step)
     const double* mn;      // moments of F^n (stage 4)
     const DevTables* tab;
     int nx, ny, bcx, bcy;
@@ -125,8 +127,10 @@ bool quadrature_rule(int Q, double* p, double* w);
 hipError_t upload_tables(int d, const int Q[2], const double p[2][kQMax], const double w[2][kQMax],
                          int tab_nodes, DevTables** d_tab, hipStream_t stream);
 void stage_coefficients(double dt, double tau, StageArgs& a);  // dt, omega, a1, a2, k[]
+// Per-pass arguments of one step from F; with Fnext the step is out of place
+// (R and F^{n+1} go to Fnext, F is only read).
 void pass_args(const StageArgs& a, void* F, void* G3, void* G4, double* Mn, double* M3, double* M4,
-               StageArgs out[3]);
+               StageArgs out[3], void* Fnext = nullptr);
 
 // Launchers (kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_stage(int d, bool f32, int kind, const StageArgs& a, hipStream_t s);

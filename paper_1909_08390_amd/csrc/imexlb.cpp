@@ -298,7 +298,8 @@ void stage_coefficients(double dt, double tau, StageArgs& a) {
 // Pass 3 advects F2 = a2 F^n + b2 E^n; passes 4 and 5 advect
 // F3 = a1 G3 + c a1 E3 and F4 = a1 G4 + c a1 E4 (relax on read).
 void pass_args(const StageArgs& a, void* F, void* G3, void* G4, double* Mn, double* M3, double* M4,
-               StageArgs out[3]) {
+               StageArgs out[3], void* Fnext) {
+    if (!Fnext) Fnext = F;
     const double cc = kAlpha * a.omega;
     out[0] = out[1] = out[2] = a;
     out[0].src = F;
@@ -312,14 +313,15 @@ void pass_args(const StageArgs& a, void* F, void* G3, void* G4, double* Mn, doub
     out[1].out = G4;
     out[1].mout = M4;
     out[1].fbuf = F;
+    out[1].rbuf = Fnext;
     out[1].mn = Mn;
     out[1].a_rel = a.a1;
     out[1].b_rel = cc * a.a1;
     out[2].src = G4;
     out[2].msrc = M4;
-    out[2].out = F;
+    out[2].out = Fnext;
     out[2].mout = Mn;
-    out[2].fbuf = F;
+    out[2].fbuf = Fnext;
     out[2].a_rel = a.a1;
     out[2].b_rel = cc * a.a1;
 }
@@ -587,8 +589,10 @@ StepRecord record_of(const imexlb_ctx* c, const void* rec) {
 // The launch sequence of nsteps IMEX steps.  When ev is non-NULL it holds
 // 3 * nsteps + 1 events recorded around the passes.  With rec (one step),
 // the stage sources G3, G4 and the moments M3, M4 go to the record instead
-// of the workspace.
-imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev, const StepRecord* rec = nullptr) {
+// of the workspace.  With next (one step), R and F^{n+1} go to next, which
+// then becomes the bound state; the buffer bound before keeps F^n.
+imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev, const StepRecord* rec = nullptr,
+                        void* next = nullptr) {
     const int d = c->cfg.d;
     const bool f32 = c->cfg.storage == IMEXLB_F32;
     StageArgs a = base_args(c);
@@ -599,7 +603,7 @@ imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev, const StepRec
     double* M3 = rec ? rec->M3 : work_m(c, 1);
     double* M4 = rec ? rec->M4 : work_m(c, 2);
     StageArgs pa[3];
-    pass_args(a, F, G3, G4, Mn, M3, M4, pa);
+    pass_args(a, F, G3, G4, Mn, M3, M4, pa, next);
     const StageArgs &a3 = pa[0], &a4 = pa[1], &a5 = pa[2];
     const bool check = c->cfg.check_physical != 0;
     hipError_t e = hipSuccess;
@@ -616,6 +620,7 @@ imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev, const StepRec
         if (e == hipSuccess && ev) e = hipEventRecord(ev[3 * s + 3], c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "step");
+    if (next) c->d_state = next;
     return IMEXLB_OK;
 }
 
@@ -649,18 +654,39 @@ size_t imexlb_step_record_bytes(const imexlb_ctx* c) {
     return c ? 2 * record_ps(c) + 3 * record_ms(c) : 0;
 }
 
-imexlb_status imexlb_step_recorded(imexlb_ctx* c, void* d_record) {
+}  // extern "C"
+
+namespace {
+
+imexlb_status step_recorded(imexlb_ctx* c, void* d_record, void* d_next, const char* what) {
     if (!c) return IMEXLB_EINVAL;
-    if (!d_record) return fail(c, IMEXLB_EINVAL, "step_recorded: NULL record");
-    if ((uintptr_t)d_record & 255) return fail(c, IMEXLB_EINVAL, "step_recorded: record must be 256-byte aligned");
-    if (need_state(c) != IMEXLB_OK) return fail(c, IMEXLB_ESTATE, "step_recorded: no bound state");
+    const std::string w = what;
+    if (!d_record) return fail(c, IMEXLB_EINVAL, w + ": NULL record");
+    if ((uintptr_t)d_record & 255) return fail(c, IMEXLB_EINVAL, w + ": record must be 256-byte aligned");
+    if (need_state(c) != IMEXLB_OK) return fail(c, IMEXLB_ESTATE, w + ": no bound state");
     const StepRecord r = record_of(c, d_record);
     // M^n before pass 5 overwrites it with M^{n+1}
     hipError_t e = hipMemcpyAsync(r.Mn, work_m(c, 0), (size_t)c->nf * c->cells * sizeof(double),
                                   hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "step_recorded");
-    imexlb_status st = run_steps(c, 1, nullptr, &r);
+    if (e != hipSuccess) return hip_fail(c, e, what);
+    imexlb_status st = run_steps(c, 1, nullptr, &r, d_next);
     return st == IMEXLB_OK ? finish_check(c) : st;
+}
+
+}  // namespace
+
+extern "C" {
+
+imexlb_status imexlb_step_recorded(imexlb_ctx* c, void* d_record) {
+    return step_recorded(c, d_record, nullptr, "step_recorded");
+}
+
+imexlb_status imexlb_step_recorded_to(imexlb_ctx* c, void* d_record, void* d_next) {
+    if (!c) return IMEXLB_EINVAL;
+    if (!d_next) return fail(c, IMEXLB_EINVAL, "step_recorded_to: NULL next state");
+    if ((uintptr_t)d_next & 255) return fail(c, IMEXLB_EINVAL, "step_recorded_to: next state must be 256-byte aligned");
+    if (d_next == c->d_state) return fail(c, IMEXLB_EINVAL, "step_recorded_to: next state is the bound state");
+    return step_recorded(c, d_record, d_next, "step_recorded_to");
 }
 
 imexlb_status imexlb_step_timed(imexlb_ctx* c, int nsteps, double ms[3]) {

@@ -767,7 +767,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                     if (row_real && ox0 + i < nx) bstore1<S, kStreamStore>(ro, own_off + i * (int)sizeof(S), outv[i]);
             }
             if constexpr (KIND == kStage4) {
-                const Rsrc rf = plane_rsrc(static_cast<S*>(a.fbuf) + plane_off(st.v), ps);
+                const Rsrc rf = plane_rsrc(static_cast<S*>(a.rbuf) + plane_off(st.v), ps);
                 if constexpr (VEC) {
                     bstore_own<S, OWN>(rf, own_off, fbv);
                 } else {
@@ -1183,7 +1183,7 @@ __device__ __forceinline__ void stage1d_body(const A& a, int x0, S (*tile)[TX + 
                     if (ox0 + i < nx) bstore1<S>(ro, own_off + i * (int)sizeof(S), outv[i]);
             }
             if constexpr (KIND == kStage4) {
-                const Rsrc rf = plane_rsrc(static_cast<S*>(a.fbuf) + plane_off(st.v), ps);
+                const Rsrc rf = plane_rsrc(static_cast<S*>(a.rbuf) + plane_off(st.v), ps);
                 if constexpr (VEC) {
                     bstore4<S>(rf, own_off, fbv);
                 } else {

@@ -116,6 +116,7 @@ def lib():
         L.imexlb_step_record_bytes.argtypes = [_vp]
         L.imexlb_step_record_bytes.restype = ctypes.c_size_t
         L.imexlb_step_recorded.argtypes = [_vp, _vp]
+        L.imexlb_step_recorded_to.argtypes = [_vp, _vp, _vp]
         L.imexlb_adjoint_step_recorded.argtypes = [_vp] * 5
         L.imexlb_moments_adjoint.argtypes = [_vp] * 7
         L.imexlb_advect_adjoint.argtypes = [_vp] * 4
@@ -318,6 +319,17 @@ class Solver:
             self._h, _vp(n.data_ptr()), _vp(ux.data_ptr()),
             _vp(uy.data_ptr()) if uy is not None else None, _vp(T.data_ptr())), "set_equilibrium")
 
+    def bind_state(self, F):
+        """Bind the tensor F (state shape and dtype, contiguous) as the state
+        buffer, keeping the workspace (``imexlb_bind``), and take its moments
+        (``imexlb_set_state`` without a copy).  Out-of-place steps then read
+        F without modifying it."""
+        assert F.dtype == self.state_dtype and tuple(F.shape) == tuple(self.cfg.shape)
+        assert F.is_contiguous() and F.device == self.device
+        self._check(self.L.imexlb_bind(self._h, _vp(F.data_ptr()), _vp(self.workspace.data_ptr())), "bind")
+        self.state = F
+        self._check(self.L.imexlb_set_state(self._h, _vp(F.data_ptr())), "set_state")
+
     def set_state(self, F):
         F = self.torch.as_tensor(F, dtype=self.state_dtype, device=self.device).contiguous()
         assert tuple(F.shape) == tuple(self.cfg.shape)
@@ -326,6 +338,12 @@ class Solver:
 
     def step(self, nsteps: int = 1):
         self._check(self.L.imexlb_step(self._h, int(nsteps)), "step")
+
+    def set_stream(self, stream):
+        """Run the following calls on ``stream`` (a torch.cuda.Stream of
+        default priority); ``imexlb_set_stream``."""
+        self._check(self.L.imexlb_set_stream(self._h, _vp(stream.cuda_stream)), "set_stream")
+        self.stream = stream
 
     def step_timed(self, nsteps: int):
         """Step and return the summed per-pass milliseconds (stage 3, 4, 5),
@@ -404,11 +422,21 @@ class Solver:
         nb = self.L.imexlb_step_record_bytes(self._h)
         return self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
 
-    def step_recorded(self, record):
+    def step_recorded(self, record, out=None):
         """One step that also leaves its stage sources and moments in record
-        (a buffer from new_record) for adjoint_step."""
+        (a buffer from new_record) for adjoint_step.  With ``out`` (a tensor
+        like ``state``) the step is out of place (``imexlb_step_recorded_to``):
+        F^{n+1} goes to ``out``, which becomes ``self.state``, and the tensor
+        that was ``self.state`` keeps F^n."""
         assert record.numel() >= self.L.imexlb_step_record_bytes(self._h) and record.data_ptr() % 256 == 0
-        self._check(self.L.imexlb_step_recorded(self._h, _vp(record.data_ptr())), "step_recorded")
+        if out is None:
+            self._check(self.L.imexlb_step_recorded(self._h, _vp(record.data_ptr())), "step_recorded")
+            return
+        assert out.dtype == self.state_dtype and tuple(out.shape) == tuple(self.cfg.shape)
+        assert out.is_contiguous() and out.device == self.device
+        self._check(self.L.imexlb_step_recorded_to(self._h, _vp(record.data_ptr()), _vp(out.data_ptr())),
+                    "step_recorded_to")
+        self.state = out
 
     def adjoint_step(self, Fn, lam1, record=None):
         """(dF^{n+1}/dF^n)^T lam1 for the step taken from state Fn; with the

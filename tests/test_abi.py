@@ -74,6 +74,7 @@ def test_null_arguments():
     assert L.imexlb_bind(None, None, None) == I.EINVAL
     assert L.imexlb_density_loss(None, None, None, None, None) == I.EINVAL
     assert L.imexlb_step_recorded(None, None) == I.EINVAL
+    assert L.imexlb_step_recorded_to(None, None, None) == I.EINVAL
     assert L.imexlb_adjoint_step_recorded(None, None, None, None, None) == I.EINVAL
     assert L.imexlb_step_record_bytes(None) == 0
 

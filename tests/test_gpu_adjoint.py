@@ -152,6 +152,109 @@ def test_recorded_step_and_adjoint_match_the_recomputing_ones(case, kind):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("case,kind", [STEP_CASES[1], STEP_CASES[4], STEP_CASES[7]])
+def test_out_of_place_recorded_step_matches_in_place(case, kind):
+    """step_recorded_to writes the same F^{n+1} and record as the in-place
+    recorded step, leaves the buffer it read holding F^n, and binds the new
+    buffer as the state (two steps in a row); a next buffer equal to the
+    bound state is rejected without launching anything.  FP64 and FP32."""
+    torch = _torch()
+    for storage in (I.F64, I.F32):
+        c = I.Config(storage=storage, **case)
+        s = base_state(c, kind, 7)
+        F = s.state.clone()
+        s.set_state(F)
+        # zeroed, so that the alignment padding between the parts compares equal
+        rec1, rec2 = s.new_record().zero_(), s.new_record().zero_()
+        s.step_recorded(rec1)
+        plain1 = s.state.clone()
+        s.step_recorded(rec2)
+        plain2 = s.state.clone()
+        src = F.clone()
+        s.bind_state(src)
+        o1, o2 = torch.empty_like(F), torch.empty_like(F)
+        r1, r2 = s.new_record().zero_(), s.new_record().zero_()
+        s.step_recorded(r1, out=o1)
+        assert s.state is o1
+        s.step_recorded(r2, out=o2)
+        assert s.state is o2
+        assert torch.equal(src, F) and torch.equal(o1, plain1) and torch.equal(o2, plain2)
+        assert torch.equal(r1, rec1) and torch.equal(r2, rec2)
+        assert s.L.imexlb_step_recorded_to(s._h, I._vp(r1.data_ptr()), I._vp(o2.data_ptr())) == I.EINVAL
+        assert s.state is o2 and torch.equal(o2, plain2)
+
+
+@pytest.mark.parametrize("nsteps,every", [(8, 3), (5, 5), (4, 1), (0, 3)])
+def test_rollout_gradient_matches_single_stream_reverse_sweep(nsteps, every):
+    """The autograd rollout (last segment recorded in the forward, earlier
+    segments recomputed out of place on a second stream while the adjoint
+    runs through the next one) gives bit for bit the gradients of the same
+    schedule run on one stream with in-place recorded steps and copies of
+    the states; and to rounding those of a plain reverse sweep with the
+    recomputing adjoint step (whose M^n comes from the moment kernel rather
+    than from the previous step's pass 5)."""
+    torch = _torch()
+    from paper_1909_08390_amd import adjoint as A
+
+    c = I.Config(d=2, nx=40, ny=36, q_phi=4, q_chi=3, K=2, tau=1e-3, dt=1e-3, bc_x=I.PERIODIC,
+                 bc_y=I.OUTFLOW)
+    n, ux, uy, T = (torch.as_tensor(x, device="cuda")
+                    for x in W.random_fields(c.field_shape, 2, n_range=(0.8, 1.2), u_max=0.3,
+                                             T_range=(0.8, 1.2)))
+    rng = np.random.Generator(np.random.PCG64(9))
+    g = [torch.as_tensor(rng.normal(size=c.field_shape), device="cuda") for _ in range(4)]
+    s = I.Solver(c)
+    ins = [x.clone().requires_grad_(True) for x in (n, ux, uy, T)]
+    outs = A.rollout(s, *ins, nsteps, every)
+    torch.autograd.backward(outs, grad_tensors=g)
+    got = [x.grad for x in ins]
+
+    r = I.Solver(c)
+
+    def recorded(k):
+        items = []
+        for _ in range(k):
+            items.append((r.state.clone(), r.new_record()))
+            r.step_recorded(items[-1][1])
+        return items
+
+    r.set_equilibrium(n, ux, uy, T)
+    nseg = (nsteps + every - 1) // every
+    tail0 = (nseg - 1) * every if nseg else 0
+    ck = []
+    for k in range(tail0):
+        if k % every == 0:
+            ck.append(r.state.clone())
+        r.step(1)
+    tail = recorded(nsteps - tail0)
+    for a, b in zip(outs, r.moments()):
+        assert torch.equal(a, b)
+    lam = r.moments_adjoint(r.state.clone(), *g)
+    for seg in reversed(range(nseg)):
+        if seg < len(ck):
+            r.set_state(ck[seg])
+            items = recorded(min(every, nsteps - seg * every))
+        else:
+            items = tail
+        for F, rec in reversed(items):
+            lam = r.adjoint_step(F, lam, record=rec)
+    want = r.equilibrium_adjoint(n, ux, uy, T, lam)
+    for a, b in zip(got, want):
+        assert torch.equal(a, b)
+
+    r.set_equilibrium(n, ux, uy, T)
+    states = []
+    for _ in range(nsteps):
+        states.append(r.state.clone())
+        r.step(1)
+    lam = r.moments_adjoint(r.state.clone(), *g)
+    for F in reversed(states):
+        lam = r.adjoint_step(F, lam)
+    plain = r.equilibrium_adjoint(n, ux, uy, T, lam)
+    for a, b in zip(got, plain):
+        assert float((a - b).abs().max()) <= 1e-12 * max(float(b.abs().max()), 1e-300)
+
+
 @pytest.mark.parametrize("case,kind", [STEP_CASES[0], STEP_CASES[2], STEP_CASES[5], STEP_CASES[9]])
 def test_f32_storage_adjoint_step_matches_f64(case, kind):
     """FP32 storage keeps the stage adjoints inside a step in FP32 (all
