@@ -201,7 +201,9 @@ imexlb_status imexlb_check_state(const imexlb_ctx* ctx);
  * ------------------------------------------------------------------------ */
 
 /* Size of, and binding of, the adjoint workspace (256-byte aligned device
- * buffer): seven plane-sets of the storage type and four FP64 moment sets. */
+ * buffer): five plane-sets of the storage type, one FP64 moment set and
+ * the record of one step (imexlb_step_record_bytes), in which the adjoint
+ * step recomputes the step it reverses. */
 size_t imexlb_adjoint_workspace_bytes(const imexlb_ctx* ctx);
 imexlb_status imexlb_adjoint_bind(imexlb_ctx* ctx, void* d_adj_workspace);
 
@@ -216,7 +218,11 @@ imexlb_status imexlb_adjoint_step(imexlb_ctx* ctx, const void* d_Fn, const doubl
  * the stage sources G3, G4 of Table I's third and fourth stages (storage
  * type, ABI layout) and the moments M^n, M3, M4 of one step (FP64, fields
  * (n, u_x, [u_y], T)), laid out G3 | G4 | M^n | M3 | M4, each part 256-byte
- * aligned.  imexlb_step_record_bytes: size of one record. */
+ * aligned; in 2D followed by F2 | F3 | F4, the stage values (Table I) at
+ * every cell as the three stage passes formed them on read and advected
+ * them (storage type), so that the adjoint linearises the advection at the
+ * very values the forward swept.  imexlb_step_record_bytes: size of one
+ * record. */
 size_t imexlb_step_record_bytes(const imexlb_ctx* ctx);
 
 /* One IMEX step, as imexlb_step(ctx, 1), that also leaves the step's stage

@@ -101,6 +101,8 @@ struct StageArgs {
     void* fbuf;            // state buffer: F^n / R / F^{n+1}
     void* rbuf;            // stage 4: where R goes (fbuf, or the next state
                            // buffer of an out-of-place step)
+    void* sval_out;        // 2D passes 3 / 4 / 5: where the stage values F2 / F3 /
+                           // F4 at the own cells go (recorded steps), or NULL
     const double* mn;      // moments of F^n (stage 4)
     const DevTables* tab;
     int nx, ny, bcx, bcy;

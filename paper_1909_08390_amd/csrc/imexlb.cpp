@@ -571,19 +571,27 @@ imexlb_status imexlb_get_state(const imexlb_ctx* c, void* F) {
 namespace {
 
 // Where a recorded step puts its stage sources and moments (caller memory,
-// imexlb_step_record_bytes): G3 | G4 (storage type) | M^n | M3 | M4 (FP64).
+// imexlb_step_record_bytes): G3 | G4 (storage type) | M^n | M3 | M4 (FP64),
+// and in 2D | F2 | F3 | F4, the stage values the three passes swept, as
+// stored at the own cells by their relax on read (storage type).
 struct StepRecord {
     void *G3, *G4;
     double *Mn, *M3, *M4;
+    void *F2, *F3, *F4;  // NULL in 1D
 };
 
 size_t record_ps(const imexlb_ctx* c) { return align256((size_t)c->nplanes * c->cells * c->elem); }
 size_t record_ms(const imexlb_ctx* c) { return align256((size_t)c->nf * c->cells * sizeof(double)); }
+int record_nsv(const imexlb_ctx* c) { return c->cfg.d == 2 ? 3 : 0; }
+size_t record_bytes(const imexlb_ctx* c) { return (2 + record_nsv(c)) * record_ps(c) + 3 * record_ms(c); }
 
 StepRecord record_of(const imexlb_ctx* c, const void* rec) {
     char* b = (char*)rec;
     const size_t ps = record_ps(c), ms = record_ms(c);
-    return StepRecord{b, b + ps, (double*)(b + 2 * ps), (double*)(b + 2 * ps + ms), (double*)(b + 2 * ps + 2 * ms)};
+    char* f = b + 2 * ps + 3 * ms;
+    const bool sv = record_nsv(c) > 0;
+    return StepRecord{b, b + ps, (double*)(b + 2 * ps), (double*)(b + 2 * ps + ms), (double*)(b + 2 * ps + 2 * ms),
+                      sv ? f : nullptr, sv ? f + ps : nullptr, sv ? f + 2 * ps : nullptr};
 }
 
 // The launch sequence of nsteps IMEX steps.  When ev is non-NULL it holds
@@ -604,6 +612,11 @@ imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev, const StepRec
     double* M4 = rec ? rec->M4 : work_m(c, 2);
     StageArgs pa[3];
     pass_args(a, F, G3, G4, Mn, M3, M4, pa, next);
+    if (rec) {
+        pa[0].sval_out = rec->F2;
+        pa[1].sval_out = rec->F3;
+        pa[2].sval_out = rec->F4;
+    }
     const StageArgs &a3 = pa[0], &a4 = pa[1], &a5 = pa[2];
     const bool check = c->cfg.check_physical != 0;
     hipError_t e = hipSuccess;
@@ -651,7 +664,7 @@ imexlb_status imexlb_step(imexlb_ctx* c, int nsteps) {
 }
 
 size_t imexlb_step_record_bytes(const imexlb_ctx* c) {
-    return c ? 2 * record_ps(c) + 3 * record_ms(c) : 0;
+    return c ? record_bytes(c) : 0;
 }
 
 }  // extern "C"
@@ -822,27 +835,29 @@ imexlb_status imexlb_check_state(const imexlb_ctx* c) {
 // ---------------------------------------------------------------------------
 namespace {
 
-// Adjoint workspace: F scratch | G3 | G4 | X1 | X2 | X3 | X4 (plane-sets of
-// the storage type: the recomputed stage sources, then the stage adjoints
-// between the kernels of the reverse sweep) | M^n | M3 | M4 | dM (FP64
-// moment sets).
+// Adjoint workspace: F scratch | X1 | X2 | X3 | X4 (plane-sets of the
+// storage type: the step's scratch copy of F^n, then the stage adjoints
+// between the kernels of the reverse sweep) | dM (FP64 moment set) | the
+// record of the recomputed step (imexlb_step_record_bytes).
 struct AdjLayout {
-    size_t ps, ms;  // bytes: storage plane-set, FP64 moment set
-    size_t total() const { return 7 * ps + 4 * ms; }
+    size_t ps, ms, rec;  // bytes: storage plane-set, FP64 moment set, record
+    size_t total() const { return 5 * ps + ms + rec; }
 };
 
 AdjLayout adj_layout(const imexlb_ctx* c) {
     AdjLayout L;
     L.ps = align256((size_t)c->nplanes * c->cells * c->elem);
     L.ms = align256((size_t)c->nf * c->cells * sizeof(double));
+    L.rec = record_bytes(c);
     return L;
 }
 
-void* adj_s(const imexlb_ctx* c, int i) { return (char*)c->d_adj + (size_t)i * adj_layout(c).ps; }
-void* adj_x(const imexlb_ctx* c, int i) { return adj_s(c, 3 + i); }
-double* adj_m(const imexlb_ctx* c, int i) {
+void* adj_s(const imexlb_ctx* c) { return c->d_adj; }
+void* adj_x(const imexlb_ctx* c, int i) { return (char*)c->d_adj + (size_t)(1 + i) * adj_layout(c).ps; }
+double* adj_dm(const imexlb_ctx* c) { return (double*)((char*)c->d_adj + 5 * adj_layout(c).ps); }
+void* adj_rec(const imexlb_ctx* c) {
     const AdjLayout L = adj_layout(c);
-    return (double*)((char*)c->d_adj + 7 * L.ps + (size_t)i * L.ms);
+    return (char*)c->d_adj + 5 * L.ps + L.ms;
 }
 
 }  // namespace
@@ -863,16 +878,19 @@ imexlb_status imexlb_adjoint_bind(imexlb_ctx* c, void* d_adj) {
 
 namespace {
 
-// The reverse sweep of one step taken from Fn, given the step's stage
-// sources G3, G4 and the moments M^n, M3, M4.
-imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const void* G4, const double* Mn,
-                           const double* M3, const double* M4, const double* lam1, double* lam0) {
+// The reverse sweep of one step taken from Fn, given the step's record: the
+// stage sources G3, G4, the moments M^n, M3, M4 and (2D) the stage values
+// F2, F3, F4 the forward swept; without those (1D) the stage values are
+// formed again from the sources and moments.
+imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const StepRecord& r, const double* lam1, double* lam0) {
+    const void *G3 = r.G3, *G4 = r.G4;
+    const double *Mn = r.Mn, *M3 = r.M3, *M4 = r.M4;
     const int d = c->cfg.d;
     const bool f32 = c->cfg.storage == IMEXLB_F32;
     const long long cells = c->cells;
     const double chi = (double)(c->cfg.K + kDTotal - d), dk = (double)(kDTotal + c->cfg.K);
     hipStream_t s = c->stream;
-    double* dM = adj_m(c, 3);
+    double* dM = adj_dm(c);
     void *X1 = adj_x(c, 0), *X2 = adj_x(c, 1), *X3 = adj_x(c, 2), *X4 = adj_x(c, 3);
     const StageArgs a = base_args(c);
     hipError_t e = hipSuccess;
@@ -918,25 +936,28 @@ imexlb_status adjoint_core(imexlb_ctx* c, const void* Fn, const void* G3, const 
     const double* L = lam1;
     // stage 4: F4 = a1 S4 + c a1 E4, dA4 = -(2/3) dt L, d(dF4) = -(2/3) L;
     // dE4 = c a1 V4 + (2/3) w a1 L, dS4 (before the moment term) = a1 V4 - (2/3) w a1 L
-    if (e == hipSuccess) e = launch_materialise(d, qm, f32, c->d_tab, G4, M4, a1, cc * a1, X1, cells, chi, s);
+    const void* F4 = r.F4 ? r.F4 : X1;
+    if (e == hipSuccess && !r.F4) e = launch_materialise(d, qm, f32, c->d_tab, G4, M4, a1, cc * a1, X1, cells, chi, s);
     if (e == hipSuccess)
-        e = adv(X1, {L}, {-(2.0 / 3.0) * dt}, cc * a1, {(2.0 / 3.0) * w * a1}, a1, {-(2.0 / 3.0) * w * a1}, X2, X4,
+        e = adv(F4, {L}, {-(2.0 / 3.0) * dt}, cc * a1, {(2.0 / 3.0) * w * a1}, a1, {-(2.0 / 3.0) * w * a1}, X2, X4,
                 false);
     if (e == hipSuccess) e = eqt(M4, X2);
     if (e == hipSuccess) e = momt(M4, X4, X3, false);  // X3 = dS4
     // stage 3: dA3 = -(1/6) dt L - dt/4 dS4, d(dF3) = -(1/6) L - kappa dS4
-    if (e == hipSuccess) e = launch_materialise(d, qm, f32, c->d_tab, G3, M3, a1, cc * a1, X1, cells, chi, s);
+    const void* F3 = r.F3 ? r.F3 : X1;
+    if (e == hipSuccess && !r.F3) e = launch_materialise(d, qm, f32, c->d_tab, G3, M3, a1, cc * a1, X1, cells, chi, s);
     if (e == hipSuccess)
-        e = adv(X1, {L, X3}, {-dt / 6.0, -0.25 * dt}, cc * a1, {w * a1 / 6.0, ka * w * a1}, a1,
+        e = adv(F3, {L, X3}, {-dt / 6.0, -0.25 * dt}, cc * a1, {w * a1 / 6.0, ka * w * a1}, a1,
                 {-w * a1 / 6.0, -ka * w * a1}, X2, X4, false);
     if (e == hipSuccess) e = eqt(M3, X2);
     if (e == hipSuccess) e = momt(M3, X4, X1, false);  // X1 = dS3
     // stages 2 and 1: F2 = a2 F^n + b2 E^n, dA2 = -(1/6) dt L - dt/4 dS4 - dt dS3,
     // d(dF1) = -beta dS4, d(dF2) = -(1/6) L - eta dS4 - (1 - alpha) dS3; the
     // moment adjoint's input goes straight to lam0 and is completed in place
-    if (e == hipSuccess) e = launch_materialise(d, qm, f32, c->d_tab, Fn, Mn, a2, b2, X2, cells, chi, s);
+    const void* F2 = r.F2 ? r.F2 : X2;
+    if (e == hipSuccess && !r.F2) e = launch_materialise(d, qm, f32, c->d_tab, Fn, Mn, a2, b2, X2, cells, chi, s);
     if (e == hipSuccess)
-        e = adv(X2, {L, X3, X1}, {-dt / 6.0, -0.25 * dt, -dt}, b2,
+        e = adv(F2, {L, X3, X1}, {-dt / 6.0, -0.25 * dt, -dt}, b2,
                 {w * a2 / 6.0, w * a1 * be + w * a2 * et, w * a2 * (1.0 - kAlpha)}, a2,
                 {1.0 - w * a2 / 6.0, 1.0 - w * a1 * be - w * a2 * et, 1.0 - w * a2 * (1.0 - kAlpha)}, X4, lam0,
                 true);
@@ -961,19 +982,24 @@ imexlb_status imexlb_adjoint_step(imexlb_ctx* c, const void* Fn, const double* l
     const long long cells = c->cells;
     const double dk = (double)(kDTotal + c->cfg.K);
     hipStream_t s = c->stream;
-    // forward recompute of the stage sources: G3 = S_3, G4 = S_4 and moments
-    void* Fs = adj_s(c, 0);
-    void* G3 = adj_s(c, 1);
-    void* G4 = adj_s(c, 2);
-    double *Mn = adj_m(c, 0), *M3 = adj_m(c, 1), *M4 = adj_m(c, 2);
+    // forward recompute of the step's record, on a scratch copy of F^n: the
+    // stage sources G3 = S_3, G4 = S_4, the moments and (2D) the stage
+    // values; pass 5 runs only for the stage values F4 its relax forms
+    void* Fs = adj_s(c);
+    const StepRecord r = record_of(c, adj_rec(c));
     StageArgs pa[3];
-    pass_args(base_args(c), Fs, G3, G4, Mn, M3, M4, pa);
+    pass_args(base_args(c), Fs, r.G3, r.G4, r.Mn, r.M3, r.M4, pa);
+    pa[0].sval_out = r.F2;
+    pa[1].sval_out = r.F3;
+    pa[2].sval_out = r.F4;
+    pa[2].mout = adj_dm(c);  // the moments of F^{n+1} are not needed
     hipError_t e = hipMemcpyAsync(Fs, Fn, imexlb_state_bytes(c), hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = launch_moments(d, f32, c->d_tab, Fn, Mn, cells, cells, dk, s);
+    if (e == hipSuccess) e = launch_moments(d, f32, c->d_tab, Fn, r.Mn, cells, cells, dk, s);
     if (e == hipSuccess) e = launch_stage(d, f32, kStage3, pa[0], s);
     if (e == hipSuccess) e = launch_stage(d, f32, kStage4, pa[1], s);
+    if (e == hipSuccess && r.F4) e = launch_stage(d, f32, kStage5, pa[2], s);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
-    return adjoint_core(c, Fn, G3, G4, Mn, M3, M4, lam1, lam0);
+    return adjoint_core(c, Fn, r, lam1, lam0);
 }
 
 imexlb_status imexlb_adjoint_step_recorded(imexlb_ctx* c, const void* Fn, const void* d_record,
@@ -985,8 +1011,7 @@ imexlb_status imexlb_adjoint_step_recorded(imexlb_ctx* c, const void* Fn, const 
         return fail(c, IMEXLB_EINVAL, "adjoint_step_recorded: record must be 256-byte aligned");
     if ((const void*)lam1 == (const void*)lam0)
         return fail(c, IMEXLB_EINVAL, "adjoint_step_recorded: lam1 and lam0 alias");
-    const StepRecord r = record_of(c, d_record);
-    return adjoint_core(c, Fn, r.G3, r.G4, r.Mn, r.M3, r.M4, lam1, lam0);
+    return adjoint_core(c, Fn, record_of(c, d_record), lam1, lam0);
 }
 
 imexlb_status imexlb_advect_adjoint(const imexlb_ctx* c, const double* F, const double* dA, double* dF) {
@@ -1017,7 +1042,7 @@ imexlb_status imexlb_moments_adjoint(imexlb_ctx* c, const void* F, const double*
         return fail(c, IMEXLB_EINVAL, "moments_adjoint: NULL buffer");
     const long long cells = c->cells;
     const size_t fb = (size_t)cells * sizeof(double);
-    double *M = adj_m(c, 0), *dM = adj_m(c, 3);
+    double *M = record_of(c, adj_rec(c)).Mn, *dM = adj_dm(c);  // scratch
     hipStream_t s = c->stream;
     hipError_t e = launch_moments(d, c->cfg.storage == IMEXLB_F32, c->d_tab, F, M, cells, cells,
                                   (double)(kDTotal + c->cfg.K), s);
@@ -1040,7 +1065,7 @@ imexlb_status imexlb_equilibrium_adjoint(imexlb_ctx* c, const double* n, const d
         return fail(c, IMEXLB_EINVAL, "equilibrium_adjoint: NULL buffer");
     const long long cells = c->cells;
     const size_t fb = (size_t)cells * sizeof(double);
-    double *M = adj_m(c, 0), *dM = adj_m(c, 3);
+    double *M = record_of(c, adj_rec(c)).Mn, *dM = adj_dm(c);  // scratch
     hipStream_t s = c->stream;
     const double* src[4] = {n, ux, d == 2 ? uy : T, T};
     hipError_t e = hipSuccess;

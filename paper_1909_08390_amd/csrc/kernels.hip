@@ -368,7 +368,7 @@ struct Stage2DShape {
     static constexpr int WPE = 2 * NT / 256;
 };
 
-template <typename S, int KIND, int QM, int TY, int OWN, bool PAIR, bool VEC>
+template <typename S, int KIND, int QM, int TY, int OWN, bool PAIR, bool VEC, bool REC>
 __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int tyi, S* tile, S* vfx,
                                              S* vfy, double* gtab) {
     using Sh = Stage2DShape<S, KIND, QM, TY, OWN, PAIR>;
@@ -666,6 +666,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                 ngm[i] = tgnm[i];
             }
         }
+        S rec[OWN];  // the stage values at the own cells, as swept
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             double e = 0.0;
@@ -674,6 +675,17 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
             if (sval[s]) {
                 const double val = RELAX ? fma(a.a_rel, g[s], a.b_rel * e) : g[s];
                 tl[lidx[s]] = (S)val;
+                if (s < OWN) rec[s] = (S)val;
+            }
+        }
+        if constexpr (REC && RELAX) {
+            const Rsrc rr = plane_rsrc(static_cast<S*>(a.sval_out) + plane_off(st.v), ps);
+            if constexpr (VEC) {
+                bstore_own<S, OWN>(rr, own_off, rec);
+            } else {
+#pragma unroll
+                for (int i = 0; i < OWN; ++i)
+                    if (row_real && ox0 + i < nx) bstore1<S, kStreamStore>(rr, own_off + i * (int)sizeof(S), rec[i]);
             }
         }
         // stage algebra with the host-combined coefficients k[] (see
@@ -893,7 +905,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
     }
 }
 
-template <typename S, int KIND, int QM, int TY, int OWN, bool PAIR>
+template <typename S, int KIND, int QM, int TY, int OWN, bool PAIR, bool REC>
 __global__ void __launch_bounds__(kTile2X * TY / OWN)
 __attribute__((amdgpu_waves_per_eu(Stage2DShape<S, KIND, QM, TY, OWN, PAIR>::WPE)))
 stage2d_kernel(StageArgs a) {
@@ -907,8 +919,8 @@ stage2d_kernel(StageArgs a) {
     // interior tiles of a grid whose rows are multiples of OWN take the
     // vector-access path; tiles at a ragged edge the element-wise one
     const bool vec = ((txi + 1) * Sh::TX <= a.nx) && ((tyi + 1) * TY <= a.ny) && (a.nx % OWN == 0);
-    if (vec) stage2d_body<S, KIND, QM, TY, OWN, PAIR, true>(a, txi, tyi, tile, vfx, vfy, gtab);
-    else stage2d_body<S, KIND, QM, TY, OWN, PAIR, false>(a, txi, tyi, tile, vfx, vfy, gtab);
+    if (vec) stage2d_body<S, KIND, QM, TY, OWN, PAIR, true, REC>(a, txi, tyi, tile, vfx, vfy, gtab);
+    else stage2d_body<S, KIND, QM, TY, OWN, PAIR, false, REC>(a, txi, tyi, tile, vfx, vfy, gtab);
 }
 
 // ---------------------------------------------------------------------------
@@ -1374,38 +1386,48 @@ __global__ void __launch_bounds__(256) moments_kernel(const DevTables* __restric
     }
 }
 
+// One launch of a 2D stage pass; REC: the pass also stores the stage values
+// at the own cells (sval_out).
+template <typename S, int KIND, bool REC>
+hipError_t launch_stage_2d(const StageArgs& a, int grid, hipStream_t s) {
+    constexpr int TY = kTile2Y, OWN = kOwn2;
+    constexpr int NT = kTile2X * TY / OWN;
+    // Even orders take the mirror-pair loop for every FP32 pass and for
+    // FP64 stage 3 (FP64 stage 5 is as fast in the software pipeline, and
+    // FP64 stage 4 has no registers left for a second plane)
+    constexpr bool CAN_PAIR =
+        ((sizeof(S) == 8 && KIND == kStage3) || sizeof(S) == 4) && KIND != kAdvect && OWN == 2;
+    if constexpr (CAN_PAIR) {
+        if (a.paired) {
+            if (a.qm == 16)
+                hipLaunchKernelGGL((stage2d_kernel<S, KIND, 16, TY, OWN, true, REC>), dim3(grid), dim3(NT), 0, s, a);
+            else
+                hipLaunchKernelGGL((stage2d_kernel<S, KIND, 8, TY, OWN, true, REC>), dim3(grid), dim3(NT), 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    if (a.qm == 16)
+        hipLaunchKernelGGL((stage2d_kernel<S, KIND, 16, TY, OWN, false, REC>), dim3(grid), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((stage2d_kernel<S, KIND, 8, TY, OWN, false, REC>), dim3(grid), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
 template <typename S, int KIND>
 hipError_t launch_stage_t(int d, const StageArgs& a, hipStream_t s) {
     const int ntiles = d == 2 ? a.ntx * a.nty : a.ntx;
     const int grid = 8 * ((ntiles + 7) / 8);
     if (d == 2) {
-        constexpr int TY = kTile2Y, OWN = kOwn2;
-        constexpr int NT = kTile2X * TY / OWN;
-        // Even orders take the mirror-pair loop for every FP32 pass and for
-        // FP64 stage 3 (FP64 stage 5 is as fast in the software pipeline,
-        // and FP64 stage 4 has no registers left for a second plane)
-        constexpr bool CAN_PAIR =
-            ((sizeof(S) == 8 && KIND == kStage3) || sizeof(S) == 4) && KIND != kAdvect && OWN == 2;
-        if constexpr (CAN_PAIR) {
-            if (a.paired) {
-                if (a.qm == 16)
-                    hipLaunchKernelGGL((stage2d_kernel<S, KIND, 16, TY, OWN, true>), dim3(grid), dim3(NT), 0, s, a);
-                else
-                    hipLaunchKernelGGL((stage2d_kernel<S, KIND, 8, TY, OWN, true>), dim3(grid), dim3(NT), 0, s, a);
-                return hipGetLastError();
-            }
+        if constexpr (KIND != kAdvect) {
+            if (a.sval_out) return launch_stage_2d<S, KIND, true>(a, grid, s);
         }
-        if (a.qm == 16)
-            hipLaunchKernelGGL((stage2d_kernel<S, KIND, 16, TY, OWN, false>), dim3(grid), dim3(NT), 0, s, a);
-        else
-            hipLaunchKernelGGL((stage2d_kernel<S, KIND, 8, TY, OWN, false>), dim3(grid), dim3(NT), 0, s, a);
-    } else {
-        constexpr int TX = kTile1X;
-        if (a.qm == 16)
-            hipLaunchKernelGGL((stage1d_kernel<S, KIND, 16, TX>), dim3(grid), dim3(TX / 4), 0, s, a);
-        else
-            hipLaunchKernelGGL((stage1d_kernel<S, KIND, 8, TX>), dim3(grid), dim3(TX / 4), 0, s, a);
+        return launch_stage_2d<S, KIND, false>(a, grid, s);
     }
+    constexpr int TX = kTile1X;
+    if (a.qm == 16)
+        hipLaunchKernelGGL((stage1d_kernel<S, KIND, 16, TX>), dim3(grid), dim3(TX / 4), 0, s, a);
+    else
+        hipLaunchKernelGGL((stage1d_kernel<S, KIND, 8, TX>), dim3(grid), dim3(TX / 4), 0, s, a);
     return hipGetLastError();
 }
 
