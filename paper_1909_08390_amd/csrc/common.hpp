@@ -99,10 +99,6 @@ struct StageArgs {
     void* out;             // output plane-set (G3, G4) or FP64 VF (advect)
     double* mout;          // output moments
     void* fbuf;            // state buffer: F^n / R / F^{n+1}
-    void* rbuf;            // stage 4: where R goes (fbuf, or the next state
-                           // buffer of an out-of-place step)
-    void* sval_out;        // 2D passes 3 / 4 / 5: where the stage values F2 / F3 /
-                           // F4 at the own cells go (recorded steps), or NULL
     const double* mn;      // moments of F^n (stage 4)
     const DevTables* tab;
     int nx, ny, bcx, bcy;
@@ -122,6 +118,13 @@ struct StageArgs {
     double k[6];
     double chi_fac;          // K + D - d
     double dk;               // D + K
+    // (last, so that the plain passes see the fields above at the offsets
+    // they were tuned with)
+    void* rbuf;              // stage 4: where R goes (fbuf, or the next state
+                             // buffer of an out-of-place step; read by the 1D
+                             // passes and the recording 2D passes)
+    void* sval_out;          // 2D passes 3 / 4 / 5: where the stage values F2 / F3 /
+                             // F4 at the own cells go (recorded steps), or NULL
 };
 
 // Host helpers shared by the single-grid and batched contexts (imexlb.cpp).

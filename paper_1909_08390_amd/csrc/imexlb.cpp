@@ -611,6 +611,9 @@ imexlb_status run_steps(imexlb_ctx* c, int nsteps, hipEvent_t* ev, const StepRec
     double* M3 = rec ? rec->M3 : work_m(c, 1);
     double* M4 = rec ? rec->M4 : work_m(c, 2);
     StageArgs pa[3];
+    // an out-of-place step is a recorded one: in 2D only the recording
+    // passes write R to a buffer other than the state they read
+    if (next && !rec) return fail(c, IMEXLB_EINVAL, "step: out of place without a record");
     pass_args(a, F, G3, G4, Mn, M3, M4, pa, next);
     if (rec) {
         pa[0].sval_out = rec->F2;

@@ -779,7 +779,9 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                     if (row_real && ox0 + i < nx) bstore1<S, kStreamStore>(ro, own_off + i * (int)sizeof(S), outv[i]);
             }
             if constexpr (KIND == kStage4) {
-                const Rsrc rf = plane_rsrc(static_cast<S*>(a.rbuf) + plane_off(st.v), ps);
+                // R over the state buffer, or (recorded steps, which may be
+                // out of place) into rbuf; the plain passes keep one pointer
+                const Rsrc rf = plane_rsrc(static_cast<S*>(REC ? a.rbuf : a.fbuf) + plane_off(st.v), ps);
                 if constexpr (VEC) {
                     bstore_own<S, OWN>(rf, own_off, fbv);
                 } else {
