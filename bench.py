@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 
 PMAX8 = 4.144547186125894  # largest root of He_8
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E spec peak
+XGMI_LINK_GBS = 153.0      # one MI355X xGMI link, spec figure (slab workload estimate only)
 METRIC = "velocity-node updates/s per IMEX step, FP32 vs FP64, % of HBM roofline"
 # Kernel sources whose hash ties a committed counter summary to the code it measured.
 KERNEL_SOURCES = ("paper_1909_08390_amd/csrc/kernels.hip", "paper_1909_08390_amd/csrc/common.hpp",
@@ -819,6 +820,59 @@ def run_sod(args):
     print(json.dumps(out), flush=True)
 
 
+def run_slab(args):
+    """One GPU's share of the 4096^2 workload split into y-slabs: the step on
+    a 4096 x (4096 / slabs) slab at the full problem's cell size and time step
+    (the slab through the quadrant corner, outflow rows standing in for the
+    neighbours' halos), FP64 and FP32 storage, and the halo bytes a sharded
+    step would exchange per pass.  No multi-GPU path exists in this library;
+    the exchange time is an estimate from the xGMI link rate, not measured."""
+    import torch
+
+    from paper_1909_08390_amd import imexlb as I
+    from paper_1909_08390_amd import workloads as W
+
+    N, parts = args.size, args.slabs
+    ny = N // parts
+    ly = ny / N
+    dt = 0.5 / N / PMAX8
+    states, k = W.quadrant_states(args.seed)
+    res = {}
+    for storage, name in ((I.F64, "f64"), (I.F32, "f32")):
+        cfg = I.Config(d=2, nx=N, ny=ny, lx=1.0, ly=ly, q_phi=8, q_chi=8, K=2, tau=1e-7, dt=dt,
+                       storage=storage)
+        s = I.Solver(cfg)
+        s.set_equilibrium(*W.riemann_2d(N, ny, states, x0=0.5, y0=0.5 * ly, lx=1.0, ly=ly))
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = s.step_timed(args.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        elem = 4 if storage == I.F32 else 8
+        res[name] = {"ms_per_step": 1e3 * wall / args.steps, "value": N * ny * cfg.planes * args.steps / wall,
+                     "unit": "VN/s",
+                     "pass_ms": {kk: ms[i] / args.steps for i, kk in enumerate(("stage3", "stage4", "stage5"))},
+                     # per pass and side: 5 ghost rows of the pass's stencil input and of its moments
+                     "halo_bytes_per_pass_per_side": 5 * N * (cfg.planes * elem + 4 * 8)}
+        res[name]["halo_ms_per_step_one_link_estimate"] = (
+            3 * 2 * res[name]["halo_bytes_per_pass_per_side"] / (XGMI_LINK_GBS * 1e9) * 1e3)
+        del s
+        torch.cuda.empty_cache()
+    out = {
+        "metric": METRIC, "value": res["f64"]["value"], "unit": "VN/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["f64"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"one of {parts} y-slabs of the {N}x{N} four-quadrant problem: {N}x{ny} cells, "
+                               "8x8 velocities per f and g, tau=1e-7, the full problem's dt, outflow",
+                   "cells": N * ny, "planes": 128, "seed": args.seed + k},
+        "slab": res,
+        "xgmi_link_gbs_assumed": XGMI_LINK_GBS,
+        "note": "single-GPU share only; the halo exchange is not implemented, its time is bytes / one link's rate",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -844,7 +898,8 @@ def main():
                     help="print the instruction-mix summary of a --pmc run of INST_COUNTERS and exit")
     ap.add_argument("--cmd", action="append", default=[],
                     help="command line recorded in a summary")
-    ap.add_argument("--workload", choices=["riemann2d", "batch", "adjoint", "sod"], default="riemann2d",
+    ap.add_argument("--slabs", type=int, default=8, help="slab workload: y-slabs of the grid")
+    ap.add_argument("--workload", choices=["riemann2d", "batch", "adjoint", "sod", "slab"], default="riemann2d",
                     help="riemann2d: the 4096^2 2D step (default); batch: 256 1D tubes; "
                          "adjoint: gradient through a 512^2 rollout; sod: the paper's 400-cell tube")
     ap.add_argument("--adj-size", type=int, default=512)
@@ -893,6 +948,9 @@ def main():
         return
     if args.workload == "sod":
         run_sod(args)
+        return
+    if args.workload == "slab":
+        run_slab(args)
         return
     horizon = args.horizon if args.horizon > args.warmup + args.steps else 0
     log(f"bench: {args.size}^2 cells x 128 planes, FP64, {args.warmup} warmup + {args.steps} steps"
