@@ -240,8 +240,9 @@ imexlb_status imexlb_step_recorded(imexlb_ctx* ctx, void* d_record);
  * aligned, distinct from the bound state, the workspace and the record; the
  * buffer bound before the call stays the caller's and keeps F^n.
  * Asynchronous unless check_physical is set.  Errors: as
- * imexlb_step_recorded; EINVAL for a NULL or misaligned d_next or one equal
- * to the bound state (nothing is launched and the binding is unchanged). */
+ * imexlb_step_recorded; EINVAL for a NULL or misaligned d_next or one that
+ * overlaps the bound state, the workspace or the record (nothing is launched
+ * and the binding is unchanged). */
 imexlb_status imexlb_step_recorded_to(imexlb_ctx* ctx, void* d_record, void* d_next);
 
 /* imexlb_adjoint_step for the step that imexlb_step_recorded took from

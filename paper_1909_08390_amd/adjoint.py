@@ -76,12 +76,7 @@ class EquilibriumRollout(torch.autograd.Function):
         g = [x if x is not None else _zeros_like_field(s) for x in (gn, gux, guy, gT)]
         lam = s.moments_adjoint(ctx.final_state, *g)
         main = torch.cuda.current_stream(s.device)
-        # one side stream per solver, kept: the caching allocator keeps each
-        # stream's freed blocks for that stream, so a new stream per call
-        # would strand the previous calls' segment buffers
-        side = getattr(s, "_side_stream", None)
-        if side is None:
-            side = s._side_stream = torch.cuda.Stream(device=s.device)  # default priority
+        side = s.side_stream()
         every, nsteps = ctx.every, ctx.nsteps
 
         def recompute(seg):

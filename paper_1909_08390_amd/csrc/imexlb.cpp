@@ -701,7 +701,16 @@ imexlb_status imexlb_step_recorded_to(imexlb_ctx* c, void* d_record, void* d_nex
     if (!c) return IMEXLB_EINVAL;
     if (!d_next) return fail(c, IMEXLB_EINVAL, "step_recorded_to: NULL next state");
     if ((uintptr_t)d_next & 255) return fail(c, IMEXLB_EINVAL, "step_recorded_to: next state must be 256-byte aligned");
-    if (d_next == c->d_state) return fail(c, IMEXLB_EINVAL, "step_recorded_to: next state is the bound state");
+    if (need_state(c) != IMEXLB_OK) return fail(c, IMEXLB_ESTATE, "step_recorded_to: no bound state");
+    // the next buffer must not overlap the bound state, the workspace or the record
+    auto overlaps = [](const void* a, size_t na, const void* b, size_t nb) {
+        const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+        return x < y + nb && y < x + na;
+    };
+    const size_t sb = imexlb_state_bytes(c);
+    if (overlaps(d_next, sb, c->d_state, sb) || overlaps(d_next, sb, c->d_work, imexlb_workspace_bytes(c)) ||
+        overlaps(d_next, sb, d_record, record_bytes(c)))
+        return fail(c, IMEXLB_EINVAL, "step_recorded_to: next state overlaps the bound state, the workspace or the record");
     return step_recorded(c, d_record, d_next, "step_recorded_to");
 }
 

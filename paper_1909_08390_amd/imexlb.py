@@ -339,6 +339,14 @@ class Solver:
     def step(self, nsteps: int = 1):
         self._check(self.L.imexlb_step(self._h, int(nsteps)), "step")
 
+    def side_stream(self):
+        """A second stream of default priority, created on first use and kept
+        for the solver's life (the caching allocator keeps each stream's freed
+        blocks for that stream, so one kept stream reuses them)."""
+        if getattr(self, "_side", None) is None:
+            self._side = self.torch.cuda.Stream(device=self.device)
+        return self._side
+
     def set_stream(self, stream):
         """Run the following calls on ``stream`` (a torch.cuda.Stream of
         default priority); ``imexlb_set_stream``."""

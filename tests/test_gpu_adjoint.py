@@ -156,8 +156,9 @@ def test_recorded_step_and_adjoint_match_the_recomputing_ones(case, kind):
 def test_out_of_place_recorded_step_matches_in_place(case, kind):
     """step_recorded_to writes the same F^{n+1} and record as the in-place
     recorded step, leaves the buffer it read holding F^n, and binds the new
-    buffer as the state (two steps in a row); a next buffer equal to the
-    bound state is rejected without launching anything.  FP64 and FP32."""
+    buffer as the state (two steps in a row); a next buffer that is the bound
+    state or overlaps the record or the workspace is rejected without
+    launching anything.  FP64 and FP32."""
     torch = _torch()
     for storage in (I.F64, I.F32):
         c = I.Config(storage=storage, **case)
@@ -180,7 +181,10 @@ def test_out_of_place_recorded_step_matches_in_place(case, kind):
         assert s.state is o2
         assert torch.equal(src, F) and torch.equal(o1, plain1) and torch.equal(o2, plain2)
         assert torch.equal(r1, rec1) and torch.equal(r2, rec2)
-        assert s.L.imexlb_step_recorded_to(s._h, I._vp(r1.data_ptr()), I._vp(o2.data_ptr())) == I.EINVAL
+        L, h = s.L, s._h
+        assert L.imexlb_step_recorded_to(h, I._vp(r1.data_ptr()), I._vp(o2.data_ptr())) == I.EINVAL
+        assert L.imexlb_step_recorded_to(h, I._vp(r1.data_ptr()), I._vp(r1.data_ptr())) == I.EINVAL
+        assert L.imexlb_step_recorded_to(h, I._vp(r1.data_ptr()), I._vp(s.workspace.data_ptr())) == I.EINVAL
         assert s.state is o2 and torch.equal(o2, plain2)
 
 
