@@ -98,15 +98,18 @@ class EquilibriumRollout(torch.autograd.Function):
             return states, records, ev
 
         nseg = len(ctx.checkpoints) + (1 if ctx.tail is not None else 0)
-        pending = (*ctx.tail, None) if ctx.tail is not None else (recompute(nseg - 1) if nseg else None)
-        for seg in reversed(range(nseg)):
-            states, records, ev = pending
-            if ev is not None:
-                main.wait_event(ev)
-            if seg > 0:
-                pending = recompute(seg - 1)
-            for F, rec in zip(reversed(states), reversed(records)):
-                lam = s.adjoint_step(F, lam, record=rec)
+        try:
+            pending = (*ctx.tail, None) if ctx.tail is not None else (recompute(nseg - 1) if nseg else None)
+            for seg in reversed(range(nseg)):
+                states, records, ev = pending
+                if ev is not None:
+                    main.wait_event(ev)
+                if seg > 0:
+                    pending = recompute(seg - 1)
+                for F, rec in zip(reversed(states), reversed(records)):
+                    lam = s.adjoint_step(F, lam, record=rec)
+        finally:
+            s.set_stream(main)  # also when a call above raised
         s.state.record_stream(main)
         dn, dux, duy, dT = s.equilibrium_adjoint(n0, ux0, uy0, T0, lam)
         return dn, dux, duy, dT, None, None, None
