@@ -359,13 +359,16 @@ struct Stage2DShape {
     // software-pipelined plane loop (double-buffered LDS tile and flux
     // buffers) for FP64 pass 5 and for FP32 passes 3 and 5 without the
     // mirror-pair loop (odd orders); stage 4, whose registers are already
-    // full with the E^n factors of its own cells, keeps the two-barrier loop
-    // when it does not pair
+    // full with the E^n factors of its own cells, and FP64 stage 3 (three
+    // waves per SIMD, below) keep the two-barrier loop when they do not pair
     static constexpr bool PIPE = KIND != kStage4 && (sizeof(S) == 4 || KIND == kStage5) && !PAIR;
     static constexpr int NBUF = (PIPE || PAIR) ? 2 : 1;
     // waves per SIMD the register budget aims at: two work-groups per
-    // compute unit
-    static constexpr int WPE = 2 * NT / 256;
+    // compute unit; three for FP64 stage 3 with x-factor tables in the
+    // single-buffer loop (49 KB of LDS; the moments of the loaded cells, read
+    // only when a factor group starts, spill to scratch and are reloaded
+    // there)
+    static constexpr int WPE = (sizeof(S) == 8 && KIND == kStage3 && QM == 8 && !PAIR) ? 3 : 2 * NT / 256;
 };
 
 template <typename S, int KIND, int QM, int TY, int OWN, bool PAIR, bool VEC, bool REC>
@@ -1394,11 +1397,11 @@ template <typename S, int KIND, bool REC>
 hipError_t launch_stage_2d(const StageArgs& a, int grid, hipStream_t s) {
     constexpr int TY = kTile2Y, OWN = kOwn2;
     constexpr int NT = kTile2X * TY / OWN;
-    // Even orders take the mirror-pair loop for every FP32 pass and for
-    // FP64 stage 3 (FP64 stage 5 is as fast in the software pipeline, and
-    // FP64 stage 4 has no registers left for a second plane)
-    constexpr bool CAN_PAIR =
-        ((sizeof(S) == 8 && KIND == kStage3) || sizeof(S) == 4) && KIND != kAdvect && OWN == 2;
+    // Even orders take the mirror-pair loop for every FP32 pass (FP64 stage
+    // 3 runs the single-buffer loop at three waves per SIMD, FP64 stage 5 is
+    // as fast in the software pipeline, and FP64 stage 4 has no registers
+    // left for a second plane)
+    constexpr bool CAN_PAIR = sizeof(S) == 4 && KIND != kAdvect && OWN == 2;
     if constexpr (CAN_PAIR) {
         if (a.paired) {
             if (a.qm == 16)
