@@ -245,11 +245,14 @@ imexlb_status imexlb_step_recorded(imexlb_ctx* ctx, void* d_record);
  * and the binding is unchanged). */
 imexlb_status imexlb_step_recorded_to(imexlb_ctx* ctx, void* d_record, void* d_next);
 
-/* imexlb_adjoint_step for the step that imexlb_step_recorded took from
- * d_Fn, reading the step's stage sources and moments from its record
- * instead of recomputing them (the forward passes 3 and 4).  Same result as
- * imexlb_adjoint_step.  Errors: as imexlb_adjoint_step; EINVAL for a NULL
- * or misaligned record. */
+/* imexlb_adjoint_step for the step that imexlb_step_recorded (or
+ * imexlb_step_recorded_to) took from d_Fn, reading the step's stage sources,
+ * moments and, in 2D, stage values from its record instead of recomputing
+ * the step.  Bit for bit the result of imexlb_adjoint_step when the
+ * recorded step started from the moments imexlb_set_state takes of d_Fn;
+ * after a step the moments come from that step's last pass and agree with
+ * those to rounding.  Errors: as imexlb_adjoint_step; EINVAL for a NULL or
+ * misaligned record. */
 imexlb_status imexlb_adjoint_step_recorded(imexlb_ctx* ctx, const void* d_Fn, const void* d_record,
                                            const double* d_lam_np1, double* d_lam_n);
 
