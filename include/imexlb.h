@@ -226,7 +226,7 @@ imexlb_status imexlb_adjoint_step(imexlb_ctx* ctx, const void* d_Fn, const doubl
 size_t imexlb_step_record_bytes(const imexlb_ctx* ctx);
 
 /* One IMEX step, as imexlb_step(ctx, 1), that also leaves the step's stage
- * sources and moments in d_record (device, 256-byte aligned,
+ * sources, moments and (2D) stage values in d_record (device, 256-byte aligned,
  * imexlb_step_record_bytes; caller-owned).  Asynchronous unless
  * check_physical is set.  Errors: as imexlb_step; EINVAL for a NULL or
  * misaligned record. */
