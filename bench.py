@@ -791,6 +791,33 @@ def run_sod(args):
                                 nx * cfg.planes * (3 * 8 + 2 * 3 * 8 / cfg.planes)))}
     per = {k: ms[i] / nsteps for i, k in enumerate(("stage3", "stage4", "stage5"))}
     gbs4 = pb["stage4"] / (per["stage4"] * 1e-3) / 1e9
+    # the same run without per-pass events, and as a batch of one tube under
+    # the tuner's plan (persistent launches cover up to 8 steps each): the
+    # step is launch-latency bound, so fewer launches is the lever
+    s.set_equilibrium(n, u, None, T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(nsteps)
+    torch.cuda.synchronize()
+    wall_plain = time.perf_counter() - t0
+    ref = s.state.clone()
+    b = I.Batch([I.TubeSpec(nx=nx, K=2, tau=1e-5, dt=2.5e-4)], q_phi=5, q_chi=3, storage=I.F64)
+    b.set_equilibrium(n, u, T)
+    tuned = b.tune(8)
+    b.set_equilibrium(n, u, T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(nsteps)
+    torch.cuda.synchronize()
+    wall_batch = time.perf_counter() - t0
+    plan = b.plan()
+    one_tube = {"us_per_step": 1e6 * wall_batch / nsteps, "value": vn / wall_batch, "unit": "VN/s",
+                "plan": {"mode": "persistent launches" if plan.mode == 1 else "per-pass launches",
+                         "tile": plan.tile, "steps_per_launch": plan.steps, "bins": plan.bins},
+                "tuner_best_us_per_step": {
+                    "per_pass_launches": 1e3 * min(v for k, v in tuned.items() if k.mode == 0),
+                    "persistent": 1e3 * min(v for k, v in tuned.items() if k.mode == 1)},
+                "state_bitwise_equal_to_single_grid": bool(torch.equal(b.tube_state(0), ref))}
     cpu = None
     if not args.no_cpu:
         import oracle as O
@@ -809,7 +836,9 @@ def run_sod(args):
         "config": {"workload": "Sod shock tube, 400 cells on [0,1], 5+3 velocities, K=2 (gamma 7/5), "
                                "tau=1e-5, dt=2.5e-4, 400 steps to t=0.1, outflow",
                    "cells": nx, "planes": cfg.planes},
-        "us_per_step": 1e3 * wall / nsteps,
+        "us_per_step": 1e6 * wall / nsteps,
+        "us_per_step_without_pass_events": 1e6 * wall_plain / nsteps,
+        "one_tube_batch": one_tube,
         "pass_ms": per,
         "roofline": {"bound": "hbm", "kernel": "stage4 (stage1d_kernel<double, 4>)", "achieved": gbs4,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs4 / HBM_PEAK_GBS, "traffic": None,
