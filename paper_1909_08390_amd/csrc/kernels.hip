@@ -356,6 +356,9 @@ struct Stage2DShape {
     // x-factor table nodes: the table groups of the plane order built by the
     // host
     static constexpr int TABN = kTabNodes2D;
+    // stage 4 with tables also keeps the x factors of E^n at its own cells in
+    // LDS (one table group, each thread its own entries)
+    static constexpr bool NTAB = TAB && KIND == kStage4;
     // software-pipelined plane loop (double-buffered LDS tile and flux
     // buffers) for FP64 pass 5 and for FP32 passes 3 and 5 without the
     // mirror-pair loop (odd orders); stage 4, whose registers are already
@@ -373,7 +376,7 @@ struct Stage2DShape {
 
 template <typename S, int KIND, int QM, int TY, int OWN, bool PAIR, bool VEC, bool REC>
 __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int tyi, S* tile, S* vfx,
-                                             S* vfy, double* gtab) {
+                                             S* vfy, double* gtab, double* gntab) {
     using Sh = Stage2DShape<S, KIND, QM, TY, OWN, PAIR>;
     constexpr int TX = Sh::TX, NT = Sh::NT, L = Sh::L, OPR = Sh::OPR, P = Sh::P, VP = Sh::VP;
     constexpr int NH = Sh::NH, HS = Sh::HS, NS = Sh::NS;
@@ -561,6 +564,15 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                                 gtab[(2 * p + 1) * NLOAD + cid[s]] = gq;
                             }
                         }
+                        if constexpr (Sh::NTAB) {
+#pragma unroll
+                            for (int i = 0; i < OWN; ++i) {
+                                double gp, gq;
+                                g_pair_r<QM>(cf, nux[i], nth[i], gp, gq);
+                                gntab[(2 * p) * (TX * TY) + cid[i]] = gp;
+                                gntab[(2 * p + 1) * (TX * TY) + cid[i]] = gq;
+                            }
+                        }
                     }
                 }
             }
@@ -644,7 +656,7 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
                 for (int i = 0; i < OWN; ++i) {
                     tgn[i] = 0.0;
                     tgnm[i] = 0.0;
-                    if constexpr (KIND == kStage4) g_pair_r<QM>(cf, nux[i], nth[i], tgn[i], tgnm[i]);
+                    if constexpr (KIND == kStage4 && !Sh::NTAB) g_pair_r<QM>(cf, nux[i], nth[i], tgn[i], tgnm[i]);
                 }
             } else {
 #pragma unroll
@@ -665,7 +677,8 @@ __device__ __forceinline__ void stage2d_body(const StageArgs& a, int txi, int ty
             }
 #pragma unroll
             for (int i = 0; i < OWN; ++i) {
-                gxn[i] = tgn[i];
+                if constexpr (Sh::NTAB) gxn[i] = gntab[st.slot() * (TX * TY) + cid[i]];
+                else gxn[i] = tgn[i];
                 ngm[i] = tgnm[i];
             }
         }
@@ -919,13 +932,14 @@ stage2d_kernel(StageArgs a) {
     __shared__ S vfx[Sh::NBUF * TY * Sh::VP];
     __shared__ S vfy[Sh::NBUF * TY * Sh::VP];
     __shared__ double gtab[Sh::TAB ? Sh::TABN * Sh::NLOAD : 1];
+    __shared__ double gntab[Sh::NTAB ? Sh::TABN * kTile2X * TY : 1];
     int txi, tyi;
     if (!tile_of_block(a, txi, tyi)) return;
     // interior tiles of a grid whose rows are multiples of OWN take the
     // vector-access path; tiles at a ragged edge the element-wise one
     const bool vec = ((txi + 1) * Sh::TX <= a.nx) && ((tyi + 1) * TY <= a.ny) && (a.nx % OWN == 0);
-    if (vec) stage2d_body<S, KIND, QM, TY, OWN, PAIR, true, REC>(a, txi, tyi, tile, vfx, vfy, gtab);
-    else stage2d_body<S, KIND, QM, TY, OWN, PAIR, false, REC>(a, txi, tyi, tile, vfx, vfy, gtab);
+    if (vec) stage2d_body<S, KIND, QM, TY, OWN, PAIR, true, REC>(a, txi, tyi, tile, vfx, vfy, gtab, gntab);
+    else stage2d_body<S, KIND, QM, TY, OWN, PAIR, false, REC>(a, txi, tyi, tile, vfx, vfy, gtab, gntab);
 }
 
 // ---------------------------------------------------------------------------
