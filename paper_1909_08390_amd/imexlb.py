@@ -249,6 +249,10 @@ def validate(cfg: Config) -> int:
 class Solver:
     """One context bound to caller-owned torch device buffers."""
 
+    # Bytes the autograd rollout (adjoint.EquilibriumRollout) may hold in
+    # recorded segments; None: 80 % of the device memory free at the time.
+    rollout_memory = None
+
     def __init__(self, cfg: Config, device="cuda:0"):
         import torch
 

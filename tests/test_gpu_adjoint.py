@@ -188,15 +188,19 @@ def test_out_of_place_recorded_step_matches_in_place(case, kind):
         assert s.state is o2 and torch.equal(o2, plain2)
 
 
-@pytest.mark.parametrize("nsteps,every", [(8, 3), (5, 5), (4, 1), (0, 3)])
-def test_rollout_gradient_matches_single_stream_reverse_sweep(nsteps, every):
-    """The autograd rollout (last segment recorded in the forward, earlier
-    segments recomputed out of place on a second stream while the adjoint
-    runs through the next one) gives bit for bit the gradients of the same
+@pytest.mark.parametrize("nsteps,every,memory", [(8, 3, None), (5, 5, None), (4, 1, None), (0, 3, None),
+                                                 (8, 3, 1), (7, 2, "one")])
+def test_rollout_gradient_matches_single_stream_reverse_sweep(nsteps, every, memory):
+    """The autograd rollout gives bit for bit the gradients of the same
     schedule run on one stream with in-place recorded steps and copies of
     the states; and to rounding those of a plain reverse sweep with the
     recomputing adjoint step (whose M^n comes from the moment kernel rather
-    than from the previous step's pass 5)."""
+    than from the previous step's pass 5).  With the default memory budget
+    the last segment is recorded in the forward and earlier segments are
+    recomputed out of place on a second stream while the adjoint runs through
+    the next one; with a budget of 1 byte every segment, the last one too, is
+    recomputed on the caller's stream; with room for one segment ("one") the
+    last segment is recorded but nothing is recomputed ahead."""
     torch = _torch()
     from paper_1909_08390_amd import adjoint as A
 
@@ -208,6 +212,8 @@ def test_rollout_gradient_matches_single_stream_reverse_sweep(nsteps, every):
     rng = np.random.Generator(np.random.PCG64(9))
     g = [torch.as_tensor(rng.normal(size=c.field_shape), device="cuda") for _ in range(4)]
     s = I.Solver(c)
+    one_seg = min(every, nsteps) * (s.L.imexlb_step_record_bytes(s._h) + s.L.imexlb_state_bytes(s._h))
+    s.rollout_memory = {None: None, 1: 1, "one": one_seg}[memory]
     ins = [x.clone().requires_grad_(True) for x in (n, ux, uy, T)]
     outs = A.rollout(s, *ins, nsteps, every)
     torch.autograd.backward(outs, grad_tensors=g)
@@ -225,6 +231,8 @@ def test_rollout_gradient_matches_single_stream_reverse_sweep(nsteps, every):
     r.set_equilibrium(n, ux, uy, T)
     nseg = (nsteps + every - 1) // every
     tail0 = (nseg - 1) * every if nseg else 0
+    if memory == 1:
+        tail0 = nsteps  # no recorded segment fits: the last one is recomputed too
     ck = []
     for k in range(tail0):
         if k % every == 0:
