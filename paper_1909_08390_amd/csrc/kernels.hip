@@ -332,12 +332,15 @@ __device__ __forceinline__ bool tile_of_block(const StageArgs& a, int& tx, int& 
 //    starts; above order 8 from one Horner evaluation per loaded cell for a
 //    node and its mirror;
 //  - three plane loops (Stage2DShape): the mirror-pair loop (even orders:
-//    every FP32 pass and FP64 pass 3; both planes of an x-mirror pair per
-//    iteration), the software pipeline (FP64 pass 5, and FP32 passes 3 and
-//    5 of odd orders: sweep plane j and relax plane j + 1 into the other of
-//    two LDS tiles, the loads of plane j + 2 in flight, one barrier,
-//    pointwise step of plane j) and the plain loop (FP64 pass 4, FP32 pass
-//    4 of odd orders: relax, barrier, sweeps, barrier, pointwise).
+//    every FP32 pass; both planes of an x-mirror pair per iteration), the
+//    software pipeline (FP64 pass 5, and FP32 passes 3 and 5 of odd orders:
+//    sweep plane j and relax plane j + 1 into the other of two LDS tiles,
+//    the loads of plane j + 2 in flight, one barrier, pointwise step of
+//    plane j) and the plain loop (FP64 passes 3 and 4, FP32 pass 4 of odd
+//    orders: relax, barrier, sweeps, barrier, pointwise; FP64 pass 3 at
+//    three waves per SIMD);
+//  - stage 4 keeps the x factors of E^n at its own cells in a second LDS
+//    table, built with the x-factor tables.
 // LDS pitches are odd so the row-strided x windows and the column-strided
 // results spread over all banks.
 // ---------------------------------------------------------------------------
